@@ -1,0 +1,187 @@
+/*
+ * apfc.h -- C ABI of the MI355X (gfx950) solver for one time step of the amplitude
+ * expansion of the phase-field crystal model (APFC), after Praetorius, Salvalaglio and
+ * Voigt, "An efficient numerical framework for the amplitude expansion of the
+ * phase-field crystal model".
+ *
+ * What is solved.  Complex amplitudes eta_j (j = 1..J) of the reciprocal lattice vectors
+ * k_j evolve by the L2 gradient flow of the amplitude energy (Eq. (2)-(4)),
+ *     d eta_j / dt = -kappa_j ( G_j^2 eta_j + dF^s/d eta_j^* ),  G_j = Lap + 2 i k_j.grad,
+ * kappa_j = a0 |k_j|^2, with the bulk energy of Eq. (5) (triangular lattice: Eq. (6)-(7)).
+ * Space: Q1 finite elements on a periodic uniform quad (2D) or hex (3D) mesh; the fourth
+ * order operator is split with zeta_j = G_j eta_j (Eq. (8)-(9)).  Time: backward Euler with
+ * the simplified Newton / amplitude-splitting iteration of Algorithm 1, i.e. per amplitude the
+ * block system of Eq. (10)/(11)
+ *     [ M          -G_j              ] [zeta_j]   [ 0                                  ]
+ *     [ kappa_j G_j  M/dt + kappa_j w D ] [eta_j ] = [ M eta_j^{m-1}/dt - kappa_j w h_j    ]
+ * with D = diag(dF), h_j = F^s_j - dF eta_j evaluated node by node (nodal quadrature weight
+ * w = h^dim).  Each system is solved by restarted flexible GMRES, right-preconditioned with
+ * the block preconditioner of Eq. (12) applied in its four steps (one mass solve, two
+ * diffusion solves with L = M/sqrt(dt) + sqrt(kappa_j) K, a G and an M product).
+ *
+ * Memory and streams.  The library allocates no device memory.  Every device buffer
+ * (amplitudes, workspace) is owned by the caller; pass a stream as a hipStream_t cast to
+ * void* (NULL = the null stream).  A context is used from one host thread at a time.
+ *
+ * Layouts.  Node index i = ix + nx*(iy + ny*iz) (x fastest), node (ix,iy,iz) at
+ * (ix*h, iy*h, iz*h), h = length[0]/n[0] (uniform: all directions share h).  A field of one
+ * instance is stored planar as [J][2][N] doubles: amplitude j, then real part (0) or
+ * imaginary part (1), then node.
+ *
+ * Errors.  Every entry point returns APFC_OK (0) on success, APFC_ERR_NOT_CONVERGED (1) when
+ * FGMRES reached max_iters, or a negative APFC_ERR_*.  apfc_step and apfc_step_adjoint are
+ * transactional: on any return other than APFC_OK the caller's output buffers are unchanged.
+ * apfc_last_error() gives a message for the last failure on the calling thread.
+ */
+#ifndef APFC_H
+#define APFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    APFC_OK = 0,
+    APFC_ERR_NOT_CONVERGED = 1,   /* soft: FGMRES did not reach rtol within max_iters   */
+    APFC_ERR_INVALID = -1,        /* bad argument (mesh, lattice, params, pointer)       */
+    APFC_ERR_HIP = -2,            /* a HIP runtime call failed                           */
+    APFC_ERR_WORKSPACE = -3,      /* workspace missing or smaller than apfc_workspace_bytes */
+    APFC_ERR_NONFINITE = -4       /* a residual norm became NaN or Inf                   */
+};
+
+enum { APFC_TRI2D = 0, APFC_BCC3D = 1, APFC_CUSTOM = 2 };
+enum { APFC_FP64 = 0, APFC_MIXED = 1 };          /* preconditioner + Z basis precision */
+enum { APFC_INNER_PCG = 0, APFC_INNER_CHEB = 1 }; /* inner solver of the preconditioner  */
+
+/* Periodic uniform Q1 mesh: dim in {2,3}; n[d] nodes (= elements) per direction, n[d] >= 4;
+ * length[d] = n[d] * h for one common h (checked to 1e-12 relative).  n[2], length[2] are
+ * ignored in 2D. */
+typedef struct {
+    int dim;
+    int64_t n[3];
+    double length[3];
+} apfc_mesh;
+
+/* Reciprocal lattice vectors.  apfc_lattice_default fills k for APFC_TRI2D (Eq. (7), J = 3)
+ * and APFC_BCC3D (six unit <110>/sqrt(2) vectors, J = 6).  APFC_CUSTOM takes J <= 8 vectors
+ * as given; apfc_create rejects sets whose resonant products are not all pair terms or terms
+ * with distinct amplitude indices. */
+typedef struct {
+    int kind;
+    int J;
+    double k[8][3];
+} apfc_lattice;
+
+typedef struct {
+    double a0, a1, a2, a3;   /* energy parameters of Eq. (5); Elder: a0 = B^x, a1 = dB/2,
+                                a2 = 3 nu / 4, a3 = tau (the cubic coefficient)          */
+    int picard_iters;        /* K of Algorithm 1 (>= 1; the adjoint needs K = 1)         */
+    double rtol;             /* stop when ||b - A x||_2 <= rtol ||b||_2 over (zeta, eta)  */
+    int restart;             /* FGMRES restart length m, 1..32                           */
+    int max_iters;           /* FGMRES iterations per solve before APFC_ERR_NOT_CONVERGED */
+    int precision;           /* APFC_FP64 or APFC_MIXED                                 */
+    int mass_iters;          /* inner iterations of the mass solve (paper: 3)            */
+    int diff_iters;          /* inner iterations of each diffusion solve (paper: 5)      */
+    int inner_kind;          /* APFC_INNER_PCG (paper) or APFC_INNER_CHEB                */
+} apfc_params;
+
+/* Device pointers of one instance, each [J][2][N] float64, owned by the caller. */
+typedef struct {
+    double* eta;
+    double* zeta;
+} apfc_state;
+
+typedef struct {
+    int total_iters;      /* FGMRES iterations summed over all systems (instance, amplitude) */
+    int max_iters;        /* largest per-system iteration count                              */
+    int cycles;           /* restart cycles of the slowest system                            */
+    double max_relres;    /* largest final true relative residual ||b-Ax||/||b||             */
+    double ms;            /* host wall time of the call in milliseconds                      */
+    int* iters;           /* optional host array [count*J]: iterations per system, or NULL   */
+} apfc_stats;
+
+typedef struct apfc_ctx apfc_ctx;
+
+/* Fill params with the paper's values (a0..a3 of Sec. II, 3 and 5 inner PCG iterations of
+ * Sec. III) and solver defaults (K = 1, rtol 1e-8, restart 30, max_iters 500, FP64). */
+void apfc_params_default(apfc_params* params);
+
+/* Fill lattice for kind APFC_TRI2D or APFC_BCC3D. Returns APFC_ERR_INVALID for other kinds. */
+int apfc_lattice_default(int kind, apfc_lattice* lattice);
+
+/* Relaxed amplitude phi of the uniform crystal eta_j = phi (positive root of d f^s / d phi = 0
+ * for the bulk energy of Eq. (5) on this lattice; 0 if only the liquid exists). Host only. */
+int apfc_uniform_amplitude(const apfc_lattice* lattice, const apfc_params* params, double* phi);
+
+/* One instance.  Validates mesh, lattice and params and builds the host-side tables; no
+ * device work happens before apfc_set_workspace. */
+int apfc_create(const apfc_mesh* mesh, const apfc_lattice* lattice, const apfc_params* params,
+                apfc_ctx** out);
+
+/* count independent instances of possibly different mesh sizes and energy parameters
+ * (meshes[count], params[count]; solver fields taken from params[0] and required equal),
+ * all solved together by the same batched launches. */
+int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* lattice,
+                      const apfc_params* params, apfc_ctx** out);
+
+/* Bytes of device workspace the context needs (256-byte aligned start required). */
+size_t apfc_workspace_bytes(const apfc_ctx* ctx);
+
+/* Attach caller-owned device memory of at least apfc_workspace_bytes bytes. The memory must
+ * stay valid until the context is destroyed or another workspace is attached. */
+int apfc_set_workspace(apfc_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* zeta_j = M^{-1} G_j eta_j for every instance (the initial auxiliary field of Algorithm 1),
+ * computed by a fixed 60-iteration Jacobi-PCG mass solve. states[count]. */
+int apfc_init_zeta(apfc_ctx* ctx, apfc_state* states, void* stream);
+
+/* One time step of Algorithm 1 for every instance: eta, zeta <- eta^m, zeta^m.  source is
+ * NULL or a device array per instance ([count] pointers to [J][2][N]) of a manufactured
+ * source s added to d eta/dt (enters the RHS as M s).  stats may be NULL. */
+int apfc_step(apfc_ctx* ctx, apfc_state* states, double dt, const double* const* source,
+              void* stream, apfc_stats* stats);
+
+/* Energy E = sum_i w f^s(eta_i) + sum_j zeta_j^H M zeta_j with zeta_j = M^{-1} G_j eta_j
+ * (Eq. (2) without the 1/2, nodal quadrature of f^s), per instance into host_out[count].
+ * The state's zeta is not read: zeta is recomputed by a 60-iteration PCG mass solve. */
+int apfc_energy(apfc_ctx* ctx, const apfc_state* states, double* host_out, void* stream);
+
+/* Gradient of apfc_energy with respect to eta in PyTorch's convention
+ * (dE/dRe eta + i dE/dIm eta = 2 dE/d eta^*), written to grad[count] device arrays
+ * [J][2][N]; dE/d(Delta B) at fixed eta is added to host ddB[count] if ddB != NULL. */
+int apfc_energy_grad(apfc_ctx* ctx, const apfc_state* states, double* const* grad,
+                     double* ddB, void* stream);
+
+/* Adjoint of one K = 1 step taken with the same dt from before[].eta to after[].eta: given
+ * lam_after = dL/d eta^m (PyTorch convention, device [J][2][N] per instance), write
+ * lam_before = dL/d eta^{m-1} and add dL/d(Delta B) of this step to host dL_ddB[count].
+ * Solves A_j^H mu = [0; lam_j] as Sigma A_j^{-1} Sigma^{-1} with Sigma = diag(-kappa_j, 1),
+ * reusing the forward FGMRES and preconditioner.  zeta carries no gradient. */
+int apfc_step_adjoint(apfc_ctx* ctx, const apfc_state* before, const apfc_state* after, double dt,
+                      const double* const* lam_after, double* const* lam_before, double* dL_ddB,
+                      void* stream, apfc_stats* stats);
+
+/* Kernel timing probe: when enabled, every launch of the kernel named `name` inside
+ * apfc_step is bracketed by HIP events on the launch stream; apfc_probe_read returns the
+ * number of launches and their summed duration since the last reset. */
+int apfc_probe_enable(apfc_ctx* ctx, const char* name);
+int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* bytes_per_launch);
+
+/* Tile-height autotuner: times the stencil kernels for each candidate tile on the attached
+ * workspace and keeps the fastest.  Optional; the default tile is used otherwise. */
+int apfc_autotune(apfc_ctx* ctx, void* stream, int* chosen_tile_rows);
+
+/* Use hipGraph replays for the FGMRES iterations (1, default) or direct launches (0). */
+int apfc_set_graphs(apfc_ctx* ctx, int enable);
+
+int apfc_destroy(apfc_ctx* ctx);
+const char* apfc_status_string(int status);
+const char* apfc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APFC_H */

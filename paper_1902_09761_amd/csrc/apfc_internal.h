@@ -1,0 +1,158 @@
+// Internal declarations of the APFC HIP library: device data descriptors, the nodal bulk
+// term table and the kernel launchers.  Not part of the public C ABI (include/apfc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace apfc {
+
+constexpr int kTX = 64;          // tile width in x = one wave64
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kChunk = 2048;     // elements of a full vector per Krylov workgroup (8 per thread)
+constexpr int kMaxJ = 8;
+constexpr int kMaxTerms = 24;
+constexpr int kMaxRestart = 32;
+
+// Complex value stored as two reals (re, im), 2*sizeof(R)-aligned for vector loads.
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+    R x, y;
+};
+using zd = cx<double>;
+using zf = cx<float>;
+
+// One linear system = (instance, amplitude).  Systems are ordered instance-major (s = inst*J + j).
+struct Sys {
+    int inst, j, dim, nx, ny, nz;
+    int tbeg, tend;        // stencil tiles of this system [tbeg, tend)
+    int cbeg, cend;        // Krylov chunks of this system [cbeg, cend)
+    long long N;           // nodes
+    long long off;         // node offset of this system inside a batched half vector
+    long long doff;        // node offset of the instance inside per-instance node arrays
+    double h, w, kappa, kv[3];
+    double a0, a1, a2, a3;
+    // time-step dependent scalars (refreshed when dt changes)
+    double inv_dt, isq_dt, sq_kap, isq_kap;
+    double diagM, diagK, diagL;
+};
+
+struct Tile { int sys, x0, y0, z; };
+struct Chunk { int sys; int e0; };     // element offset inside the system's 2N-element full vector
+
+// Resonant products of the bulk energy with distinct amplitude indices: term value
+// c (T + T^*), T = prod_q u_q, u_q = eta_{idx[q]} or its conjugate (cj[q] = 1); c = -2 a3/a0
+// for cubic terms (order 3) and 8 a2/a0 for quartic ones (order 4).
+struct Terms {
+    int J;
+    int n;
+    int order[kMaxTerms];
+    int idx[kMaxTerms][4];
+    int cj[kMaxTerms][4];
+};
+
+// Reduction slots in the per-tile partial array (stride kSlots).
+enum Slot { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kBB = 4, kE0 = 5, kE1 = 6, kSlots = 8 };
+
+// Kernel identifiers for the timing probe.
+enum KernelId {
+    KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
+    KID_RESIDUAL, KID_MDOT, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_COUNT
+};
+const char* kernel_name(int kid);
+int kernel_id(const char* name);
+
+struct Probe {
+    int target = KID_NONE;
+    int n = 0;
+    double bytes = 0.0;       // algorithmic HBM bytes of the recorded launches
+    static constexpr int kMax = 8192;
+    hipEvent_t ev[2 * kMax];
+    bool created = false;
+};
+
+// Everything a launcher needs about the batch (device pointers + host copies of sizes).
+struct Dev {
+    const Sys* sys = nullptr;        // device [S]
+    const Tile* tiles = nullptr;     // device [ntiles]
+    const Chunk* chunks = nullptr;   // device [nchunks]
+    int ntiles = 0, nchunks = 0, S = 0, TY = 16, J = 0, count = 0, dim = 2;
+    long long NT = 0;                // half-vector length (complex values)
+    Terms terms{};
+    Probe* probe = nullptr;
+};
+
+// Krylov bookkeeping on the device (all [S]-indexed, see api.hip).
+struct Krylov {
+    double* H;          // [S][m][m+1] complex, column k holds rows 0..k after the rotations
+    double* cs;         // [S][m]
+    double* sn;         // [S][m] complex
+    double* g;          // [S][m+1] complex
+    double* y;          // [S][m] complex
+    double* hsum;       // [S][m+1] complex, h1 + h2 of the current column
+    double* hinv;       // [S] 1/||w''||
+    double* red1;       // [S][nv1] reduced first projection
+    double* red2;       // [S][nv1+1] reduced second projection and ||w'||^2
+    double* redr;       // [S][2] reduced |r|^2, |b|^2
+    double* bnorm;      // [S]
+    double* target;     // [S]
+    double* inv_beta;   // [S]
+    double* relres;     // [S]
+    int* solve_active;  // [S]
+    int* iter_active;   // [S]
+    int* kcount;        // [S]
+    int* iters;         // [S]
+    int* cycles;        // [S]
+    int* err;           // [1]
+    int m;
+    int nv1;            // 2*(m+1)
+    double rtol;
+};
+
+// ------------------------------------------------------------------------------------------
+// Launchers (kernels.hip).  `mask` points to per-system int flags (nullptr = all systems).
+// ------------------------------------------------------------------------------------------
+void launch_state_in(const Dev& d, double* const* eta_tab, double* const* zeta_tab, zd* X, hipStream_t st);
+void launch_state_out(const Dev& d, const zd* X, double* const* eta_tab, double* const* zeta_tab, hipStream_t st);
+void launch_planar_in(const Dev& d, double* const* tab, zd* half, hipStream_t st);
+void launch_planar_out(const Dev& d, const zd* half, double* const* tab, hipStream_t st);
+void launch_fill_zero(zd* p, long long n, hipStream_t st);
+
+void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st);
+void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st);
+
+void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, zd* R, double* part,
+                     const int* mask, hipStream_t st);
+template <typename T>
+void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st);
+
+template <typename T>
+void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
+                    cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+
+void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
+                   const int* mask, hipStream_t st);
+void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
+                 bool project, double* part, const int* mask, hipStream_t st);
+void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
+                       const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st);
+void launch_scale(const Dev& d, const zd* r, const double* inv_beta, zd* v0, const int* mask, hipStream_t st);
+template <typename T>
+void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
+                    zd* X, const int* mask, hipStream_t st);
+
+void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st);
+void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st);
+void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
+
+void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,
+                       int iters, hipStream_t st);
+void launch_energy_parts(const Dev& d, const zd* eta, const zd* zeta, double* part, hipStream_t st);
+void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* const* grad_tab, double* part,
+                        hipStream_t st);
+void launch_adjoint_rhs(const Dev& d, double* const* lam_tab, zd* B, hipStream_t st);
+void launch_adjoint_out(const Dev& d, const zd* Y, const zd* eta_prev, double* const* eta_new_tab,
+                        double* const* lam_out_tab, double* part, hipStream_t st);
+
+}  // namespace apfc

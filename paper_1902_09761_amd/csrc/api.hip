@@ -1,0 +1,942 @@
+// Host side of the APFC library: argument checking, batch tables, workspace carving, the
+// restarted FGMRES driver of the per-amplitude block systems (Algorithm 1, Eq. (10)-(12)),
+// energy, gradient and adjoint entry points, the timing probe, the tile autotuner and hipGraph
+// capture of FGMRES iterations.  Every device buffer belongs to the caller.
+#include "apfc.h"
+#include "apfc_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace apfc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return fail(APFC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------------------------------------------
+// Resonant products of the bulk energy (Eq. (1), (5)): the part of <n^p> (p = 3, 4) that survives
+// the average over the lattice scale.  With distinct amplitude indices the ordered products of a
+// set occur p! times; pair terms |eta_i|^2 |eta_l|^2 give A^2 - 2 sum |eta|^4 of Eq. (5).
+// ----------------------------------------------------------------------------------------------
+bool zero_vec(const double* v) { return std::fabs(v[0]) < 1e-9 && std::fabs(v[1]) < 1e-9 && std::fabs(v[2]) < 1e-9; }
+
+int build_terms(const apfc_lattice& L, Terms& T) {
+    std::memset(&T, 0, sizeof(T));
+    T.J = L.J;
+    const int J = L.J;
+    // distinct-index resonances, first factor unconjugated (its conjugate is the "+ c.c." part)
+    for (int order = 3; order <= 4; ++order) {
+        int idx[4];
+        for (idx[0] = 0; idx[0] < J; ++idx[0])
+            for (idx[1] = idx[0] + 1; idx[1] < J; ++idx[1])
+                for (idx[2] = idx[1] + 1; idx[2] < J; ++idx[2])
+                    for (int i3 = (order == 4 ? idx[2] + 1 : 0); i3 < (order == 4 ? J : 1); ++i3) {
+                        idx[3] = i3;
+                        for (int signs = 0; signs < (1 << (order - 1)); ++signs) {
+                            double v[3] = {0, 0, 0};
+                            int cj[4] = {0, 0, 0, 0};
+                            for (int q = 0; q < order; ++q) {
+                                cj[q] = q == 0 ? 0 : (signs >> (q - 1)) & 1;
+                                for (int c = 0; c < 3; ++c) v[c] += (cj[q] ? -1.0 : 1.0) * L.k[idx[q]][c];
+                            }
+                            if (!zero_vec(v)) continue;
+                            if (T.n >= kMaxTerms) return fail(APFC_ERR_INVALID, "lattice: too many resonant terms");
+                            T.order[T.n] = order;
+                            for (int q = 0; q < order; ++q) {
+                                T.idx[T.n][q] = idx[q];
+                                T.cj[T.n][q] = cj[q];
+                            }
+                            T.n++;
+                        }
+                    }
+    }
+    // every other zero-sum product must be a pair term (k_i - k_i + k_l - k_l)
+    for (int i = 0; i < J; ++i)
+        for (int l = i + 1; l < J; ++l)
+            for (int si = -1; si <= 1; si += 2) {
+                double v[3];
+                for (int c = 0; c < 3; ++c) v[c] = L.k[i][c] + si * L.k[l][c];
+                if (zero_vec(v)) return fail(APFC_ERR_INVALID, "lattice: k_l = +-k_i for l != i");
+            }
+    for (int i = 0; i < J; ++i)
+        for (int l = 0; l < J; ++l)
+            for (int si = -1; si <= 1; si += 2) {
+                // 2 k_i +- k_l = 0 (cubic with a repeated index)
+                double v[3];
+                for (int c = 0; c < 3; ++c) v[c] = 2.0 * L.k[i][c] + si * L.k[l][c];
+                if (zero_vec(v)) return fail(APFC_ERR_INVALID, "lattice: resonance 2 k_i = -+ k_l not supported");
+                for (int m = 0; m < J; ++m)
+                    for (int sm = -1; sm <= 1; sm += 2) {
+                        // 2 k_i + si k_l + sm k_m = 0 (quartic with a repeated index, not a pair term);
+                        // l = i or m = i with a minus sign leaves k_i -+ k_other, zero only for |eta_i|^4
+                        if ((l == i && si == -1) || (m == i && sm == -1)) continue;
+                        for (int c = 0; c < 3; ++c) v[c] = 2.0 * L.k[i][c] + si * L.k[l][c] + sm * L.k[m][c];
+                        if (zero_vec(v)) return fail(APFC_ERR_INVALID, "lattice: resonance 2 k_i + k_l + k_m = 0 not supported");
+                    }
+            }
+    return APFC_OK;
+}
+
+// f^s(phi) = c2 phi^2 + c3 phi^3 + c4 phi^4 for the uniform crystal eta_j = phi.
+void uniform_poly(const Terms& T, const apfc_params& p, double& c2, double& c3, double& c4) {
+    const int J = T.J;
+    c2 = 2.0 * J * p.a1 / p.a0;                                  // (a1/a0) A, A = 2 J phi^2
+    c4 = p.a2 / p.a0 * (4.0 * J * J - 2.0 * J);                  // (a2/a0)(A^2 - 2 sum |eta|^4)
+    c3 = 0.0;
+    for (int t = 0; t < T.n; ++t) {
+        if (T.order[t] == 3) c3 += 2.0 * (-2.0 * p.a3 / p.a0);
+        else c4 += 2.0 * (8.0 * p.a2 / p.a0);
+    }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------------------
+// context
+// ----------------------------------------------------------------------------------------------
+struct apfc_ctx {
+    int count = 0, J = 0, dim = 2, S = 0;
+    apfc_lattice lattice{};
+    std::vector<apfc_mesh> meshes;
+    std::vector<apfc_params> params;
+    apfc_params solver{};
+    Terms terms{};
+    std::vector<Sys> sys;
+    std::vector<Tile> tiles;
+    std::vector<Chunk> chunks;
+    long long NT = 0, NI = 0;
+    int TY = 16;
+    int max_tiles = 0;
+    double dt = -1.0;
+    bool mixed = false;
+
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Sys* d_sys = nullptr;
+    Tile* d_tiles = nullptr;
+    Chunk* d_chunks = nullptr;
+    double** d_tab = nullptr;          // 4 tables of [count] pointers
+    zd *X = nullptr, *B = nullptr, *R = nullptr, *W = nullptr, *BB = nullptr;
+    zd* V = nullptr;
+    void* Z = nullptr;
+    void* pc[6] = {};
+    double* dnode = nullptr;
+    double* tpart = nullptr;
+    double* cpart = nullptr;
+    Krylov kr{};
+    int m = 30;
+
+    // host staging (pinned)
+    double** h_tab = nullptr;
+    int* h_flags = nullptr;
+    double* h_dbl = nullptr;
+
+    Probe probe;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraphExec_t> graphs;
+    bool graphs_valid = false;
+
+    Dev dev() {
+        Dev d;
+        d.sys = d_sys;
+        d.tiles = d_tiles;
+        d.chunks = d_chunks;
+        d.ntiles = (int)tiles.size();
+        d.nchunks = (int)chunks.size();
+        d.S = S;
+        d.TY = TY;
+        d.J = J;
+        d.count = count;
+        d.dim = dim;
+        d.NT = NT;
+        d.terms = terms;
+        d.probe = probe.target != KID_NONE ? &probe : nullptr;
+        return d;
+    }
+    size_t zsize() const { return mixed ? sizeof(zf) : sizeof(zd); }
+    long long vstride() const { return 2 * NT; }   // complex values per full vector
+};
+
+namespace {
+
+void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
+    tiles.clear();
+    for (int s = 0; s < c.S; ++s) {
+        Sys& y = c.sys[s];
+        y.tbeg = (int)tiles.size();
+        for (int z = 0; z < y.nz; ++z)
+            for (int y0 = 0; y0 < y.ny; y0 += TY)
+                for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, z});
+        y.tend = (int)tiles.size();
+    }
+}
+
+void set_dt_scalars(apfc_ctx& c, double dt) {
+    for (auto& y : c.sys) {
+        y.inv_dt = 1.0 / dt;
+        y.isq_dt = 1.0 / std::sqrt(dt);
+        y.sq_kap = std::sqrt(y.kappa);
+        y.isq_kap = 1.0 / std::sqrt(y.kappa);
+        y.diagL = y.diagM * y.isq_dt + y.sq_kap * y.diagK;
+    }
+    c.dt = dt;
+}
+
+int upload_tables(apfc_ctx& c) {
+    HIPCHK(hipMemcpy(c.d_sys, c.sys.data(), sizeof(Sys) * c.S, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.d_tiles, c.tiles.data(), sizeof(Tile) * c.tiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.d_chunks, c.chunks.data(), sizeof(Chunk) * c.chunks.size(), hipMemcpyHostToDevice));
+    return APFC_OK;
+}
+
+void invalidate_graphs(apfc_ctx& c) {
+    for (auto g : c.graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    c.graphs.clear();
+    c.graphs_valid = false;
+}
+
+// carve the workspace; returns bytes needed (base may be null to only measure)
+size_t carve(apfc_ctx& c, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~size_t(255);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const long long NT = c.NT;
+    const int S = c.S, m = c.m;
+    const size_t zs = c.zsize();
+    c.d_sys = (Sys*)take(sizeof(Sys) * S);
+    c.d_tiles = (Tile*)take(sizeof(Tile) * c.max_tiles);
+    c.d_chunks = (Chunk*)take(sizeof(Chunk) * c.chunks.size());
+    c.d_tab = (double**)take(sizeof(double*) * 4 * c.count);
+    c.X = (zd*)take(sizeof(zd) * 2 * NT);
+    c.B = (zd*)take(sizeof(zd) * 2 * NT);
+    c.R = (zd*)take(sizeof(zd) * 2 * NT);
+    c.W = (zd*)take(sizeof(zd) * 2 * NT);
+    c.BB = (zd*)take(sizeof(zd) * NT);
+    c.V = (zd*)take(sizeof(zd) * 2 * NT * (m + 1));
+    c.Z = take(zs * 2 * NT * m);
+    for (int i = 0; i < 6; ++i) c.pc[i] = take(zs * NT);
+    c.dnode = (double*)take(sizeof(double) * c.NI);
+    c.tpart = (double*)take(sizeof(double) * kSlots * c.max_tiles);
+    c.cpart = (double*)take(sizeof(double) * (2 * kMaxRestart + 2) * c.chunks.size());
+    Krylov& k = c.kr;
+    k.m = m;
+    k.nv1 = 2 * (m + 1);
+    k.rtol = c.solver.rtol;
+    k.H = (double*)take(sizeof(double) * S * m * 2 * (m + 1));
+    k.cs = (double*)take(sizeof(double) * S * m);
+    k.sn = (double*)take(sizeof(double) * S * 2 * m);
+    k.g = (double*)take(sizeof(double) * S * 2 * (m + 1));
+    k.y = (double*)take(sizeof(double) * S * 2 * m);
+    k.hsum = (double*)take(sizeof(double) * S * 2 * (m + 1));
+    k.hinv = (double*)take(sizeof(double) * S);
+    k.red1 = (double*)take(sizeof(double) * S * k.nv1);
+    k.red2 = (double*)take(sizeof(double) * S * (k.nv1 + 1));
+    k.redr = (double*)take(sizeof(double) * S * kSlots);
+    k.bnorm = (double*)take(sizeof(double) * S);
+    k.target = (double*)take(sizeof(double) * S);
+    k.inv_beta = (double*)take(sizeof(double) * S);
+    k.relres = (double*)take(sizeof(double) * S);
+    k.solve_active = (int*)take(sizeof(int) * S);
+    k.iter_active = (int*)take(sizeof(int) * S);
+    k.kcount = (int*)take(sizeof(int) * S);
+    k.iters = (int*)take(sizeof(int) * S);
+    k.cycles = (int*)take(sizeof(int) * S);
+    k.err = (int*)take(sizeof(int) * 4);
+    return off + 256;
+}
+
+__global__ void k_reset_counters(Krylov kr, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) {
+        kr.iters[s] = 0;
+        kr.cycles[s] = 0;
+        kr.kcount[s] = 0;
+        kr.solve_active[s] = 1;
+        kr.iter_active[s] = 0;
+        if (s == 0) kr.err[0] = 0;
+    }
+}
+
+int check_mesh(const apfc_mesh& m) {
+    if (m.dim != 2 && m.dim != 3) return fail(APFC_ERR_INVALID, "mesh.dim must be 2 or 3");
+    const double h = m.length[0] / (double)m.n[0];
+    for (int d = 0; d < m.dim; ++d) {
+        if (m.n[d] < 4 || m.n[d] > (1 << 20)) return fail(APFC_ERR_INVALID, "mesh.n[d] must be in [4, 2^20]");
+        if (!(m.length[d] > 0.0) || !std::isfinite(m.length[d])) return fail(APFC_ERR_INVALID, "mesh.length must be positive");
+        const double hd = m.length[d] / (double)m.n[d];
+        if (std::fabs(hd - h) > 1e-12 * h) return fail(APFC_ERR_INVALID, "mesh: all directions must share one h");
+    }
+    return APFC_OK;
+}
+
+int check_params(const apfc_params& p) {
+    if (!(p.a0 > 0.0) || !std::isfinite(p.a1) || !(p.a2 >= 0.0) || !std::isfinite(p.a2) || !std::isfinite(p.a3))
+        return fail(APFC_ERR_INVALID, "params: need a0 > 0, a2 >= 0, finite a1, a3");
+    if (p.picard_iters < 1 || p.picard_iters > 100) return fail(APFC_ERR_INVALID, "params.picard_iters must be in [1,100]");
+    if (!(p.rtol > 0.0) || p.rtol >= 1.0) return fail(APFC_ERR_INVALID, "params.rtol must be in (0,1)");
+    if (p.restart < 1 || p.restart > kMaxRestart) return fail(APFC_ERR_INVALID, "params.restart must be in [1,32]");
+    if (p.max_iters < 1) return fail(APFC_ERR_INVALID, "params.max_iters must be >= 1");
+    if (p.precision != APFC_FP64 && p.precision != APFC_MIXED) return fail(APFC_ERR_INVALID, "params.precision");
+    if (p.mass_iters < 1 || p.mass_iters > 64 || p.diff_iters < 1 || p.diff_iters > 64)
+        return fail(APFC_ERR_INVALID, "params: inner iterations must be in [1,64]");
+    if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB)
+        return fail(APFC_ERR_INVALID, "params.inner_kind");
+    return APFC_OK;
+}
+
+int check_lattice(const apfc_lattice& L, int dim) {
+    if (L.J < 1 || L.J > kMaxJ) return fail(APFC_ERR_INVALID, "lattice.J must be in [1,8]");
+    for (int j = 0; j < L.J; ++j) {
+        double n2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(L.k[j][c])) return fail(APFC_ERR_INVALID, "lattice.k not finite");
+            n2 += L.k[j][c] * L.k[j][c];
+        }
+        if (!(n2 > 0.0)) return fail(APFC_ERR_INVALID, "lattice.k must be nonzero");
+        if (dim == 2 && L.k[j][2] != 0.0) return fail(APFC_ERR_INVALID, "lattice: k_z must be 0 in 2D");
+    }
+    return APFC_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------------------
+// public API
+// ----------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* apfc_last_error(void) { return g_err.c_str(); }
+
+const char* apfc_status_string(int status) {
+    switch (status) {
+        case APFC_OK: return "ok";
+        case APFC_ERR_NOT_CONVERGED: return "FGMRES did not converge within max_iters";
+        case APFC_ERR_INVALID: return "invalid argument";
+        case APFC_ERR_HIP: return "HIP runtime error";
+        case APFC_ERR_WORKSPACE: return "workspace missing or too small";
+        case APFC_ERR_NONFINITE: return "non-finite residual";
+        default: return "unknown status";
+    }
+}
+
+void apfc_params_default(apfc_params* p) {
+    if (!p) return;
+    p->a0 = 0.98;
+    p->a1 = 0.01;
+    p->a2 = 0.25;
+    p->a3 = 0.5;
+    p->picard_iters = 1;
+    p->rtol = 1e-8;
+    p->restart = 30;
+    p->max_iters = 500;
+    p->precision = APFC_FP64;
+    p->mass_iters = 3;
+    p->diff_iters = 5;
+    p->inner_kind = APFC_INNER_PCG;
+}
+
+int apfc_lattice_default(int kind, apfc_lattice* L) {
+    if (!L) return fail(APFC_ERR_INVALID, "lattice is NULL");
+    std::memset(L, 0, sizeof(*L));
+    L->kind = kind;
+    if (kind == APFC_TRI2D) {
+        // Eq. (7)
+        const double s = std::sqrt(3.0) / 2.0;
+        L->J = 3;
+        L->k[0][0] = -s; L->k[0][1] = -0.5;
+        L->k[1][0] = 0.0; L->k[1][1] = 1.0;
+        L->k[2][0] = s; L->k[2][1] = -0.5;
+        return APFC_OK;
+    }
+    if (kind == APFC_BCC3D) {
+        const double r = 1.0 / std::sqrt(2.0);
+        const double v[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+        L->J = 6;
+        for (int j = 0; j < 6; ++j)
+            for (int c = 0; c < 3; ++c) L->k[j][c] = r * v[j][c];
+        return APFC_OK;
+    }
+    return fail(APFC_ERR_INVALID, "apfc_lattice_default: kind must be APFC_TRI2D or APFC_BCC3D");
+}
+
+int apfc_uniform_amplitude(const apfc_lattice* L, const apfc_params* p, double* phi) {
+    if (!L || !p || !phi) return fail(APFC_ERR_INVALID, "NULL argument");
+    if (int rc = check_lattice(*L, 3); rc) return rc;
+    Terms T;
+    if (int rc = build_terms(*L, T); rc) return rc;
+    double c2, c3, c4;
+    uniform_poly(T, *p, c2, c3, c4);
+    // d f / d phi = phi (2 c2 + 3 c3 phi + 4 c4 phi^2) = 0
+    const double disc = 9.0 * c3 * c3 - 32.0 * c2 * c4;
+    *phi = (disc < 0.0 || !(c4 > 0.0)) ? 0.0 : (-3.0 * c3 + std::sqrt(disc)) / (8.0 * c4);
+    if (*phi < 0.0) *phi = 0.0;
+    return APFC_OK;
+}
+
+int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* lattice, const apfc_params* params,
+                      apfc_ctx** out) {
+    if (!out) return fail(APFC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 4096 || !meshes || !lattice || !params)
+        return fail(APFC_ERR_INVALID, "apfc_create_batch: need 1 <= count <= 4096 and non-NULL arrays");
+    const int dim = meshes[0].dim;
+    for (int b = 0; b < count; ++b) {
+        if (int rc = check_mesh(meshes[b]); rc) return rc;
+        if (meshes[b].dim != dim) return fail(APFC_ERR_INVALID, "all instances must have the same dim");
+        if (int rc = check_params(params[b]); rc) return rc;
+        const apfc_params& a = params[0];
+        const apfc_params& p = params[b];
+        if (p.picard_iters != a.picard_iters || p.rtol != a.rtol || p.restart != a.restart ||
+            p.max_iters != a.max_iters || p.precision != a.precision || p.mass_iters != a.mass_iters ||
+            p.diff_iters != a.diff_iters || p.inner_kind != a.inner_kind)
+            return fail(APFC_ERR_INVALID, "solver fields of params[] must be equal across instances");
+    }
+    if (int rc = check_lattice(*lattice, dim); rc) return rc;
+    auto c = new apfc_ctx();
+    c->count = count;
+    c->J = lattice->J;
+    c->dim = dim;
+    c->lattice = *lattice;
+    c->meshes.assign(meshes, meshes + count);
+    c->params.assign(params, params + count);
+    c->solver = params[0];
+    c->m = params[0].restart;
+    c->mixed = params[0].precision == APFC_MIXED;
+    if (int rc = build_terms(*lattice, c->terms); rc) {
+        delete c;
+        return rc;
+    }
+    if (params[0].inner_kind == APFC_INNER_CHEB) {
+        delete c;
+        return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB is not available in this build");
+    }
+    c->S = count * c->J;
+    long long off = 0, doff = 0;
+    for (int b = 0; b < count; ++b) {
+        const apfc_mesh& m = meshes[b];
+        const long long nx = m.n[0], ny = m.n[1], nz = dim == 3 ? m.n[2] : 1;
+        const long long N = nx * ny * nz;
+        const double h = m.length[0] / (double)nx;
+        for (int j = 0; j < c->J; ++j) {
+            Sys y{};
+            y.inst = b;
+            y.j = j;
+            y.dim = dim;
+            y.nx = (int)nx;
+            y.ny = (int)ny;
+            y.nz = (int)nz;
+            y.N = N;
+            y.off = off;
+            y.doff = doff;
+            y.h = h;
+            y.w = std::pow(h, dim);
+            double k2 = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                y.kv[q] = lattice->k[j][q];
+                k2 += y.kv[q] * y.kv[q];
+            }
+            y.kappa = params[b].a0 * k2;      // kappa_j = a0 |k_j|^2 (below Eq. (3))
+            y.a0 = params[b].a0;
+            y.a1 = params[b].a1;
+            y.a2 = params[b].a2;
+            y.a3 = params[b].a3;
+            // Jacobi diagonals: M_ii = (2h/3)^dim, K_ii = dim (2/h) (2h/3)^(dim-1)
+            y.diagM = std::pow(2.0 * h / 3.0, dim);
+            y.diagK = dim * (2.0 / h) * std::pow(2.0 * h / 3.0, dim - 1);
+            c->sys.push_back(y);
+            off += N;
+        }
+        doff += N;
+    }
+    c->NT = off;
+    c->NI = doff;
+    for (int s = 0; s < c->S; ++s) {
+        Sys& y = c->sys[s];
+        y.cbeg = (int)c->chunks.size();
+        for (long long e0 = 0; e0 < 2 * y.N; e0 += kChunk) c->chunks.push_back(Chunk{s, (int)e0});
+        y.cend = (int)c->chunks.size();
+    }
+    std::vector<Tile> t4;
+    build_tiles(*c, 4, t4);
+    c->max_tiles = (int)t4.size();
+    c->TY = 16;
+    build_tiles(*c, c->TY, c->tiles);
+    set_dt_scalars(*c, 1.0);
+    *out = c;
+    return APFC_OK;
+}
+
+int apfc_create(const apfc_mesh* mesh, const apfc_lattice* lattice, const apfc_params* params, apfc_ctx** out) {
+    return apfc_create_batch(1, mesh, lattice, params, out);
+}
+
+size_t apfc_workspace_bytes(const apfc_ctx* c) {
+    if (!c) return 0;
+    apfc_ctx tmp_view = *c;   // carve on a copy: only sizes are computed
+    tmp_view.h_tab = nullptr;
+    tmp_view.h_flags = nullptr;
+    tmp_view.h_dbl = nullptr;
+    tmp_view.graphs.clear();
+    size_t n = carve(tmp_view, nullptr);
+    return n;
+}
+
+int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
+    if (!c || !ptr) return fail(APFC_ERR_INVALID, "NULL argument");
+    if (((uintptr_t)ptr & 255) != 0) return fail(APFC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < apfc_workspace_bytes(c)) return fail(APFC_ERR_WORKSPACE, "workspace smaller than apfc_workspace_bytes");
+    invalidate_graphs(*c);
+    if (!c->h_tab) {
+        // pinned host staging for pointer tables and flag / scalar read-back
+        if (hipHostMalloc((void**)&c->h_tab, sizeof(double*) * 4 * c->count) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_flags, sizeof(int) * (4 * c->S + 8)) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_dbl, sizeof(double) * (kSlots * c->S + 8)) != hipSuccess)
+            return fail(APFC_ERR_HIP, "hipHostMalloc of host staging buffers failed");
+    }
+    c->ws = (char*)ptr;
+    c->ws_bytes = bytes;
+    carve(*c, c->ws);
+    return upload_tables(*c);
+}
+
+int apfc_destroy(apfc_ctx* c) {
+    if (!c) return APFC_OK;
+    invalidate_graphs(*c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->probe.created)
+        for (auto& e : c->probe.ev) (void)hipEventDestroy(e);
+    if (c->h_tab) (void)hipHostFree(c->h_tab);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    if (c->h_dbl) (void)hipHostFree(c->h_dbl);
+    delete c;
+    return APFC_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------------------------
+// the solver
+// ----------------------------------------------------------------------------------------------
+namespace {
+
+int need_ws(apfc_ctx* c) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    if (!c->ws) return fail(APFC_ERR_WORKSPACE, "no workspace attached (apfc_set_workspace)");
+    return APFC_OK;
+}
+
+int refresh_dt(apfc_ctx* c, double dt, hipStream_t st) {
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(APFC_ERR_INVALID, "dt must be positive and finite");
+    if (dt != c->dt) {
+        set_dt_scalars(*c, dt);
+        HIPCHK(hipMemcpyAsync(c->d_sys, c->sys.data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return APFC_OK;
+}
+
+// upload up to 4 tables of per-instance device pointers
+int upload_ptrs(apfc_ctx* c, const std::vector<const void*>* tabs, int ntabs, hipStream_t st) {
+    for (int t = 0; t < ntabs; ++t)
+        for (int b = 0; b < c->count; ++b) c->h_tab[t * c->count + b] = (double*)tabs[t][b];
+    HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(double*) * ntabs * c->count, hipMemcpyHostToDevice, st));
+    return APFC_OK;
+}
+double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
+
+template <typename T>
+void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
+    const Krylov& kr = c->kr;
+    const long long vs = c->vstride();
+    cx<T>* Z = (cx<T>*)c->Z;
+    cx<T>** pc = (cx<T>**)c->pc;
+    const int* act = kr.iter_active;
+    launch_precond<T>(d, c->V + k * vs, Z + k * vs, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                      c->solver.mass_iters, c->solver.diff_iters, act, st);
+    launch_apply<T>(d, Z + k * vs, c->dnode, c->W, act, st);
+    const int nv = k + 1;
+    launch_mdot(d, c->V, vs, nv, c->W, nullptr, kr.nv1, false, c->cpart, act, st);
+    launch_reduce(d, c->cpart, 0, 2 * nv, true, kr.red1, kr.nv1, act, st);
+    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1, true, c->cpart, act, st);
+    launch_reduce(d, c->cpart, 0, 2 * nv + 1, true, kr.red2, kr.nv1 + 1, act, st);
+    launch_arnoldi(d, kr, k, st);
+    launch_proj_final(d, c->V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), c->V + (k + 1) * vs, act, st);
+}
+
+void run_iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
+    if (c->mixed)
+        iteration<float>(c, d, k, st);
+    else
+        iteration<double>(c, d, k, st);
+}
+
+int capture_graphs(apfc_ctx* c) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    invalidate_graphs(*c);
+    Dev d = c->dev();
+    d.probe = nullptr;
+    c->graphs.assign(c->m, nullptr);
+    for (int k = 0; k < c->m; ++k) {
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        run_iteration(c, d, k, c->cap_stream);
+        HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+        hipGraphExec_t ge;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(APFC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        c->graphs[k] = ge;
+    }
+    c->graphs_valid = true;
+    return APFC_OK;
+}
+
+// Restarted FGMRES on every system: B and the initial guess X must be set, dnode current.
+int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
+    Dev d = c->dev();
+    Krylov& kr = c->kr;
+    const long long vs = c->vstride();
+    const bool graphs = c->use_graphs && d.probe == nullptr;
+    if (graphs && !c->graphs_valid)
+        if (int rc = capture_graphs(c); rc) return rc;
+    hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, kr, c->S);
+    launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
+    launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, nullptr, st);
+    launch_cycle_init(d, kr, true, st);
+    launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    int launched = 0;
+    const int S = c->S;
+    for (int cyc = 0;; ++cyc) {
+        for (int k = 0; k < c->m; ++k) {
+            if (graphs)
+                HIPCHK(hipGraphLaunch(c->graphs[k], st));
+            else
+                run_iteration(c, d, k, st);
+            ++launched;
+            // poll the per-system flags; cheap relative to one iteration of these sizes
+            HIPCHK(hipMemcpyAsync(c->h_flags, kr.iter_active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool any = false;
+            for (int s = 0; s < S; ++s) any |= c->h_flags[s] != 0;
+            if (!any) break;
+        }
+        launch_solve_y(d, kr, st);
+        if (c->mixed)
+            launch_xupdate<float>(d, (const zf*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
+        else
+            launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
+        launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
+        launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
+        launch_cycle_init(d, kr, false, st);
+        launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+        HIPCHK(hipMemcpyAsync(c->h_flags, kr.solve_active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(c->h_flags + S, kr.err, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (c->h_flags[S]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
+        bool any = false;
+        for (int s = 0; s < S; ++s) any |= c->h_flags[s] != 0;
+        if (!any) break;
+        if (launched >= c->solver.max_iters) {
+            if (total_iters) *total_iters = launched;
+            return fail(APFC_ERR_NOT_CONVERGED, "FGMRES reached max_iters");
+        }
+    }
+    if (total_iters) *total_iters = launched;
+    return APFC_OK;
+}
+
+int fill_stats(apfc_ctx* c, hipStream_t st, apfc_stats* stats, double ms) {
+    if (!stats) return APFC_OK;
+    const int S = c->S;
+    HIPCHK(hipMemcpyAsync(c->h_flags, c->kr.iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->h_flags + S, c->kr.cycles, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->h_dbl, c->kr.relres, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    stats->total_iters = 0;
+    stats->max_iters = 0;
+    stats->cycles = 0;
+    stats->max_relres = 0.0;
+    for (int s = 0; s < S; ++s) {
+        stats->total_iters += c->h_flags[s];
+        stats->max_iters = std::max(stats->max_iters, c->h_flags[s]);
+        stats->cycles = std::max(stats->cycles, c->h_flags[S + s]);
+        stats->max_relres = std::max(stats->max_relres, c->h_dbl[s]);
+        if (stats->iters) stats->iters[s] = c->h_flags[s];
+    }
+    stats->ms = ms;
+    return APFC_OK;
+}
+
+int check_states(apfc_ctx* c, const apfc_state* states, bool need_zeta) {
+    if (!states) return fail(APFC_ERR_INVALID, "states is NULL");
+    for (int b = 0; b < c->count; ++b)
+        if (!states[b].eta || (need_zeta && !states[b].zeta)) return fail(APFC_ERR_INVALID, "state pointer is NULL");
+    return APFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, void* stream,
+              apfc_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, true); rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = refresh_dt(c, dt, st); rc) return rc;
+    std::vector<const void*> t[3];
+    for (int b = 0; b < c->count; ++b) {
+        t[0].push_back(states[b].eta);
+        t[1].push_back(states[b].zeta);
+        t[2].push_back(source ? source[b] : nullptr);
+        if (source && !source[b]) return fail(APFC_ERR_INVALID, "source[b] is NULL");
+    }
+    if (int rc = upload_ptrs(c, t, 3, st); rc) return rc;
+    Dev d = c->dev();
+    launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
+    launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
+    int iters = 0;
+    for (int k = 0; k < c->solver.picard_iters; ++k) {
+        // all amplitudes linearised at the previous iterate (Jacobi splitting)
+        launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
+        if (int rc = fgmres(c, st, &iters); rc) {
+            (void)fill_stats(c, st, stats, 0.0);
+            return rc;
+        }
+    }
+    launch_state_out(d, c->X, tab(c, 0), tab(c, 1), st);
+    HIPCHK(hipGetLastError());
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return fill_stats(c, st, stats, ms);
+}
+
+int apfc_init_zeta(apfc_ctx* c, apfc_state* states, void* stream) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, true); rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<const void*> t[2];
+    for (int b = 0; b < c->count; ++b) {
+        t[0].push_back(states[b].eta);
+        t[1].push_back(states[b].zeta);
+    }
+    if (int rc = upload_ptrs(c, t, 2, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    launch_state_in(d, tab(c, 0), nullptr, c->X, st);
+    const int it = c->dim == 2 ? 60 : 100;
+    launch_mass_solve(d, c->X + c->NT, c->R, c->R + c->NT, c->W, c->W + c->NT, c->B, c->tpart, it, st);
+    launch_planar_out(d, c->R, tab(c, 1), st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return APFC_OK;
+}
+
+int apfc_energy(apfc_ctx* c, const apfc_state* states, double* host_out, void* stream) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, false); rc) return rc;
+    if (!host_out) return fail(APFC_ERR_INVALID, "host_out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<const void*> t[1];
+    for (int b = 0; b < c->count; ++b) t[0].push_back(states[b].eta);
+    if (int rc = upload_ptrs(c, t, 1, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    launch_state_in(d, tab(c, 0), nullptr, c->X, st);
+    const int it = c->dim == 2 ? 60 : 100;
+    launch_mass_solve(d, c->X + c->NT, c->R, c->R + c->NT, c->W, c->W + c->NT, c->B, c->tpart, it, st);
+    launch_energy_parts(d, c->X + c->NT, c->R, c->tpart, st);
+    launch_reduce(d, c->tpart, kE0, 2, false, c->kr.redr, kSlots, nullptr, st);
+    HIPCHK(hipMemcpyAsync(c->h_dbl, c->kr.redr, sizeof(double) * kSlots * c->S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < c->count; ++b) {
+        double e = 0.0;
+        for (int j = 0; j < c->J; ++j) e += c->h_dbl[(b * c->J + j) * kSlots + 0];
+        e += c->h_dbl[(b * c->J) * kSlots + 1];
+        host_out[b] = e;
+    }
+    return APFC_OK;
+}
+
+int apfc_energy_grad(apfc_ctx* c, const apfc_state* states, double* const* grad, double* ddB, void* stream) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, false); rc) return rc;
+    if (!grad) return fail(APFC_ERR_INVALID, "grad is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<const void*> t[2];
+    for (int b = 0; b < c->count; ++b) {
+        if (!grad[b]) return fail(APFC_ERR_INVALID, "grad[b] is NULL");
+        t[0].push_back(states[b].eta);
+        t[1].push_back(grad[b]);
+    }
+    if (int rc = upload_ptrs(c, t, 2, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    launch_state_in(d, tab(c, 0), nullptr, c->X, st);
+    const int it = c->dim == 2 ? 60 : 100;
+    launch_mass_solve(d, c->X + c->NT, c->R, c->R + c->NT, c->W, c->W + c->NT, c->B, c->tpart, it, st);
+    launch_energy_grad(d, c->X + c->NT, c->R, tab(c, 1), c->tpart, st);
+    launch_reduce(d, c->tpart, kE1, 1, false, c->kr.redr, kSlots, nullptr, st);
+    HIPCHK(hipMemcpyAsync(c->h_dbl, c->kr.redr, sizeof(double) * kSlots * c->S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ddB)
+        for (int b = 0; b < c->count; ++b) ddB[b] += c->h_dbl[(b * c->J) * kSlots];
+    return APFC_OK;
+}
+
+int apfc_step_adjoint(apfc_ctx* c, const apfc_state* before, const apfc_state* after, double dt,
+                      const double* const* lam_after, double* const* lam_before, double* dL_ddB, void* stream,
+                      apfc_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = need_ws(c); rc) return rc;
+    if (c->solver.picard_iters != 1) return fail(APFC_ERR_INVALID, "apfc_step_adjoint needs picard_iters == 1");
+    if (int rc = check_states(c, before, false); rc) return rc;
+    if (int rc = check_states(c, after, false); rc) return rc;
+    if (!lam_after || !lam_before) return fail(APFC_ERR_INVALID, "lam arrays are NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = refresh_dt(c, dt, st); rc) return rc;
+    std::vector<const void*> t[4];
+    for (int b = 0; b < c->count; ++b) {
+        if (!lam_after[b] || !lam_before[b]) return fail(APFC_ERR_INVALID, "lam pointer is NULL");
+        t[0].push_back(before[b].eta);
+        t[1].push_back(after[b].eta);
+        t[2].push_back(lam_after[b]);
+        t[3].push_back(lam_before[b]);
+    }
+    if (int rc = upload_ptrs(c, t, 4, st); rc) return rc;
+    Dev d = c->dev();
+    launch_planar_in(d, tab(c, 0), c->BB, st);                  // eta^{m-1}
+    launch_nonlinear(d, c->BB, c->BB, c->dnode, c->B, st);      // only d(eta^{m-1}) is used
+    launch_adjoint_rhs(d, tab(c, 2), c->B, st);                 // B = [0 ; lam]
+    launch_fill_zero(c->X, 2 * c->NT, st);
+    int iters = 0;
+    if (int rc = fgmres(c, st, &iters); rc) {
+        (void)fill_stats(c, st, stats, 0.0);
+        return rc;
+    }
+    launch_adjoint_out(d, c->X, c->BB, tab(c, 1), tab(c, 3), c->tpart, st);
+    launch_reduce(d, c->tpart, kE1, 1, false, c->kr.redr, kSlots, nullptr, st);
+    HIPCHK(hipMemcpyAsync(c->h_dbl, c->kr.redr, sizeof(double) * kSlots * c->S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (dL_ddB)
+        for (int b = 0; b < c->count; ++b) dL_ddB[b] += c->h_dbl[(b * c->J) * kSlots];
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return fill_stats(c, st, stats, ms);
+}
+
+int apfc_set_graphs(apfc_ctx* c, int enable) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    c->use_graphs = enable != 0;
+    return APFC_OK;
+}
+
+int apfc_probe_enable(apfc_ctx* c, const char* name) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    const int kid = name ? kernel_id(name) : KID_NONE;
+    if (name && kid == KID_NONE) return fail(APFC_ERR_INVALID, std::string("unknown kernel name: ") + name);
+    if (!c->probe.created && kid != KID_NONE) {
+        for (auto& e : c->probe.ev) HIPCHK(hipEventCreate(&e));
+        c->probe.created = true;
+    }
+    c->probe.target = kid;
+    c->probe.n = 0;
+    c->probe.bytes = 0.0;
+    return APFC_OK;
+}
+
+int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_per_launch) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    double tot = 0.0;
+    for (int i = 0; i < c->probe.n; ++i) {
+        HIPCHK(hipEventSynchronize(c->probe.ev[2 * i + 1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->probe.ev[2 * i], c->probe.ev[2 * i + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = c->probe.n;
+    if (total_ms) *total_ms = tot;
+    if (bytes_per_launch) *bytes_per_launch = c->probe.n > 0 ? c->probe.bytes / c->probe.n : 0.0;
+    c->probe.n = 0;
+    c->probe.bytes = 0.0;
+    return APFC_OK;
+}
+
+int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
+    if (int rc = need_ws(c); rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int cand[4] = {4, 8, 16, 32};
+    float best = 1e30f;
+    int best_ty = c->TY;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    launch_fill_zero(c->V, 2 * c->NT, st);
+    hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, c->kr, c->S);
+    for (int ty : cand) {
+        c->TY = ty;
+        build_tiles(*c, ty, c->tiles);
+        if (int rc = upload_tables(*c); rc) return rc;
+        Dev d = c->dev();
+        d.probe = nullptr;
+        auto body = [&]() {
+            if (c->mixed) {
+                zf** pc = (zf**)c->pc;
+                launch_precond<float>(d, c->V, (zf*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                                      c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+                launch_apply<float>(d, (zf*)c->Z, c->dnode, c->W, nullptr, st);
+            } else {
+                zd** pc = (zd**)c->pc;
+                launch_precond<double>(d, c->V, (zd*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                                       c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+                launch_apply<double>(d, (zd*)c->Z, c->dnode, c->W, nullptr, st);
+            }
+        };
+        body();
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) body();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_ty = ty;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->TY = best_ty;
+    build_tiles(*c, best_ty, c->tiles);
+    if (int rc = upload_tables(*c); rc) return rc;
+    invalidate_graphs(*c);
+    if (chosen) *chosen = best_ty;
+    return APFC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1327 @@
+// HIP kernels of the APFC time step for gfx950 (CDNA4, wave64).
+//
+// Every operator here is a constant-coefficient tensor-product stencil of the Q1 element on a
+// periodic uniform mesh, built from the 1D weights
+//     mass m = h/6 [1 4 1],  stiffness k = 1/h [-1 2 -1],  derivative d = 1/2 [-1 0 1]
+// (row = test function, column = trial function), so that
+//     M = m (x) m (x) m,   K = sum_d k_d (x) m (x) m,   T_j = 2 sum_d k_{j,d} d_d (x) m (x) m,
+//     G_j = -K + i T_j                                  (Sec. II.A, Eq. (8)-(11)).
+// The stencils are evaluated separably (x pass, then y, then z) from neighbour loads; all
+// kernels stream HBM with 64-wide rows per wave.  Reductions are deterministic: one partial
+// per workgroup, summed in a fixed order.
+#include "apfc_internal.h"
+
+#include <type_traits>
+#include <utility>
+
+namespace apfc {
+
+// ------------------------------------------------------------------------------------------
+// complex helpers
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ R abs2(cx<R> a) { return a.x * a.x + a.y * a.y; }
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cdot(cx<R> a, cx<R> b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.y, a.x}; }
+
+template <typename R, typename S>
+__device__ __forceinline__ cx<R> ld(const cx<S>* p, long long i) {
+    const cx<S> v = p[i];
+    return {R(v.x), R(v.y)};
+}
+template <typename S, typename R>
+__device__ __forceinline__ void stv(cx<S>* p, long long i, cx<R> v) {
+    p[i] = cx<S>{S(v.x), S(v.y)};
+}
+
+// ------------------------------------------------------------------------------------------
+// reductions
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV per-thread values over the workgroup; thread 0 receives the totals.  lds >= 4*NV.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double t = wave_sum(v[i]);
+        if (lane == 0) lds[wv * NV + i] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = ((lds[i] + lds[NV + i]) + lds[2 * NV + i]) + lds[3 * NV + i];
+    }
+    __syncthreads();
+}
+
+// The same fixed-order sum of part[slot*P + t], t in [beg, end), in every workgroup.
+template <int NS>
+__device__ __forceinline__ void sum_partials(const double* part, long long P, const int (&slot)[NS], int beg,
+                                             int end, double (&out)[NS], double* lds) {
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            double a = 0.0;
+            for (int t = beg + (int)threadIdx.x; t < end; t += 64) a += part[slot[k] * P + t];
+            a = wave_sum(a);
+            if (threadIdx.x == 0) lds[k] = a;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) out[k] = lds[k];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------
+// geometry: periodic neighbours of node (x, y, z)
+// ------------------------------------------------------------------------------------------
+template <int DIM>
+struct Nbr {
+    int xs[3];
+    long long rb[DIM == 3 ? 3 : 1][3];   // [dz][dy] local node index of (0, y+dy, z+dz)
+};
+
+template <int DIM>
+__device__ __forceinline__ void make_nbr(const Sys& s, int x, int y, int z, Nbr<DIM>& n) {
+    n.xs[0] = x == 0 ? s.nx - 1 : x - 1;
+    n.xs[1] = x;
+    n.xs[2] = x == s.nx - 1 ? 0 : x + 1;
+    const int ys[3] = {y == 0 ? s.ny - 1 : y - 1, y, y == s.ny - 1 ? 0 : y + 1};
+    if constexpr (DIM == 2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) n.rb[0][b] = (long long)ys[b] * s.nx;
+    } else {
+        const int zs[3] = {z == 0 ? s.nz - 1 : z - 1, z, z == s.nz - 1 ? 0 : z + 1};
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) n.rb[c][b] = ((long long)zs[c] * s.ny + ys[b]) * s.nx;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ long long nb_index(const Nbr<DIM>& n, int a, int b, int c) {
+    if constexpr (DIM == 2)
+        return n.rb[0][b] + n.xs[a];
+    else
+        return n.rb[c][b] + n.xs[a];
+}
+
+// Separable evaluation of (M u, K u, T_j u) at one node; f(a, b, c) returns u at the
+// neighbour (x + a - 1, y + b - 1, z + c - 1).
+template <int DIM, bool WK, bool WT, typename R, typename F>
+__device__ __forceinline__ void stencil(const F& f, R h, R k0, R k1, R k2, cx<R>& Mu, cx<R>& Ku, cx<R>& Tu) {
+    const R m0 = h * R(1.0 / 6.0), m1 = h * R(4.0 / 6.0), ih = R(1) / h, half = R(0.5);
+    auto mass1 = [&](cx<R> l, cx<R> c, cx<R> r) { return m0 * (l + r) + m1 * c; };
+    auto stiff1 = [&](cx<R> l, cx<R> c, cx<R> r) { return ih * ((c + c) - (l + r)); };
+    auto der1 = [&](cx<R> l, cx<R> r) { return half * (r - l); };
+    if constexpr (DIM == 2) {
+        cx<R> mx[3], kx[3], dx[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const cx<R> l = f(0, b, 1), c = f(1, b, 1), r = f(2, b, 1);
+            mx[b] = mass1(l, c, r);
+            if (WK) kx[b] = stiff1(l, c, r);
+            if (WT) dx[b] = der1(l, r);
+        }
+        Mu = mass1(mx[0], mx[1], mx[2]);
+        if (WK) Ku = mass1(kx[0], kx[1], kx[2]) + stiff1(mx[0], mx[1], mx[2]);
+        if (WT) Tu = R(2) * (k0 * mass1(dx[0], dx[1], dx[2]) + k1 * der1(mx[0], mx[2]));
+    } else {
+        cx<R> mxy[3], kxy[3], dxm[3], dym[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> mx[3], kx[3], dx[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const cx<R> l = f(0, b, c), ce = f(1, b, c), r = f(2, b, c);
+                mx[b] = mass1(l, ce, r);
+                if (WK) kx[b] = stiff1(l, ce, r);
+                if (WT) dx[b] = der1(l, r);
+            }
+            mxy[c] = mass1(mx[0], mx[1], mx[2]);
+            if (WK) kxy[c] = mass1(kx[0], kx[1], kx[2]) + stiff1(mx[0], mx[1], mx[2]);
+            if (WT) {
+                dxm[c] = mass1(dx[0], dx[1], dx[2]);
+                dym[c] = der1(mx[0], mx[2]);
+            }
+        }
+        Mu = mass1(mxy[0], mxy[1], mxy[2]);
+        if (WK) Ku = mass1(kxy[0], kxy[1], kxy[2]) + stiff1(mxy[0], mxy[1], mxy[2]);
+        if (WT)
+            Tu = R(2) * (k0 * mass1(dxm[0], dxm[1], dxm[2]) + k1 * mass1(dym[0], dym[1], dym[2]) +
+                         k2 * der1(mxy[0], mxy[2]));
+    }
+}
+
+// G u = -K u + i T u
+template <typename R>
+__device__ __forceinline__ cx<R> gop(cx<R> Ku, cx<R> Tu) {
+    return {-Ku.x - Tu.y, -Ku.y + Tu.x};
+}
+
+// ------------------------------------------------------------------------------------------
+// tile iteration: a workgroup covers x in [x0, x0+64) and rows y0 + ty + 4 r (r < TY/4)
+// ------------------------------------------------------------------------------------------
+#define TILE_PROLOGUE()                                        \
+    const Tile tile = tiles[blockIdx.x];                       \
+    if (mask && !mask[tile.sys]) return;                       \
+    const Sys s = sys[tile.sys];                               \
+    const int x = tile.x0 + (int)(threadIdx.x & 63);           \
+    const int ty = (int)(threadIdx.x >> 6);
+
+#define FOR_ROWS(TY)                                           \
+    _Pragma("unroll") for (int rr_ = 0; rr_ < (TY) / 4; ++rr_) \
+        if (const int y = tile.y0 + ty + 4 * rr_; x < s.nx && y < s.ny)
+
+// ------------------------------------------------------------------------------------------
+// state <-> batched vector
+// ------------------------------------------------------------------------------------------
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_state_in(const Sys* sys, const Tile* tiles, const int* mask,
+                                                    double* const* eta_tab, double* const* zeta_tab, zd* X,
+                                                    long long NT) {
+    TILE_PROLOGUE();
+    const double* e = eta_tab[s.inst] + (long long)s.j * 2 * s.N;
+    const double* z = zeta_tab ? zeta_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    FOR_ROWS(TY) {
+        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        X[NT + s.off + i] = zd{e[i], e[s.N + i]};
+        if (z) X[s.off + i] = zd{z[i], z[s.N + i]};
+    }
+}
+
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_state_out(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
+                                                     double* const* eta_tab, double* const* zeta_tab, long long NT) {
+    TILE_PROLOGUE();
+    double* e = eta_tab[s.inst] + (long long)s.j * 2 * s.N;
+    double* z = zeta_tab ? zeta_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    FOR_ROWS(TY) {
+        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const zd ve = X[NT + s.off + i];
+        e[i] = ve.x;
+        e[s.N + i] = ve.y;
+        if (z) {
+            const zd vz = X[s.off + i];
+            z[i] = vz.x;
+            z[s.N + i] = vz.y;
+        }
+    }
+}
+
+// planar [J][2][N] per instance <-> one batched half vector
+template <int DIM, int TY, bool IN>
+__global__ __launch_bounds__(kBlock) void k_planar(const Sys* sys, const Tile* tiles, const int* mask,
+                                                  double* const* tab, zd* half) {
+    TILE_PROLOGUE();
+    double* p = tab[s.inst] + (long long)s.j * 2 * s.N;
+    FOR_ROWS(TY) {
+        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        if constexpr (IN) {
+            half[s.off + i] = zd{p[i], p[s.N + i]};
+        } else {
+            const zd v = half[s.off + i];
+            p[i] = v.x;
+            p[s.N + i] = v.y;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(zd* p, long long n) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        p[i] = zd{0.0, 0.0};
+}
+
+// ------------------------------------------------------------------------------------------
+// bulk energy at one node (Eq. (5) with the resonant terms of the lattice)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double term_coef(const Terms& T, int t, const Sys& s) {
+    return T.order[t] == 3 ? -2.0 * s.a3 / s.a0 : 8.0 * s.a2 / s.a0;
+}
+__device__ __forceinline__ zd factor(const Terms& T, int t, int q, const zd* eta) {
+    const zd v = eta[T.idx[t][q]];
+    return T.cj[t][q] ? cconj(v) : v;
+}
+
+// d = dF_j = 2 a1/a0 + 4 (a2/a0) A (same for every j), h_j = F^s_j - d eta_j.
+__device__ __forceinline__ void bulk_h(const Terms& T, const Sys& s, const zd* eta, double& d, zd* h) {
+    const int J = T.J;
+    double A = 0.0;
+    for (int l = 0; l < J; ++l) A += abs2(eta[l]);
+    A *= 2.0;
+    d = 2.0 * s.a1 / s.a0 + 4.0 * s.a2 / s.a0 * A;
+    const double c4 = -4.0 * s.a2 / s.a0;
+    for (int l = 0; l < J; ++l) h[l] = (c4 * abs2(eta[l])) * eta[l];
+    for (int t = 0; t < T.n; ++t) {
+        const double c = term_coef(T, t, s);
+        const int ord = T.order[t];
+        for (int q = 0; q < ord; ++q) {
+            zd p{c, 0.0};
+            for (int r = 0; r < ord; ++r)
+                if (r != q) p = cmul(p, factor(T, t, r, eta));
+            const int l = T.idx[t][q];
+            h[l] = h[l] + (T.cj[t][q] ? p : cconj(p));
+        }
+    }
+}
+
+__device__ __forceinline__ double bulk_f(const Terms& T, const Sys& s, const zd* eta) {
+    const int J = T.J;
+    double A = 0.0, S4 = 0.0;
+    for (int l = 0; l < J; ++l) {
+        const double a = abs2(eta[l]);
+        A += a;
+        S4 += a * a;
+    }
+    A *= 2.0;
+    double f = s.a1 / s.a0 * A + s.a2 / s.a0 * (A * A - 2.0 * S4);
+    for (int t = 0; t < T.n; ++t) {
+        zd p{1.0, 0.0};
+        for (int r = 0; r < T.order[t]; ++r) p = cmul(p, factor(T, t, r, eta));
+        f += 2.0 * term_coef(T, t, s) * p.x;
+    }
+    return f;
+}
+
+// ------------------------------------------------------------------------------------------
+// RHS and nonlinearity (Eq. (10)/(11), nodal quadrature)
+// ------------------------------------------------------------------------------------------
+// BB_j = M eta_j / dt (+ M s_j)
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_rhs_base(const Sys* sys, const Tile* tiles, const int* mask,
+                                                    const zd* Xeta, double* const* src_tab, zd* BB) {
+    TILE_PROLOGUE();
+    const double* src = src_tab ? src_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        zd Mu, Ku, Tu;
+        stencil<DIM, false, false, double>(
+            [&](int a, int b, int c) { return Xeta[s.off + nb_index<DIM>(n, a, b, c)]; }, s.h, s.kv[0], s.kv[1],
+            s.kv[2], Mu, Ku, Tu);
+        zd out = s.inv_dt * Mu;
+        if (src) {
+            zd Ms;
+            stencil<DIM, false, false, double>(
+                [&](int a, int b, int c) {
+                    const long long i = nb_index<DIM>(n, a, b, c);
+                    return zd{src[i], src[s.N + i]};
+                },
+                s.h, 0.0, 0.0, 0.0, Ms, Ku, Tu);
+            out = out + Ms;
+        }
+        BB[s.off + nb_index<DIM>(n, 1, 1, 1)] = out;
+    }
+}
+
+// d (per instance node) and B = [0 ; BB - kappa_j w h_j(eta_it)] for every amplitude of the instance.
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
+                                                     const zd* eta_half, const zd* BB, double* dnode, zd* B,
+                                                     long long NT) {
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    if (s.j != 0) return;
+    FOR_ROWS(TY) {
+        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        zd eta[kMaxJ], h[kMaxJ];
+        for (int l = 0; l < T.J; ++l) eta[l] = eta_half[s.off + l * s.N + i];
+        double d;
+        bulk_h(T, s, eta, d, h);
+        dnode[s.doff + i] = d;
+        for (int l = 0; l < T.J; ++l) {
+            const double kap = sys[tile.sys + l].kappa;
+            const long long o = s.off + l * s.N + i;
+            B[o] = zd{0.0, 0.0};
+            B[NT + o] = BB[o] - (kap * s.w) * h[l];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// block operator A_j (Eq. (11)): y1 = M zeta - G eta,  y2 = kappa G zeta + M eta/dt + kappa w d eta
+// ------------------------------------------------------------------------------------------
+template <int DIM, typename S>
+__device__ __forceinline__ void apply_A(const Sys& s, const Nbr<DIM>& n, const cx<S>* zz, const cx<S>* ze, double dn,
+                                        zd& y1, zd& y2) {
+    zd Mz, Kz, Tz, Me, Ke, Te;
+    stencil<DIM, true, true, double>(
+        [&](int a, int b, int c) { return ld<double>(zz, s.off + nb_index<DIM>(n, a, b, c)); }, s.h, s.kv[0],
+        s.kv[1], s.kv[2], Mz, Kz, Tz);
+    stencil<DIM, true, true, double>(
+        [&](int a, int b, int c) { return ld<double>(ze, s.off + nb_index<DIM>(n, a, b, c)); }, s.h, s.kv[0],
+        s.kv[1], s.kv[2], Me, Ke, Te);
+    const zd ec = ld<double>(ze, s.off + nb_index<DIM>(n, 1, 1, 1));
+    y1 = Mz - gop(Ke, Te);
+    y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dn) * ec;
+}
+
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_residual(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
+                                                    const zd* B, const double* dnode, zd* R, double* part,
+                                                    long long NT, int ntiles) {
+    __shared__ double lds[8];
+    TILE_PROLOGUE();
+    double acc[2] = {0.0, 0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        const long long il = nb_index<DIM>(n, 1, 1, 1);
+        zd y1, y2;
+        apply_A<DIM, double>(s, n, X, X + NT, dnode[s.doff + il], y1, y2);
+        const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
+        const zd r1 = b1 - y1, r2 = b2 - y2;
+        R[s.off + il] = r1;
+        R[NT + s.off + il] = r2;
+        acc[0] += abs2(r1) + abs2(r2);
+        acc[1] += abs2(b1) + abs2(b2);
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
+        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
+    }
+}
+
+template <int DIM, int TY, typename T>
+__global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* tiles, const int* mask,
+                                                 const cx<T>* Z, const double* dnode, zd* W, long long NT) {
+    TILE_PROLOGUE();
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        const long long il = nb_index<DIM>(n, 1, 1, 1);
+        zd y1, y2;
+        apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + il], y1, y2);
+        W[s.off + il] = y1;
+        W[NT + s.off + il] = y2;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Block preconditioner (Eq. (12), four steps) with fixed-count Jacobi-PCG inner solves.
+// Operator of an inner solve: OP = 0 -> M (diag diagM), OP = 1 -> L = M/sqrt(dt) + sqrt(kappa) K.
+// The Jacobi diagonal is a constant on the uniform periodic mesh.
+// Partials: rho ping-pong slots kRho0/kRho1 = sum |r|^2 / D, slot kPQ = Re p^H q.
+// ------------------------------------------------------------------------------------------
+template <int OP>
+__device__ __forceinline__ double op_diag(const Sys& s) { return OP == 0 ? s.diagM : s.diagL; }
+
+// step 1 init: r = beta1 (zeta part of v), p0 = r / D_M
+template <int DIM, int TY, typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_init_copy(const Sys* sys, const Tile* tiles, const int* mask,
+                                                        const zd* v, cx<T>* r, cx<T>* p0, double* part,
+                                                        int ntiles) {
+    __shared__ double lds[4];
+    TILE_PROLOGUE();
+    const double iD = 1.0 / s.diagM;
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        const cx<T> rv = ld<T>(v, i);
+        r[i] = rv;
+        p0[i] = T(iD) * rv;
+        acc[0] += (double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y)) * iD;
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kRho0 * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// step 2 init: r = beta2 - kappa G x1 (x1 ~ M^{-1} beta1), p0 = r / D_L
+template <int DIM, int TY, typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_init_g(const Sys* sys, const Tile* tiles, const int* mask,
+                                                     const zd* v, const cx<T>* x1, cx<T>* r, cx<T>* p0,
+                                                     double* part, int ntiles, long long NT) {
+    __shared__ double lds[4];
+    TILE_PROLOGUE();
+    const T iD = T(1.0 / s.diagL);
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        cx<T> Mu, Ku, Tu;
+        stencil<DIM, true, true, T>([&](int a, int b, int c) { return ld<T>(x1, s.off + nb_index<DIM>(n, a, b, c)); },
+                                    T(s.h), T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
+        const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
+        const cx<T> rv = ld<T>(v, NT + i) - T(s.kappa) * gop(Ku, Tu);
+        r[i] = rv;
+        p0[i] = iD * rv;
+        acc[0] += (double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y)) / s.diagL;
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kRho0 * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// step 3 init: r = M x2 (x2 ~ beta2'), p0 = r / D_L.  Also the energy's mass solve uses
+// GETA = true: r = G_j eta_j (rhs of M zeta = G eta), p0 = r / D_M.
+template <int DIM, int TY, typename T, bool GETA>
+__global__ __launch_bounds__(kBlock) void k_cg_init_m(const Sys* sys, const Tile* tiles, const int* mask,
+                                                     const cx<T>* x2, cx<T>* r, cx<T>* p0, double* part,
+                                                     int ntiles) {
+    __shared__ double lds[4];
+    TILE_PROLOGUE();
+    const double D = GETA ? s.diagM : s.diagL;
+    const T iD = T(1.0 / D);
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        cx<T> Mu, Ku, Tu;
+        stencil<DIM, GETA, GETA, T>([&](int a, int b, int c) { return ld<T>(x2, s.off + nb_index<DIM>(n, a, b, c)); },
+                                    T(s.h), T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
+        const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
+        const cx<T> rv = GETA ? gop(Ku, Tu) : Mu;
+        r[i] = rv;
+        p0[i] = iD * rv;
+        acc[0] += (double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y)) / D;
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kRho0 * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// q = OP p with p = r/D + beta p_prev (FIRST: p = pin as is); partial Re p^H q.
+template <int DIM, int TY, typename T, int OP, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(const Sys* sys, const Tile* tiles, const int* mask,
+                                                   const cx<T>* r, const cx<T>* pin, cx<T>* pout, cx<T>* q,
+                                                   double* part, int ntiles, int it) {
+    __shared__ double lds[8];
+    TILE_PROLOGUE();
+    const double D = op_diag<OP>(s);
+    T beta = T(0);
+    if constexpr (!FIRST) {
+        const int sl[2] = {it & 1, (it - 1) & 1};
+        double rho[2];
+        sum_partials<2>(part, ntiles, sl, s.tbeg, s.tend, rho, lds);
+        beta = rho[1] != 0.0 ? T(rho[0] / rho[1]) : T(0);
+    }
+    const T iD = T(1.0 / D);
+    const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        auto fp = [&](int a, int b, int c) {
+            const long long i = s.off + nb_index<DIM>(n, a, b, c);
+            if constexpr (FIRST)
+                return ld<T>(pin, i);
+            else
+                return iD * ld<T>(r, i) + beta * ld<T>(pin, i);
+        };
+        cx<T> Mu, Ku, Tu;
+        stencil<DIM, OP == 1, false, T>(fp, T(s.h), T(0), T(0), T(0), Mu, Ku, Tu);
+        const cx<T> qv = OP == 0 ? Mu : cM * Mu + cK * Ku;
+        const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
+        const cx<T> pc = fp(1, 1, 1);
+        if constexpr (!FIRST) pout[i] = pc;
+        q[i] = qv;
+        acc[0] += double(pc.x) * double(qv.x) + double(pc.y) * double(qv.y);
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kPQ * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// alpha = rho / p^H q; x = x + alpha p (FIRST: x = alpha p); r -= alpha q and partial of the
+// next rho unless LAST.
+template <int DIM, int TY, typename T, int OP, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cg_update(const Sys* sys, const Tile* tiles, const int* mask,
+                                                     cx<T>* xv, cx<T>* r, const cx<T>* p, const cx<T>* q,
+                                                     double* part, int ntiles, int it) {
+    __shared__ double lds[8];
+    TILE_PROLOGUE();
+    const int sl[2] = {it & 1, kPQ};
+    double red[2];
+    sum_partials<2>(part, ntiles, sl, s.tbeg, s.tend, red, lds);
+    const T alpha = (red[0] != 0.0 && red[1] != 0.0) ? T(red[0] / red[1]) : T(0);
+    const double D = op_diag<OP>(s);
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        const cx<T> pv = ld<T>(p, i);
+        if constexpr (FIRST)
+            xv[i] = alpha * pv;
+        else
+            xv[i] = ld<T>(xv, i) + alpha * pv;
+        if constexpr (!LAST) {
+            const cx<T> rv = ld<T>(r, i) - alpha * ld<T>(q, i);
+            r[i] = rv;
+            acc[0] += (double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y)) / D;
+        }
+    }
+    if constexpr (!LAST) {
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) part[((it + 1) & 1) * (long long)ntiles + blockIdx.x] = acc[0];
+    }
+}
+
+// step 4: chi1 = beta1' - (beta2' - chi2 / sqrt(dt)) / sqrt(kappa); chi2 already in z's eta part
+template <int DIM, int TY, typename T>
+__global__ __launch_bounds__(kBlock) void k_pc_final(const Sys* sys, const Tile* tiles, const int* mask,
+                                                    const cx<T>* x1, const cx<T>* x2, cx<T>* z, long long NT) {
+    TILE_PROLOGUE();
+    const T isd = T(s.isq_dt), isk = T(s.isq_kap);
+    FOR_ROWS(TY) {
+        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        z[i] = ld<T>(x1, i) - isk * (ld<T>(x2, i) - isd * ld<T>(z, NT + i));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Krylov kernels over chunks of full vectors (element e < N: zeta part, else eta part)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long long e) {
+    return e < s.N ? s.off + e : NT + s.off + (e - s.N);
+}
+
+#define CHUNK_PROLOGUE()                                 \
+    const Chunk ch = chunks[blockIdx.x];                 \
+    if (mask && !mask[ch.sys]) return;                   \
+    const Sys s = sys[ch.sys];                           \
+    const long long twoN = 2 * s.N;
+
+#define FOR_ELEMS()                                                                   \
+    _Pragma("unroll") for (int u_ = 0; u_ < kChunk / kBlock; ++u_)                    \
+        if (const long long e = (long long)ch.e0 + threadIdx.x + (long long)u_ * kBlock; e < twoN)
+
+// partials of V_i^H w' (i < nv) with w' = w - sum_l coef_l V_l when PROJECT, plus |w'|^2.
+// Each thread keeps its 8 elements of w' in registers; V is streamed once for the projection
+// and once more for the dots (the second pass mostly hits the caches).
+template <int NV, bool PROJECT>
+__global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const zd* V,
+                                                long long vstride, int nv, const zd* w, const double* coef,
+                                                int coef_ld, double* part, int nchunks, long long NT) {
+    constexpr int EPT = kChunk / kBlock;
+    __shared__ double lds[4 * (2 * NV + 1)];
+    __shared__ zd cf[NV];
+    CHUNK_PROLOGUE();
+    if (PROJECT) {
+        if (threadIdx.x < NV)
+            cf[threadIdx.x] = (int)threadIdx.x < nv ? zd{coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x],
+                                                        coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x + 1]}
+                                                    : zd{0.0, 0.0};
+        __syncthreads();
+    }
+    zd wv[EPT];
+    long long gi[EPT];
+    bool ok[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const long long e = (long long)ch.e0 + threadIdx.x + (long long)u * kBlock;
+        ok[u] = e < twoN;
+        gi[u] = ok[u] ? elem_index(s, NT, e) : 0;
+        wv[u] = ok[u] ? w[gi[u]] : zd{0.0, 0.0};
+    }
+    if constexpr (PROJECT) {
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                const zd c = cf[l];
+#pragma unroll
+                for (int u = 0; u < EPT; ++u)
+                    if (ok[u]) wv[u] = wv[u] - cmul(c, V[l * vstride + gi[u]]);
+            }
+    }
+    double acc[2 * NV + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NV; ++l)
+        if (l < nv) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u)
+                if (ok[u]) {
+                    const zd t = cdot(V[l * vstride + gi[u]], wv[u]);
+                    acc[2 * l] += t.x;
+                    acc[2 * l + 1] += t.y;
+                }
+        }
+    if constexpr (PROJECT) {
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) acc[2 * NV] += abs2(wv[u]);
+    }
+    block_sum<2 * NV + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < nv; ++l) {
+            part[(2 * l) * (long long)nchunks + blockIdx.x] = acc[2 * l];
+            part[(2 * l + 1) * (long long)nchunks + blockIdx.x] = acc[2 * l + 1];
+        }
+        if (PROJECT) part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
+    }
+}
+
+// out = (w - sum_l hcoef_l V_l) * hinv
+__global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chunk* chunks, const int* mask,
+                                                      const zd* V, long long vstride, int nv, const zd* w,
+                                                      const double* hcoef, int hld, const double* hinv, zd* out,
+                                                      long long NT) {
+    __shared__ zd cf[kMaxRestart + 1];
+    CHUNK_PROLOGUE();
+    for (int l = threadIdx.x; l < nv; l += kBlock)
+        cf[l] = zd{hcoef[ch.sys * hld + 2 * l], hcoef[ch.sys * hld + 2 * l + 1]};
+    __syncthreads();
+    const double sc = hinv[ch.sys];
+    FOR_ELEMS() {
+        const long long gi = elem_index(s, NT, e);
+        zd wv = w[gi];
+        for (int l = 0; l < nv; ++l) wv = wv - cmul(cf[l], V[l * vstride + gi]);
+        out[gi] = sc * wv;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(const Sys* sys, const Chunk* chunks, const int* mask, const zd* r,
+                                                 const double* inv_beta, zd* v0, long long NT) {
+    CHUNK_PROLOGUE();
+    const double sc = inv_beta[ch.sys];
+    FOR_ELEMS() {
+        const long long gi = elem_index(s, NT, e);
+        v0[gi] = sc * r[gi];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_xupdate(const Sys* sys, const Chunk* chunks, const int* mask,
+                                                   const cx<T>* Z, long long zstride, const int* kcount,
+                                                   const double* y, int ldy, zd* X, long long NT) {
+    __shared__ zd cf[kMaxRestart];
+    CHUNK_PROLOGUE();
+    const int kc = kcount[ch.sys];
+    if (kc <= 0) return;
+    for (int l = threadIdx.x; l < kc; l += kBlock) cf[l] = zd{y[ch.sys * ldy + 2 * l], y[ch.sys * ldy + 2 * l + 1]};
+    __syncthreads();
+    FOR_ELEMS() {
+        const long long gi = elem_index(s, NT, e);
+        zd xv = X[gi];
+        for (int l = 0; l < kc; ++l) xv = xv + cmul(cf[l], ld<double>(Z, l * zstride + gi));
+        X[gi] = xv;
+    }
+}
+
+// out[s*nvals + v] = sum of part[v*P + t] over the system's tiles or chunks (fixed order)
+__global__ __launch_bounds__(kBlock) void k_reduce(const Sys* sys, const int* mask, const double* part, long long P,
+                                                  int slot0, int nvals, bool chunk_ranges, double* out, int ld) {
+    const int si = blockIdx.x;
+    if (mask && !mask[si]) return;
+    const Sys s = sys[si];
+    const int beg = chunk_ranges ? s.cbeg : s.tbeg, end = chunk_ranges ? s.cend : s.tend;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int v = blockIdx.y * 4 + wv; v < nvals; v += gridDim.y * 4) {
+        double a = 0.0;
+        for (int t = beg + lane; t < end; t += 64) a += part[(slot0 + v) * P + t];
+        a = wave_sum(a);
+        if (lane == 0) out[si * (long long)ld + v] = a;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// small per-system FGMRES bookkeeping (one thread per system)
+// ------------------------------------------------------------------------------------------
+__global__ void k_cycle_init(Krylov kr, int S, int first) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (!first && !kr.solve_active[s]) return;
+    const double rr = kr.redr[2 * s], bb = kr.redr[2 * s + 1];
+    const double beta = sqrt(rr);
+    if (!isfinite(beta) || !isfinite(bb)) {
+        kr.err[0] = 1;
+        kr.solve_active[s] = 0;
+        kr.iter_active[s] = 0;
+        return;
+    }
+    if (first) {
+        const double bn = sqrt(bb);
+        kr.bnorm[s] = bn;
+        // a zero right-hand side is solved relative to the initial residual
+        kr.target[s] = kr.rtol * (bn > 0.0 ? bn : beta);
+    }
+    kr.relres[s] = kr.bnorm[s] > 0.0 ? beta / kr.bnorm[s] : beta;
+    kr.kcount[s] = 0;
+    if (beta <= kr.target[s]) {
+        kr.solve_active[s] = 0;
+        kr.iter_active[s] = 0;
+        return;
+    }
+    kr.solve_active[s] = 1;
+    kr.iter_active[s] = 1;
+    kr.cycles[s] += 1;
+    kr.inv_beta[s] = 1.0 / beta;
+    double* g = kr.g + (long long)s * 2 * (kr.m + 1);
+    g[0] = beta;
+    g[1] = 0.0;
+    for (int i = 1; i <= kr.m; ++i) g[2 * i] = g[2 * i + 1] = 0.0;
+}
+
+__global__ void k_arnoldi(Krylov kr, int S, int k) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || !kr.iter_active[s]) return;
+    const int m = kr.m, nv1 = kr.nv1;
+    const double* h1 = kr.red1 + (long long)s * nv1;
+    const double* h2 = kr.red2 + (long long)s * (nv1 + 1);
+    double* col = kr.H + ((long long)s * m + k) * 2 * (m + 1);
+    double* hs = kr.hsum + (long long)s * 2 * (m + 1);
+    double h2n = 0.0;
+    for (int i = 0; i <= k; ++i) {
+        const double re = h1[2 * i] + h2[2 * i], im = h1[2 * i + 1] + h2[2 * i + 1];
+        hs[2 * i] = re;
+        hs[2 * i + 1] = im;
+        col[2 * i] = re;
+        col[2 * i + 1] = im;
+        h2n += h2[2 * i] * h2[2 * i] + h2[2 * i + 1] * h2[2 * i + 1];
+    }
+    const double wn2 = h2[2 * (k + 1)];
+    const double hn = sqrt(fmax(wn2 - h2n, 0.0));
+    double cnorm = hn * hn;
+    for (int i = 0; i <= k; ++i) cnorm += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
+    cnorm = sqrt(cnorm);
+    // previous rotations: [c s; -conj(s) c]
+    double* cs = kr.cs + (long long)s * m;
+    double* sn = kr.sn + (long long)s * 2 * m;
+    for (int i = 0; i < k; ++i) {
+        const double ar = col[2 * i], ai = col[2 * i + 1], br = col[2 * i + 2], bi = col[2 * i + 3];
+        const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
+        col[2 * i] = c * ar + (sr * br - si * bi);
+        col[2 * i + 1] = c * ai + (sr * bi + si * br);
+        col[2 * i + 2] = -(sr * ar + si * ai) + c * br;
+        col[2 * i + 3] = -(sr * ai - si * ar) + c * bi;
+    }
+    // new rotation zeroing the subdiagonal hn (real, >= 0)
+    const double ar = col[2 * k], ai = col[2 * k + 1];
+    const double aa = sqrt(ar * ar + ai * ai);
+    const double nu = sqrt(aa * aa + hn * hn);
+    double c, sr, si, rr, ri;
+    if (hn == 0.0) {
+        c = 1.0; sr = 0.0; si = 0.0; rr = ar; ri = ai;
+    } else if (aa == 0.0) {
+        c = 0.0; sr = 1.0; si = 0.0; rr = hn; ri = 0.0;
+    } else {
+        c = aa / nu;
+        sr = (ar / aa) * hn / nu;
+        si = (ai / aa) * hn / nu;
+        rr = ar * nu / aa;
+        ri = ai * nu / aa;
+    }
+    cs[k] = c;
+    sn[2 * k] = sr;
+    sn[2 * k + 1] = si;
+    col[2 * k] = rr;
+    col[2 * k + 1] = ri;
+    double* g = kr.g + (long long)s * 2 * (m + 1);
+    const double gr = g[2 * k], gi = g[2 * k + 1];
+    g[2 * k] = c * gr;
+    g[2 * k + 1] = c * gi;
+    g[2 * k + 2] = -(sr * gr + si * gi);
+    g[2 * k + 3] = -(sr * gi - si * gr);
+    const double res = sqrt(g[2 * k + 2] * g[2 * k + 2] + g[2 * k + 3] * g[2 * k + 3]);
+    kr.iters[s] += 1;
+    kr.hinv[s] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (!isfinite(res) || !isfinite(hn)) {
+        kr.err[0] = 1;
+        kr.kcount[s] = 0;
+        kr.iter_active[s] = 0;
+        kr.solve_active[s] = 0;
+        return;
+    }
+    const bool breakdown = hn <= 1e-14 * cnorm;
+    if (res <= kr.target[s] || breakdown || k + 1 == m) {
+        kr.kcount[s] = k + 1;
+        kr.iter_active[s] = 0;
+    }
+}
+
+__global__ void k_solve_y(Krylov kr, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || !kr.solve_active[s]) return;
+    const int kc = kr.kcount[s], m = kr.m;
+    if (kc <= 0) return;
+    const double* g = kr.g + (long long)s * 2 * (m + 1);
+    double* y = kr.y + (long long)s * 2 * m;
+    for (int i = kc - 1; i >= 0; --i) {
+        double tr = g[2 * i], ti = g[2 * i + 1];
+        for (int l = i + 1; l < kc; ++l) {
+            const double* col = kr.H + ((long long)s * m + l) * 2 * (m + 1);
+            const double hr = col[2 * i], hi = col[2 * i + 1];
+            tr -= hr * y[2 * l] - hi * y[2 * l + 1];
+            ti -= hr * y[2 * l + 1] + hi * y[2 * l];
+        }
+        const double* cc = kr.H + ((long long)s * m + i) * 2 * (m + 1);
+        const double dr = cc[2 * i], di = cc[2 * i + 1];
+        const double den = dr * dr + di * di;
+        y[2 * i] = den > 0.0 ? (tr * dr + ti * di) / den : 0.0;
+        y[2 * i + 1] = den > 0.0 ? (ti * dr - tr * di) / den : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// energy, its gradient, adjoint pieces
+// ------------------------------------------------------------------------------------------
+// per tile: E0 = sum 2 Re(zeta^H G eta) - zeta^H M zeta (= eta^H G M^{-1} G eta to second order
+// in the error of zeta); E1 = sum w f^s(eta) on the amplitude-0 tiles of each instance.
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_energy(const Sys* sys, const Tile* tiles, const Terms T, const zd* eta,
+                                                  const zd* zeta, double* part, int ntiles) {
+    __shared__ double lds[8];
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    double acc[2] = {0.0, 0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        zd Me, Ke, Te, Mz, Kz, Tz;
+        stencil<DIM, true, true, double>([&](int a, int b, int c) { return eta[s.off + nb_index<DIM>(n, a, b, c)]; },
+                                         s.h, s.kv[0], s.kv[1], s.kv[2], Me, Ke, Te);
+        stencil<DIM, false, false, double>(
+            [&](int a, int b, int c) { return zeta[s.off + nb_index<DIM>(n, a, b, c)]; }, s.h, 0.0, 0.0, 0.0, Mz,
+            Kz, Tz);
+        const long long il = nb_index<DIM>(n, 1, 1, 1);
+        const zd zc = zeta[s.off + il];
+        acc[0] += 2.0 * cdot(zc, gop(Ke, Te)).x - cdot(zc, Mz).x;
+        if (s.j == 0) {
+            zd e[kMaxJ];
+            for (int l = 0; l < T.J; ++l) e[l] = eta[s.off + l * s.N + il];
+            acc[1] += s.w * bulk_f(T, s, e);
+        }
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[kE0 * (long long)ntiles + blockIdx.x] = acc[0];
+        part[kE1 * (long long)ntiles + blockIdx.x] = acc[1];
+    }
+}
+
+// grad_j = 2 (w F^s_j(eta) + G_j zeta_j) (planar output); partial of dE/dDeltaB = sum w A/(2 a0).
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_energy_grad(const Sys* sys, const Tile* tiles, const Terms T,
+                                                       const zd* eta, const zd* zeta, double* const* grad_tab,
+                                                       double* part, int ntiles) {
+    __shared__ double lds[4];
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    double* g = grad_tab[s.inst] + (long long)s.j * 2 * s.N;
+    double acc[1] = {0.0};
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        zd Mz, Kz, Tz;
+        stencil<DIM, true, true, double>([&](int a, int b, int c) { return zeta[s.off + nb_index<DIM>(n, a, b, c)]; },
+                                         s.h, s.kv[0], s.kv[1], s.kv[2], Mz, Kz, Tz);
+        const long long il = nb_index<DIM>(n, 1, 1, 1);
+        const long long i0 = s.off - (long long)s.j * s.N;     // amplitude 0 of this instance
+        zd e[kMaxJ], h[kMaxJ];
+        double A = 0.0;
+        for (int l = 0; l < T.J; ++l) {
+            e[l] = eta[i0 + l * s.N + il];
+            A += abs2(e[l]);
+        }
+        double d;
+        bulk_h(T, s, e, d, h);
+        const zd F = d * e[s.j] + h[s.j];
+        const zd gv = 2.0 * (s.w * F + gop(Kz, Tz));
+        g[il] = gv.x;
+        g[s.N + il] = gv.y;
+        if (s.j == 0) acc[0] += s.w * 2.0 * A / (2.0 * s.a0);
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kE1 * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// adjoint right-hand side [0 ; lam_j]
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_adjoint_rhs(const Sys* sys, const Tile* tiles, double* const* lam_tab,
+                                                       zd* B, long long NT) {
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    const double* lam = lam_tab[s.inst] + (long long)s.j * 2 * s.N;
+    FOR_ROWS(TY) {
+        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        B[s.off + i] = zd{0.0, 0.0};
+        B[NT + s.off + i] = zd{lam[i], lam[s.N + i]};
+    }
+}
+
+// lam_before_l = M mu_l / dt + nodal adjoint of -kappa_j w h_j(eta) and of kappa_j w diag(d(eta)) eta^m_j.
+// mu_j = eta part of Y = A_j^{-1} [0; lam_j] (Sigma leaves the eta part unchanged).
+// Launched on amplitude-0 tiles; computes every amplitude of the instance at the node.
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Tile* tiles, const Terms T, const zd* Y,
+                                                       const zd* eta_prev, double* const* eta_new_tab,
+                                                       double* const* lam_out_tab, double* part, int ntiles,
+                                                       long long NT) {
+    __shared__ double lds[4];
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    double acc[1] = {0.0};
+    if (s.j == 0) {
+        const double* en = eta_new_tab[s.inst];
+        double* lo = lam_out_tab[s.inst];
+        const int J = T.J;
+        FOR_ROWS(TY) {
+            Nbr<DIM> n;
+            make_nbr<DIM>(s, x, y, tile.z, n);
+            const long long il = nb_index<DIM>(n, 1, 1, 1);
+            zd ep[kMaxJ], nu[kMaxJ], gr[kMaxJ];
+            double C = 0.0;
+            for (int l = 0; l < J; ++l) {
+                const Sys& sl = sys[tile.sys + l];
+                const zd* mu = Y + NT;
+                zd Mm, Km, Tm;
+                stencil<DIM, false, false, double>(
+                    [&](int a, int b, int c) { return mu[sl.off + nb_index<DIM>(n, a, b, c)]; }, s.h, 0.0, 0.0, 0.0,
+                    Mm, Km, Tm);
+                gr[l] = s.inv_dt * Mm;
+                const zd muc = mu[sl.off + il];
+                ep[l] = eta_prev[sl.off + il];
+                nu[l] = (-sl.kappa * s.w) * muc;
+                const zd enl = zd{en[(long long)l * 2 * s.N + il], en[(long long)l * 2 * s.N + s.N + il]};
+                C += sl.kappa * s.w * cdot(muc, enl).x;
+            }
+            // pair term h_j += -4 (a2/a0) eta_j^2 eta_j^*
+            const double c4 = 4.0 * s.a2 / s.a0;
+            for (int l = 0; l < J; ++l) {
+                gr[l] = gr[l] - (2.0 * c4 * abs2(ep[l])) * nu[l] - c4 * cmul(cmul(ep[l], ep[l]), cconj(nu[l]));
+            }
+            // resonant terms c (T + T^*)
+            for (int t = 0; t < T.n; ++t) {
+                const double c = term_coef(T, t, s);
+                const int ord = T.order[t];
+                for (int q = 0; q < ord; ++q) {
+                    const zd nq = nu[T.idx[t][q]];
+                    const bool direct = T.cj[t][q];   // h_{idx q} += c prod_{r != q} u_r  (else its conjugate)
+                    for (int r = 0; r < ord; ++r) {
+                        if (r == q) continue;
+                        zd a{c, 0.0};
+                        for (int r2 = 0; r2 < ord; ++r2)
+                            if (r2 != q && r2 != r) {
+                                const zd u = factor(T, t, r2, ep);
+                                a = cmul(a, direct ? u : cconj(u));
+                            }
+                        const int l = T.idx[t][r];
+                        // the factor r of the contribution is eta_l when (direct and not conjugated) or
+                        // (not direct and conjugated); otherwise it is eta_l^*
+                        const bool is_eta = direct ? (T.cj[t][r] == 0) : (T.cj[t][r] != 0);
+                        gr[l] = gr[l] + (is_eta ? cmul(cconj(a), nq) : cmul(cconj(nq), a));
+                    }
+                }
+            }
+            // d = 2 a1/a0 + 8 (a2/a0) sum |eta|^2 enters A as kappa_j w d eta^m_j
+            for (int l = 0; l < J; ++l) {
+                gr[l] = gr[l] - (16.0 * s.a2 / s.a0 * C) * ep[l];
+                lo[(long long)l * 2 * s.N + il] = gr[l].x;
+                lo[(long long)l * 2 * s.N + s.N + il] = gr[l].y;
+            }
+            acc[0] += -C / s.a0;
+        }
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[kE1 * (long long)ntiles + blockIdx.x] = acc[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// launch plumbing
+// ------------------------------------------------------------------------------------------
+static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init",   "pc_final", "apply",  "residual",
+                                        "mdot",     "proj_final", "xupdate",    "reduce",   "small",  "other"};
+const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : "none"; }
+int kernel_id(const char* name) {
+    if (!name) return KID_NONE;
+    for (int i = 0; i < KID_COUNT; ++i) {
+        const char* a = kNames[i];
+        const char* b = name;
+        while (*a && *a == *b) ++a, ++b;
+        if (*a == 0 && *b == 0) return i;
+    }
+    return KID_NONE;
+}
+
+struct ProbeScope {
+    Probe* p;
+    hipStream_t st;
+    bool on;
+    ProbeScope(const Dev& d, int kid, hipStream_t s, double bytes = 0.0) : p(d.probe), st(s) {
+        on = p && p->target == kid && p->n < Probe::kMax;
+        if (on) {
+            (void)hipEventRecord(p->ev[2 * p->n], st);
+            p->bytes += bytes;
+        }
+    }
+    ~ProbeScope() {
+        if (on) {
+            (void)hipEventRecord(p->ev[2 * p->n + 1], st);
+            p->n += 1;
+        }
+    }
+};
+
+template <typename F>
+static void dispatch(const Dev& d, F&& f) {
+    auto ty = [&](auto dimc) {
+        switch (d.TY) {
+            case 4: f(dimc, std::integral_constant<int, 4>{}); break;
+            case 8: f(dimc, std::integral_constant<int, 8>{}); break;
+            case 32: f(dimc, std::integral_constant<int, 32>{}); break;
+            default: f(dimc, std::integral_constant<int, 16>{}); break;
+        }
+    };
+    if (d.dim == 3)
+        ty(std::integral_constant<int, 3>{});
+    else
+        ty(std::integral_constant<int, 2>{});
+}
+
+#define TILE_GRID dim3(d.ntiles), dim3(kBlock), 0, st
+#define CHUNK_GRID dim3(d.nchunks), dim3(kBlock), 0, st
+
+void launch_state_in(const Dev& d, double* const* eta_tab, double* const* zeta_tab, zd* X, hipStream_t st) {
+    ProbeScope ps(d, KID_OTHER, st);
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_state_in<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, eta_tab, zeta_tab, X, d.NT);
+    });
+}
+void launch_state_out(const Dev& d, const zd* X, double* const* eta_tab, double* const* zeta_tab, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_state_out<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, X, eta_tab, zeta_tab, d.NT);
+    });
+}
+void launch_planar_in(const Dev& d, double* const* tab, zd* half, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_planar<D(), TY(), true>), TILE_GRID, d.sys, d.tiles, nullptr, tab, half);
+    });
+}
+void launch_planar_out(const Dev& d, const zd* half, double* const* tab, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_planar<D(), TY(), false>), TILE_GRID, d.sys, d.tiles, nullptr, tab,
+                           const_cast<zd*>(half));
+    });
+}
+void launch_fill_zero(zd* p, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+}
+void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_rhs_base<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, Xeta, src_tab, BB);
+    });
+}
+void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_nonlinear<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half, BB, dnode, B,
+                           d.NT);
+    });
+}
+void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, zd* R, double* part,
+                     const int* mask, hipStream_t st) {
+    ProbeScope ps(d, KID_RESIDUAL, st, (double)d.NT * (6.0 * sizeof(zd) + 8.0 / d.J));
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_residual<D(), TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+                           d.ntiles);
+    });
+}
+template <typename T>
+void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st) {
+    // reads z (2 half vectors) and d (per instance), writes w (2 FP64 half vectors)
+    ProbeScope ps(d, KID_APPLY, st, (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) + 8.0 / d.J));
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_apply<D(), TY(), T>), TILE_GRID, d.sys, d.tiles, mask, Z, dnode, W, d.NT);
+    });
+}
+template void launch_apply<double>(const Dev&, const zd*, const double*, zd*, const int*, hipStream_t);
+template void launch_apply<float>(const Dev&, const zf*, const double*, zd*, const int*, hipStream_t);
+
+template <int DIM, int TY, typename T, int OP>
+static void cg_iterations(const Dev& d, cx<T>* xv, cx<T>* r, cx<T>* p0, cx<T>* p1, cx<T>* q, double* part, int n,
+                          const int* mask, hipStream_t st) {
+    cx<T>* P[2] = {p0, p1};
+    for (int it = 0; it < n; ++it) {
+        {
+            // algorithmic bytes: FIRST reads p, writes q; otherwise reads r, p and writes p, q
+            const double nb = (double)d.NT * sizeof(cx<T>) * (it == 0 ? 2.0 : 4.0);
+            ProbeScope ps(d, KID_PCG_SPMV, st, nb);
+            if (it == 0)
+                hipLaunchKernelGGL((k_cg_spmv<DIM, TY, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, r, p0, p0, q,
+                                   part, d.ntiles, it);
+            else
+                hipLaunchKernelGGL((k_cg_spmv<DIM, TY, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, r,
+                                   P[(it - 1) & 1], P[it & 1], q, part, d.ntiles, it);
+        }
+        const bool first = it == 0, last = it == n - 1;
+        // reads p (+x unless first, + r, q unless last), writes x (+ r unless last)
+        const double nb = (double)d.NT * sizeof(cx<T>) * (2.0 + (first ? 0.0 : 1.0) + (last ? 0.0 : 3.0));
+        ProbeScope ps(d, KID_PCG_UPDATE, st, nb);
+        cx<T>* pv = P[it & 1];
+        if (first && last)
+            hipLaunchKernelGGL((k_cg_update<DIM, TY, T, OP, true, true>), TILE_GRID, d.sys, d.tiles, mask, xv, r, pv,
+                               q, part, d.ntiles, it);
+        else if (first)
+            hipLaunchKernelGGL((k_cg_update<DIM, TY, T, OP, true, false>), TILE_GRID, d.sys, d.tiles, mask, xv, r,
+                               pv, q, part, d.ntiles, it);
+        else if (last)
+            hipLaunchKernelGGL((k_cg_update<DIM, TY, T, OP, false, true>), TILE_GRID, d.sys, d.tiles, mask, xv, r,
+                               pv, q, part, d.ntiles, it);
+        else
+            hipLaunchKernelGGL((k_cg_update<DIM, TY, T, OP, false, false>), TILE_GRID, d.sys, d.tiles, mask, xv, r,
+                               pv, q, part, d.ntiles, it);
+    }
+}
+
+template <typename T>
+void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
+                    cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        constexpr int DIM = D(), TYv = TY();
+        // step 1: beta1' ~ M^{-1} beta1
+        {
+            ProbeScope ps(d, KID_PCG_INIT, st);
+            hipLaunchKernelGGL((k_cg_init_copy<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, v, r, p0, part,
+                               d.ntiles);
+        }
+        cg_iterations<DIM, TYv, T, 0>(d, x1, r, p0, p1, q, part, mass_iters, mask, st);
+        // step 2: beta2' ~ L^{-1} (beta2 - kappa G beta1')
+        {
+            ProbeScope ps(d, KID_PCG_INIT, st);
+            hipLaunchKernelGGL((k_cg_init_g<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, v, x1, r, p0, part,
+                               d.ntiles, d.NT);
+        }
+        cg_iterations<DIM, TYv, T, 1>(d, x2, r, p0, p1, q, part, diff_iters, mask, st);
+        // step 3: chi2 ~ L^{-1} M beta2'  (written straight into the eta part of z)
+        {
+            ProbeScope ps(d, KID_PCG_INIT, st);
+            hipLaunchKernelGGL((k_cg_init_m<DIM, TYv, T, false>), TILE_GRID, d.sys, d.tiles, mask, x2, r, p0, part,
+                               d.ntiles);
+        }
+        cg_iterations<DIM, TYv, T, 1>(d, z + d.NT, r, p0, p1, q, part, diff_iters, mask, st);
+        // step 4
+        ProbeScope ps(d, KID_PC_FINAL, st);
+        hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);
+    });
+}
+template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, zd*, double*, int, int,
+                                     const int*, hipStream_t);
+template void launch_precond<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
+                                    const int*, hipStream_t);
+
+void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
+                       hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        constexpr int DIM = D(), TYv = TY();
+        hipLaunchKernelGGL((k_cg_init_m<DIM, TYv, double, true>), TILE_GRID, d.sys, d.tiles, nullptr, eta, r, p0,
+                           part, d.ntiles);
+        cg_iterations<DIM, TYv, double, 0>(d, zeta, r, p0, p1, q, part, iters, nullptr, st);
+    });
+}
+
+void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
+                   const int* mask, hipStream_t st) {
+    ProbeScope ps(d, KID_REDUCE, st);
+    const long long P = chunk_ranges ? d.nchunks : d.ntiles;
+    int gy = (nvals + 3) / 4;
+    if (gy > 16) gy = 16;
+    hipLaunchKernelGGL(k_reduce, dim3(d.S, gy), dim3(kBlock), 0, st, d.sys, mask, part, P, slot0, nvals, chunk_ranges,
+                       out, ld);
+}
+
+template <int NV, bool PROJECT>
+static void mdot_launch(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef,
+                        int coef_ld, double* part, const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL((k_mdot<NV, PROJECT>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, coef, coef_ld,
+                       part, d.nchunks, d.NT);
+}
+
+void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
+                 bool project, double* part, const int* mask, hipStream_t st) {
+    // reads w and nv basis vectors (full vectors of 2 NT complex doubles)
+    ProbeScope ps(d, KID_MDOT, st, (double)(nv + 1) * 2.0 * d.NT * sizeof(zd));
+    auto go = [&](auto nvc, auto pc) {
+        mdot_launch<decltype(nvc)::value, decltype(pc)::value>(d, V, vstride, nv, w, coef, coef_ld, part, mask, st);
+    };
+    auto sel = [&](auto pc) {
+        if (nv <= 4) go(std::integral_constant<int, 4>{}, pc);
+        else if (nv <= 8) go(std::integral_constant<int, 8>{}, pc);
+        else if (nv <= 16) go(std::integral_constant<int, 16>{}, pc);
+        else go(std::integral_constant<int, 32>{}, pc);
+    };
+    if (project)
+        sel(std::true_type{});
+    else
+        sel(std::false_type{});
+}
+
+void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
+                       const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st) {
+    ProbeScope ps(d, KID_PROJ_FINAL, st, (double)(nv + 2) * 2.0 * d.NT * sizeof(zd));
+    hipLaunchKernelGGL(k_proj_final, CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, hcoef, hstride, hinv, out,
+                       d.NT);
+}
+void launch_scale(const Dev& d, const zd* r, const double* inv_beta, zd* v0, const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale, CHUNK_GRID, d.sys, d.chunks, mask, r, inv_beta, v0, d.NT);
+}
+template <typename T>
+void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
+                    zd* X, const int* mask, hipStream_t st) {
+    ProbeScope ps(d, KID_XUPDATE, st);
+    hipLaunchKernelGGL((k_xupdate<T>), CHUNK_GRID, d.sys, d.chunks, mask, Z, zstride, kcount, y, ldy, X, d.NT);
+}
+template void launch_xupdate<double>(const Dev&, const zd*, long long, const int*, const double*, int, zd*,
+                                     const int*, hipStream_t);
+template void launch_xupdate<float>(const Dev&, const zf*, long long, const int*, const double*, int, zd*,
+                                    const int*, hipStream_t);
+
+void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st) {
+    ProbeScope ps(d, KID_SMALL, st);
+    hipLaunchKernelGGL(k_cycle_init, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, first ? 1 : 0);
+}
+void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
+    ProbeScope ps(d, KID_SMALL, st);
+    hipLaunchKernelGGL(k_arnoldi, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, k);
+}
+void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st) {
+    ProbeScope ps(d, KID_SMALL, st);
+    hipLaunchKernelGGL(k_solve_y, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S);
+}
+
+void launch_energy_parts(const Dev& d, const zd* eta, const zd* zeta, double* part, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_energy<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta, zeta, part, d.ntiles);
+    });
+}
+void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* const* grad_tab, double* part,
+                        hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_energy_grad<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta, zeta, grad_tab, part,
+                           d.ntiles);
+    });
+}
+void launch_adjoint_rhs(const Dev& d, double* const* lam_tab, zd* B, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_adjoint_rhs<D(), TY()>), TILE_GRID, d.sys, d.tiles, lam_tab, B, d.NT);
+    });
+}
+void launch_adjoint_out(const Dev& d, const zd* Y, const zd* eta_prev, double* const* eta_new_tab,
+                        double* const* lam_out_tab, double* part, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_adjoint_out<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, Y, eta_prev, eta_new_tab,
+                           lam_out_tab, part, d.ntiles, d.NT);
+    });
+}
+
+}  // namespace apfc
