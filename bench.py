@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--compare", action="store_true", help="also time the other precision")
+    ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--mass-iters", type=int, default=None)
+    ap.add_argument("--diff-iters", type=int, default=None)
     ap.add_argument("--probe", default="pcg_spmv", help="kernel timed with HIP events for the roofline")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -57,7 +61,11 @@ def run_gpu(args, precision, probe=None):
     from paper_1902_09761_amd import apfc, inputs
     wl, lat = make_workload(args.n)
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
-    p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=wl.rtol, precision=prec)
+    inner = apfc.APFC_INNER_CHEB if args.inner == "cheb" else apfc.APFC_INNER_PCG
+    mi = args.mass_iters or (4 if args.inner == "cheb" else 3)
+    di = args.diff_iters or (4 if args.inner == "cheb" else 5)
+    p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=wl.rtol, precision=prec, inner_kind=inner,
+                                 restart=args.restart, mass_iters=mi, diff_iters=di)
     m = apfc.make_mesh(2, wl.mesh.n, wl.mesh.length)
     s = apfc.Solver([m], lat, [p])
     if args.no_graphs:
@@ -130,8 +138,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"tri{args.n}_voronoi16", "mesh": f"{args.n}x{args.n} periodic Q1", "J": 3,
-                   "dt": 1.0, "rtol": 1e-8, "precision": args.precision, "restart": 30,
-                   "inner": "Jacobi-PCG 3/5/5", "tile_rows": res["tile_rows"],
+                   "dt": 1.0, "rtol": 1e-8, "precision": args.precision, "restart": args.restart,
+                   "inner": args.inner, "tile_rows": res["tile_rows"],
                    "graphs": not args.no_graphs},
         "fgmres_iters_per_step": float(np.mean(res["iters"])),
         "final_relres": res["relres"],

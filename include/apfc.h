@@ -164,6 +164,15 @@ int apfc_step_adjoint(apfc_ctx* ctx, const apfc_state* before, const apfc_state*
                       const double* const* lam_after, double* const* lam_before, double* dL_ddB,
                       void* stream, apfc_stats* stats);
 
+/* Apply one operator of the step to every instance: out_j = A_j in_j (which = APFC_OP_A, the
+ * block matrix of Eq. (11) linearised at lin[].eta with step dt) or out_j = P_j^{-1} in_j
+ * (which = APFC_OP_PINV, the block preconditioner of Eq. (12) by its four steps with the context's
+ * inner solver and precision).  in/out hold (zeta, eta) pairs as [J][2][N] device arrays; lin is
+ * read only for APFC_OP_A.  For testing and for callers that drive their own Krylov method. */
+enum { APFC_OP_A = 0, APFC_OP_PINV = 1 };
+int apfc_apply(apfc_ctx* ctx, int which, const apfc_state* lin, const apfc_state* in, apfc_state* out,
+               double dt, void* stream);
+
 /* Kernel timing probe: when enabled, every launch of the kernel named `name` inside
  * apfc_step is bracketed by HIP events on the launch stream; apfc_probe_read returns the
  * number of launches and their summed duration since the last reset. */

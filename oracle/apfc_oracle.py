@@ -433,17 +433,37 @@ class Oracle:
         return grad, ddB
 
     # -- preconditioner of Eq. (12), four steps (R3) ------------------------------------
+    def jacobi_bounds(self, j, dt):
+        """Exact extremes of the spectra of D^{-1} M and D^{-1} L (L = M/sqrt(dt) + sqrt(kappa_j) K)
+        on the periodic uniform mesh: the symbols are multilinear in cos(theta_d), so the extremes
+        are attained at theta_d in {0, pi} (whether or not those modes exist on the mesh)."""
+        g = self.grid
+        kap = self.kappa[j]
+        DM = self.M.diagonal()[0]
+        DL = (self.M / math.sqrt(dt) + math.sqrt(kap) * self.K).diagonal()[0]
+        lm, ll = [], []
+        for corner in itertools.product((0.0, math.pi), repeat=g.dim):
+            Mh, Kh, _ = symbols_at(g, np.zeros(g.dim), corner)
+            lm.append(Mh / DM)
+            ll.append((Mh / math.sqrt(dt) + math.sqrt(kap) * Kh) / DL)
+        return (min(lm), max(lm)), (min(ll), max(ll))
+
     def precond_apply(self, j, beta1, beta2, dt, inner=None, mass_iters=3, diff_iters=5):
         """x = P^{-1} b by the four steps; inner=None uses exact (direct) inner solves,
-        inner='pcg' uses fixed-count Jacobi-preconditioned CG from a zero start."""
+        inner='pcg' uses fixed-count Jacobi-preconditioned CG from a zero start, inner='cheb'
+        fixed-count Chebyshev iteration with the exact Jacobi spectral bounds."""
         kap = self.kappa[j]
         L = (self.M / math.sqrt(dt) + math.sqrt(kap) * self.K).tocsc()
         if inner is None:
             solve_M = lambda b: spla.spsolve(self.M.tocsc().astype(complex), b)
             solve_L = lambda b: spla.spsolve(L.astype(complex), b)
-        else:
+        elif inner == "pcg":
             solve_M = lambda b: jacobi_pcg(self.M, b, mass_iters)
             solve_L = lambda b: jacobi_pcg(L, b, diff_iters)
+        else:
+            bm, bl = self.jacobi_bounds(j, dt)
+            solve_M = lambda b: chebyshev(self.M, b, mass_iters, *bm)
+            solve_L = lambda b: chebyshev(L.tocsr(), b, diff_iters, *bl)
         b1p = solve_M(beta1)                                   # step 1
         b2p = solve_L(beta2 - kap * (self.G[j] @ b1p))         # step 2
         chi2 = solve_L(self.M @ b2p)                           # step 3
@@ -491,9 +511,50 @@ def jacobi_pcg(A, b, iters):
     return x
 
 
+def chebyshev(A, b, iters, lam_min, lam_max):
+    """Fixed-count Chebyshev iteration for A x = b preconditioned by D = diag(A), x0 = 0, for a
+    spectrum of D^{-1} A inside [lam_min, lam_max] (Chebyshev acceleration, Saad, Iterative Methods
+    for Sparse Linear Systems, Sec. 12.3): theta, delta = centre and half width, sigma = theta/delta,
+    d_0 = D^{-1} r_0 / theta, rho_0 = 1/sigma, then x += d; r -= A d; rho' = 1/(2 sigma - rho);
+    d = rho' rho d + (2 rho'/delta) D^{-1} r."""
+    Dinv = 1.0 / A.diagonal()
+    theta = 0.5 * (lam_max + lam_min)
+    delta = 0.5 * (lam_max - lam_min)
+    sigma = theta / delta
+    x = np.zeros_like(b)
+    r = b.copy()
+    d = Dinv * r / theta
+    rho = 1.0 / sigma
+    for k in range(iters):
+        x = x + d
+        if k == iters - 1:
+            break
+        r = r - A @ d
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (Dinv * r)
+        rho = rho_new
+    return x
+
+
 # ---------------------------------------------------------------------------------------
 # Closed-form Fourier symbols on the periodic uniform mesh (pins for the operators)
 # ---------------------------------------------------------------------------------------
+
+def symbols_at(grid: "Grid", kvec, theta):
+    """M^, K^ and G^ of the plane wave with phase increments theta_d = q_d h (see fourier_symbols)."""
+    h = grid.h
+    m = [(2.0 + math.cos(t)) / 3.0 for t in theta]
+    Mh = h ** grid.dim * np.prod(m)
+    Kh = 0.0
+    Th = 0.0
+    for d in range(grid.dim):
+        other = np.prod([m[e] for e in range(grid.dim) if e != d])
+        Kh += (2.0 - 2.0 * math.cos(theta[d])) * other
+        Th += 2.0 * kvec[d] * 1j * math.sin(theta[d]) * other
+    Kh *= h ** (grid.dim - 2)
+    Th *= h ** (grid.dim - 1)
+    return Mh, Kh, -Kh + 1j * Th
+
 
 def fourier_symbols(grid: Grid, kvec, mode):
     """Eigenvalues of M, K, G_j on the plane wave e^{i q.r} with q = 2 pi mode / L.

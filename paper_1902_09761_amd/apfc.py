@@ -26,10 +26,11 @@ APFC_ERR_NONFINITE = -4
 APFC_TRI2D, APFC_BCC3D, APFC_CUSTOM = 0, 1, 2
 APFC_FP64, APFC_MIXED = 0, 1
 APFC_INNER_PCG, APFC_INNER_CHEB = 0, 1
+APFC_OP_A, APFC_OP_PINV = 0, 1
 
 EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_create",
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
-           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_probe_enable", "apfc_probe_read",
+           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_probe_enable", "apfc_probe_read",
            "apfc_autotune", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
 
 
@@ -92,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "apfc_energy_grad": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_double), c_void_p]),
         "apfc_step_adjoint": (c_int, [c_void_p, P(apfc_state), P(apfc_state), c_double, P(c_void_p),
                                       P(c_void_p), P(c_double), c_void_p, P(apfc_stats)]),
+        "apfc_apply": (c_int, [c_void_p, c_int, P(apfc_state), P(apfc_state), P(apfc_state), c_double, c_void_p]),
         "apfc_probe_enable": (c_int, [c_void_p, c_char_p]),
         "apfc_probe_read": (c_int, [c_void_p, P(c_int), P(c_double), P(c_double)]),
         "apfc_autotune": (c_int, [c_void_p, c_void_p, P(c_int)]),
@@ -269,6 +271,12 @@ class Solver:
                                      _stream_handle(stream), byref(st))
         _check(rc)
         return list(ddb)
+
+    def apply(self, which: int, in_zetas, in_etas, out_zetas, out_etas, dt: float, lin_etas=None, stream=None):
+        """out = A in (which = APFC_OP_A, linearised at lin_etas) or P^{-1} in (APFC_OP_PINV)."""
+        lin = self._states(lin_etas) if lin_etas is not None else None
+        _check(lib().apfc_apply(self.ctx, which, lin, self._states(in_etas, in_zetas),
+                                self._states(out_etas, out_zetas), float(dt), _stream_handle(stream)))
 
     def autotune(self, stream=None) -> int:
         ty = c_int()

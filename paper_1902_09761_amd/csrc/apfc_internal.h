@@ -36,9 +36,16 @@ struct Sys {
     // time-step dependent scalars (refreshed when dt changes)
     double inv_dt, isq_dt, sq_kap, isq_kap;
     double diagM, diagK, diagL;
+    // Chebyshev parameters (centre theta, half width delta) of the Jacobi-scaled spectra of M and
+    // L = M/sqrt(dt) + sqrt(kappa) K on the periodic uniform mesh
+    double thM, deM, thL, deL;
 };
 
 struct Tile { int sys, x0, y0, z; };
+// Interior tile of the fused Chebyshev preconditioner kernels (region = interior + halo).
+struct CTile { int sys, x0, y0, z; };
+constexpr int kChebRX = 128;      // region width (x) of the fused preconditioner tiles
+constexpr int kChebRY = 32;       // region height (y)
 struct Chunk { int sys; int e0; };     // element offset inside the system's 2N-element full vector
 
 // Resonant products of the bulk energy with distinct amplitude indices: term value
@@ -58,7 +65,7 @@ enum Slot { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kBB = 4, kE0 = 5, kE1 = 6, k
 // Kernel identifiers for the timing probe.
 enum KernelId {
     KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
-    KID_RESIDUAL, KID_MDOT, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_COUNT
+    KID_RESIDUAL, KID_MDOT, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_COUNT
 };
 const char* kernel_name(int kid);
 int kernel_id(const char* name);
@@ -101,6 +108,8 @@ struct Krylov {
     double* relres;     // [S]
     int* solve_active;  // [S]
     int* iter_active;   // [S]
+    int* reorth;        // [S] second Gram-Schmidt pass needed in this iteration
+    int always_reorth;  // 1: classical Gram-Schmidt twice on every iteration
     int* kcount;        // [S]
     int* iters;         // [S]
     int* cycles;        // [S]
@@ -118,6 +127,7 @@ void launch_state_out(const Dev& d, const zd* X, double* const* eta_tab, double*
 void launch_planar_in(const Dev& d, double* const* tab, zd* half, hipStream_t st);
 void launch_planar_out(const Dev& d, const zd* half, double* const* tab, hipStream_t st);
 void launch_fill_zero(zd* p, long long n, hipStream_t st);
+void launch_widen(const zf* in, zd* out, long long n, hipStream_t st);
 
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st);
 void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st);
@@ -131,10 +141,17 @@ template <typename T>
 void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
+template <typename T>
+void launch_precond_cheb(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
+                         cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
 void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 bool project, double* part, const int* mask, hipStream_t st);
+                 double* part, const int* mask, hipStream_t st);
+template <typename T>
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const zd* V, long long vstride, int nv,
+                      double* part, const int* mask, hipStream_t st);
 void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
                        const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st);
 void launch_scale(const Dev& d, const zd* r, const double* inv_beta, zd* v0, const int* mask, hipStream_t st);
@@ -144,6 +161,7 @@ void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* 
 
 void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st);
 void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st);
+void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,

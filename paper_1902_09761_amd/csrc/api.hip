@@ -123,6 +123,8 @@ struct apfc_ctx {
     std::vector<Sys> sys;
     std::vector<Tile> tiles;
     std::vector<Chunk> chunks;
+    std::vector<CTile> ctiles;
+    CTile* d_ctiles = nullptr;
     long long NT = 0, NI = 0;
     int TY = 16;
     int max_tiles = 0;
@@ -143,6 +145,7 @@ struct apfc_ctx {
     double* dnode = nullptr;
     double* tpart = nullptr;
     double* cpart = nullptr;
+    double* apart = nullptr;
     Krylov kr{};
     int m = 30;
 
@@ -192,6 +195,35 @@ void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
     }
 }
 
+// Extremes of the Jacobi-scaled symbols of M and L = M/sqrt(dt) + sqrt(kappa) K on the periodic
+// uniform mesh.  With c_d = cos(theta_d): M^ = h^dim prod_d (2 + c_d)/3 and
+// K^ = h^(dim-2) sum_d (2 - 2 c_d) prod_{e != d} (2 + c_e)/3 are multilinear in (c_1..c_dim), so the
+// extremes over [-1, 1]^dim sit at the corners.
+void cheb_bounds(const Sys& y, double& thM, double& deM, double& thL, double& deL) {
+    double mnM = 1e300, mxM = -1e300, mnL = 1e300, mxL = -1e300;
+    for (int corner = 0; corner < (1 << y.dim); ++corner) {
+        double cc[3];
+        for (int d = 0; d < y.dim; ++d) cc[d] = (corner >> d) & 1 ? -1.0 : 1.0;
+        double Mh = std::pow(y.h, y.dim), Kh = 0.0;
+        for (int d = 0; d < y.dim; ++d) Mh *= (2.0 + cc[d]) / 3.0;
+        for (int d = 0; d < y.dim; ++d) {
+            double t = (2.0 - 2.0 * cc[d]) * std::pow(y.h, y.dim - 2);
+            for (int e = 0; e < y.dim; ++e)
+                if (e != d) t *= (2.0 + cc[e]) / 3.0;
+            Kh += t;
+        }
+        const double lm = Mh / y.diagM, ll = (Mh * y.isq_dt + y.sq_kap * Kh) / y.diagL;
+        mnM = std::min(mnM, lm);
+        mxM = std::max(mxM, lm);
+        mnL = std::min(mnL, ll);
+        mxL = std::max(mxL, ll);
+    }
+    thM = 0.5 * (mxM + mnM);
+    deM = 0.5 * (mxM - mnM);
+    thL = 0.5 * (mxL + mnL);
+    deL = 0.5 * (mxL - mnL);
+}
+
 void set_dt_scalars(apfc_ctx& c, double dt) {
     for (auto& y : c.sys) {
         y.inv_dt = 1.0 / dt;
@@ -199,14 +231,31 @@ void set_dt_scalars(apfc_ctx& c, double dt) {
         y.sq_kap = std::sqrt(y.kappa);
         y.isq_kap = 1.0 / std::sqrt(y.kappa);
         y.diagL = y.diagM * y.isq_dt + y.sq_kap * y.diagK;
+        cheb_bounds(y, y.thM, y.deM, y.thL, y.deL);
     }
     c.dt = dt;
+}
+
+int cheb_halo(const apfc_params& p) { return std::max(p.mass_iters - 1, p.diff_iters); }
+
+void build_ctiles(apfc_ctx& c) {
+    c.ctiles.clear();
+    const int H = cheb_halo(c.solver);
+    const int IX = kChebRX - 2 * H, IY = kChebRY - 2 * H;
+    for (int s = 0; s < c.S; ++s) {
+        const Sys& y = c.sys[s];
+        for (int z = 0; z < y.nz; ++z)
+            for (int y0 = 0; y0 < y.ny; y0 += IY)
+                for (int x0 = 0; x0 < y.nx; x0 += IX) c.ctiles.push_back(CTile{s, x0, y0, z});
+    }
 }
 
 int upload_tables(apfc_ctx& c) {
     HIPCHK(hipMemcpy(c.d_sys, c.sys.data(), sizeof(Sys) * c.S, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c.d_tiles, c.tiles.data(), sizeof(Tile) * c.tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c.d_chunks, c.chunks.data(), sizeof(Chunk) * c.chunks.size(), hipMemcpyHostToDevice));
+    if (!c.ctiles.empty())
+        HIPCHK(hipMemcpy(c.d_ctiles, c.ctiles.data(), sizeof(CTile) * c.ctiles.size(), hipMemcpyHostToDevice));
     return APFC_OK;
 }
 
@@ -232,6 +281,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.d_sys = (Sys*)take(sizeof(Sys) * S);
     c.d_tiles = (Tile*)take(sizeof(Tile) * c.max_tiles);
     c.d_chunks = (Chunk*)take(sizeof(Chunk) * c.chunks.size());
+    c.d_ctiles = (CTile*)take(sizeof(CTile) * std::max<size_t>(1, c.ctiles.size()));
     c.d_tab = (double**)take(sizeof(double*) * 4 * c.count);
     c.X = (zd*)take(sizeof(zd) * 2 * NT);
     c.B = (zd*)take(sizeof(zd) * 2 * NT);
@@ -244,10 +294,12 @@ size_t carve(apfc_ctx& c, char* base) {
     c.dnode = (double*)take(sizeof(double) * c.NI);
     c.tpart = (double*)take(sizeof(double) * kSlots * c.max_tiles);
     c.cpart = (double*)take(sizeof(double) * (2 * kMaxRestart + 2) * c.chunks.size());
+    c.apart = (double*)take(sizeof(double) * (2 * kMaxRestart + 2) * c.max_tiles);
     Krylov& k = c.kr;
     k.m = m;
     k.nv1 = 2 * (m + 1);
     k.rtol = c.solver.rtol;
+    k.always_reorth = 0;
     k.H = (double*)take(sizeof(double) * S * m * 2 * (m + 1));
     k.cs = (double*)take(sizeof(double) * S * m);
     k.sn = (double*)take(sizeof(double) * S * 2 * m);
@@ -255,7 +307,7 @@ size_t carve(apfc_ctx& c, char* base) {
     k.y = (double*)take(sizeof(double) * S * 2 * m);
     k.hsum = (double*)take(sizeof(double) * S * 2 * (m + 1));
     k.hinv = (double*)take(sizeof(double) * S);
-    k.red1 = (double*)take(sizeof(double) * S * k.nv1);
+    k.red1 = (double*)take(sizeof(double) * S * (k.nv1 + 1));
     k.red2 = (double*)take(sizeof(double) * S * (k.nv1 + 1));
     k.redr = (double*)take(sizeof(double) * S * kSlots);
     k.bnorm = (double*)take(sizeof(double) * S);
@@ -264,6 +316,7 @@ size_t carve(apfc_ctx& c, char* base) {
     k.relres = (double*)take(sizeof(double) * S);
     k.solve_active = (int*)take(sizeof(int) * S);
     k.iter_active = (int*)take(sizeof(int) * S);
+    k.reorth = (int*)take(sizeof(int) * S);
     k.kcount = (int*)take(sizeof(int) * S);
     k.iters = (int*)take(sizeof(int) * S);
     k.cycles = (int*)take(sizeof(int) * S);
@@ -433,8 +486,14 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
         return rc;
     }
     if (params[0].inner_kind == APFC_INNER_CHEB) {
-        delete c;
-        return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB is not available in this build");
+        if (dim != 2) {
+            delete c;
+            return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB (fused 2D tiles) needs dim == 2");
+        }
+        if (cheb_halo(params[0]) > 12) {
+            delete c;
+            return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB needs mass_iters <= 13 and diff_iters <= 12");
+        }
     }
     c->S = count * c->J;
     long long off = 0, doff = 0;
@@ -488,6 +547,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
     c->TY = 16;
     build_tiles(*c, c->TY, c->tiles);
     set_dt_scalars(*c, 1.0);
+    if (params[0].inner_kind == APFC_INNER_CHEB) build_ctiles(*c);
     *out = c;
     return APFC_OK;
 }
@@ -577,14 +637,19 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     cx<T>* Z = (cx<T>*)c->Z;
     cx<T>** pc = (cx<T>**)c->pc;
     const int* act = kr.iter_active;
-    launch_precond<T>(d, c->V + k * vs, Z + k * vs, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                      c->solver.mass_iters, c->solver.diff_iters, act, st);
-    launch_apply<T>(d, Z + k * vs, c->dnode, c->W, act, st);
+    if (c->solver.inner_kind == APFC_INNER_CHEB)
+        launch_precond_cheb<T>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V + k * vs,
+                               Z + k * vs, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, act, st);
+    else
+        launch_precond<T>(d, c->V + k * vs, Z + k * vs, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                          c->solver.mass_iters, c->solver.diff_iters, act, st);
     const int nv = k + 1;
-    launch_mdot(d, c->V, vs, nv, c->W, nullptr, kr.nv1, false, c->cpart, act, st);
-    launch_reduce(d, c->cpart, 0, 2 * nv, true, kr.red1, kr.nv1, act, st);
-    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1, true, c->cpart, act, st);
-    launch_reduce(d, c->cpart, 0, 2 * nv + 1, true, kr.red2, kr.nv1 + 1, act, st);
+    // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
+    launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
+    launch_reduce(d, c->apart, 0, 2 * nv + 1, false, kr.red1, kr.nv1 + 1, act, st);
+    launch_reorth_flag(d, kr, k, st);
+    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, st);
+    launch_reduce(d, c->cpart, 0, 2 * nv + 1, true, kr.red2, kr.nv1 + 1, kr.reorth, st);
     launch_arnoldi(d, kr, k, st);
     launch_proj_final(d, c->V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), c->V + (k + 1) * vs, act, st);
 }
@@ -850,6 +915,69 @@ int apfc_step_adjoint(apfc_ctx* c, const apfc_state* before, const apfc_state* a
     return fill_stats(c, st, stats, ms);
 }
 
+int apfc_apply(apfc_ctx* c, int which, const apfc_state* lin, const apfc_state* in, apfc_state* out, double dt,
+               void* stream) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (which != APFC_OP_A && which != APFC_OP_PINV) return fail(APFC_ERR_INVALID, "apfc_apply: unknown operator");
+    if (int rc = check_states(c, in, true); rc) return rc;
+    if (int rc = check_states(c, out, true); rc) return rc;
+    if (which == APFC_OP_A)
+        if (int rc = check_states(c, lin, false); rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = refresh_dt(c, dt, st); rc) return rc;
+    std::vector<const void*> t[4];
+    for (int b = 0; b < c->count; ++b) {
+        t[0].push_back(in[b].eta);
+        t[1].push_back(in[b].zeta);
+        t[2].push_back(out[b].eta);
+        t[3].push_back(out[b].zeta);
+    }
+    if (int rc = upload_ptrs(c, t, 4, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    if (which == APFC_OP_A) {
+        std::vector<const void*> tl[1];
+        for (int b = 0; b < c->count; ++b) tl[0].push_back(lin[b].eta);
+        launch_state_in(d, tab(c, 0), tab(c, 1), c->W, st);          // W = input (zeta, eta)
+        HIPCHK(hipStreamSynchronize(st));
+        if (int rc = upload_ptrs(c, tl, 1, st); rc) return rc;
+        launch_planar_in(d, tab(c, 0), c->BB, st);                    // linearisation eta
+        launch_nonlinear(d, c->BB, c->BB, c->dnode, c->B, st);
+        HIPCHK(hipStreamSynchronize(st));
+        if (int rc = upload_ptrs(c, t, 4, st); rc) return rc;
+        launch_apply<double>(d, c->W, c->dnode, c->R, nullptr, st);
+        launch_state_out(d, c->R, tab(c, 2), tab(c, 3), st);
+    } else {
+        launch_state_in(d, tab(c, 0), tab(c, 1), c->V, st);
+        const long long vs = c->vstride();
+        (void)vs;
+        if (c->mixed) {
+            zf** pc = (zf**)c->pc;
+            if (c->solver.inner_kind == APFC_INNER_CHEB)
+                launch_precond_cheb<float>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V,
+                                           (zf*)c->Z, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters,
+                                           nullptr, st);
+            else
+                launch_precond<float>(d, c->V, (zf*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                                      c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+            launch_widen((const zf*)c->Z, c->R, 2 * c->NT, st);
+        } else {
+            zd** pc = (zd**)c->pc;
+            if (c->solver.inner_kind == APFC_INNER_CHEB)
+                launch_precond_cheb<double>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V,
+                                            c->R, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters,
+                                            nullptr, st);
+            else
+                launch_precond<double>(d, c->V, c->R, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
+                                       c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+        }
+        launch_state_out(d, c->R, tab(c, 2), tab(c, 3), st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return APFC_OK;
+}
+
 int apfc_set_graphs(apfc_ctx* c, int enable) {
     if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
     c->use_graphs = enable != 0;
@@ -904,19 +1032,7 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
         if (int rc = upload_tables(*c); rc) return rc;
         Dev d = c->dev();
         d.probe = nullptr;
-        auto body = [&]() {
-            if (c->mixed) {
-                zf** pc = (zf**)c->pc;
-                launch_precond<float>(d, c->V, (zf*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                                      c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
-                launch_apply<float>(d, (zf*)c->Z, c->dnode, c->W, nullptr, st);
-            } else {
-                zd** pc = (zd**)c->pc;
-                launch_precond<double>(d, c->V, (zd*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                                       c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
-                launch_apply<double>(d, (zd*)c->Z, c->dnode, c->W, nullptr, st);
-            }
-        };
+        auto body = [&]() { run_iteration(c, d, 0, st); };
         body();
         HIPCHK(hipEventRecord(e0, st));
         for (int r = 0; r < 3; ++r) body();

@@ -420,6 +420,45 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* ti
     }
 }
 
+// W = A Z at every node of the tile and, fused, the first Gram-Schmidt pass: per-tile partials of
+// V_i^H w (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).
+template <int DIM, int TY, typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_apply_dot(const Sys* sys, const Tile* tiles, const int* mask,
+                                                     const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                     long long vstride, int nv, double* part, long long NT,
+                                                     int ntiles) {
+    __shared__ double lds[4 * (2 * NV + 1)];
+    TILE_PROLOGUE();
+    double acc[2 * NV + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        const long long il = s.off + nb_index<DIM>(n, 1, 1, 1);
+        zd y1, y2;
+        apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + nb_index<DIM>(n, 1, 1, 1)], y1, y2);
+        W[il] = y1;
+        W[NT + il] = y2;
+        acc[2 * NV] += abs2(y1) + abs2(y2);
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                const zd a = cdot(V[l * vstride + il], y1), b = cdot(V[l * vstride + NT + il], y2);
+                acc[2 * l] += a.x + b.x;
+                acc[2 * l + 1] += a.y + b.y;
+            }
+    }
+    block_sum<2 * NV + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < nv; ++l) {
+            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
+            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
+        }
+        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Block preconditioner (Eq. (12), four steps) with fixed-count Jacobi-PCG inner solves.
 // Operator of an inner solve: OP = 0 -> M (diag diagM), OP = 1 -> L = M/sqrt(dt) + sqrt(kappa) K.
@@ -588,6 +627,134 @@ __global__ __launch_bounds__(kBlock) void k_pc_final(const Sys* sys, const Tile*
 }
 
 // ------------------------------------------------------------------------------------------
+// Block preconditioner with Chebyshev-Jacobi inner solves, fused per step (2D).
+//
+// A workgroup owns a region of kChebRX x kChebRY nodes = an interior tile plus `halo` layers
+// (periodic wrap).  Every stencil application inside the region is evaluated from LDS and is
+// exact one layer further in than the previous one, so after `halo` applications the interior
+// holds the same values an unfused sweep over the whole mesh would give.  Three kernels per
+// preconditioner application:
+//   STAGE 0: x1   = Cheb_M^{sM}(beta1)                         (step 1)
+//   STAGE 1: x2   = Cheb_L^{sL}(beta2 - kappa G x1)             (step 2)
+//   STAGE 2: chi2 = Cheb_L^{sL}(M x2);  chi1 = x1 - (x2 - chi2/sqrt(dt))/sqrt(kappa)   (steps 3, 4)
+// Chebyshev iteration for D^{-1} A with spectrum in [theta - delta, theta + delta], x0 = 0
+// (three-term recurrence on the correction d):
+//   d0 = r0/(theta D), rho0 = delta/theta; x_{k+1} = x_k + d_k;
+//   r_{k+1} = r_k - A d_k; rho_{k+1} = 1/(2 theta/delta - rho_k);
+//   d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^{-1} r_{k+1}.
+// The spectral bounds are exact for the constant-coefficient operators (symbol extremes at the
+// corners cos(theta_d) = +-1), so the iteration needs no inner products.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int wrapi(int g, int n) {
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+template <typename T, bool WK, bool WT>
+__device__ __forceinline__ void lds_stencil(const cx<T>* buf, int px, int py, int RX, int RY, T h, T k0, T k1,
+                                            cx<T>& Mu, cx<T>& Ku, cx<T>& Tu) {
+    const int xm = px > 0 ? px - 1 : px, xp = px < RX - 1 ? px + 1 : px;
+    const int ym = py > 0 ? py - 1 : py, yp = py < RY - 1 ? py + 1 : py;
+    const int xs[3] = {xm, px, xp};
+    const int ys[3] = {ym, py, yp};
+    stencil<2, WK, WT, T>([&](int a, int b, int c) { return buf[ys[b] * RX + xs[a]]; }, h, k0, k1, T(0), Mu, Ku, Tu);
+}
+
+template <typename T, int STAGE, int NTH>
+__global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
+                                               cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
+                                               long long NT) {
+    constexpr int RX = kChebRX, RY = kChebRY, RP = RX * RY, NP = RP / NTH;
+    static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
+    constexpr int ROWS = NTH / RX;                 // region rows covered by one pass of the workgroup
+    __shared__ cx<T> buf[RP];
+    const CTile tile = tiles[blockIdx.x];
+    if (mask && !mask[tile.sys]) return;
+    const Sys s = sys[tile.sys];
+    const int IX = RX - 2 * halo, IY = RY - 2 * halo;
+    const T h = T(s.h);
+    // thread -> region column px (fixed) and rows py = ty + ROWS * i
+    const int px = threadIdx.x % RX, ty = threadIdx.x / RX;
+    const long long gx = wrapi(tile.x0 - halo + px, s.nx);
+    auto gidx = [&](int i) {
+        const int py = ty + ROWS * i;
+        return s.off + (long long)wrapi(tile.y0 - halo + py, s.ny) * s.nx + gx;
+    };
+    cx<T> X[NP], R[NP], Dd[NP];
+    // right-hand side of the inner solve
+    if constexpr (STAGE == 0) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) R[i] = ld<T>(v, gidx(i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) buf[threadIdx.x + NTH * i] = STAGE == 1 ? x1[gidx(i)] : x2[gidx(i)];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int py = ty + ROWS * i;
+            cx<T> Mu, Ku, Tu;
+            if constexpr (STAGE == 1) {
+                lds_stencil<T, true, true>(buf, px, py, RX, RY, h, T(s.kv[0]), T(s.kv[1]), Mu, Ku, Tu);
+                R[i] = ld<T>(v, NT + gidx(i)) - T(s.kappa) * gop(Ku, Tu);
+            } else {
+                lds_stencil<T, false, false>(buf, px, py, RX, RY, h, T(0), T(0), Mu, Ku, Tu);
+                R[i] = Mu;
+            }
+        }
+    }
+    // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
+    constexpr bool isM = STAGE == 0;
+    const int its = isM ? sM : sL;
+    const T th = T(isM ? s.thM : s.thL), de = T(isM ? s.deM : s.deL);
+    const T iD = T(1.0 / (isM ? s.diagM : s.diagL));
+    const T cM = isM ? T(1) : T(s.isq_dt), cK = isM ? T(0) : T(s.sq_kap);
+    const T sig = th / de;
+    T rho = T(1) / sig;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        Dd[i] = (iD / th) * R[i];
+        X[i] = Dd[i];
+    }
+    for (int k = 1; k < its; ++k) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) buf[threadIdx.x + NTH * i] = Dd[i];
+        __syncthreads();
+        const T rn = T(1) / (T(2) * sig - rho);
+        const T c1 = rn * rho, c2 = T(2) * rn / de * iD;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int py = ty + ROWS * i;
+            cx<T> Mu, Ku, Tu;
+            lds_stencil<T, !isM, false>(buf, px, py, RX, RY, h, T(0), T(0), Mu, Ku, Tu);
+            const cx<T> q = isM ? Mu : cM * Mu + cK * Ku;
+            R[i] = R[i] - q;
+            Dd[i] = c1 * Dd[i] + c2 * R[i];
+            X[i] = X[i] + Dd[i];
+        }
+        rho = rn;
+    }
+    // interior output (no wrap: each mesh node is written by exactly one tile)
+    const int ix = px - halo;
+    if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int iy = ty + ROWS * i - halo;
+        if (iy < 0 || iy >= IY || tile.y0 + iy >= s.ny) continue;
+        const long long g = gidx(i);
+        if constexpr (STAGE == 0) {
+            x1[g] = X[i];
+        } else if constexpr (STAGE == 1) {
+            x2[g] = X[i];
+        } else {
+            const cx<T> chi2 = X[i];
+            z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
+            z[NT + g] = chi2;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Krylov kernels over chunks of full vectors (element e < N: zeta part, else eta part)
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long long e) {
@@ -604,10 +771,10 @@ __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long
     _Pragma("unroll") for (int u_ = 0; u_ < kChunk / kBlock; ++u_)                    \
         if (const long long e = (long long)ch.e0 + threadIdx.x + (long long)u_ * kBlock; e < twoN)
 
-// partials of V_i^H w' (i < nv) with w' = w - sum_l coef_l V_l when PROJECT, plus |w'|^2.
-// Each thread keeps its 8 elements of w' in registers; V is streamed once for the projection
-// and once more for the dots (the second pass mostly hits the caches).
-template <int NV, bool PROJECT>
+// Partials of V_i^H w' (i < nv) and |w'|^2 with w' = w - sum_l coef_l V_l (the second, re-
+// orthogonalising Gram-Schmidt pass).  Each thread walks its elements one at a time and keeps the
+// nv basis values of the element in registers, so V is read once.
+template <int NV>
 __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const zd* V,
                                                 long long vstride, int nv, const zd* w, const double* coef,
                                                 int coef_ld, double* part, int nchunks, long long NT) {
@@ -615,50 +782,31 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
     __shared__ double lds[4 * (2 * NV + 1)];
     __shared__ zd cf[NV];
     CHUNK_PROLOGUE();
-    if (PROJECT) {
-        if (threadIdx.x < NV)
-            cf[threadIdx.x] = (int)threadIdx.x < nv ? zd{coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x],
-                                                        coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x + 1]}
-                                                    : zd{0.0, 0.0};
-        __syncthreads();
-    }
-    zd wv[EPT];
-    long long gi[EPT];
-    bool ok[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const long long e = (long long)ch.e0 + threadIdx.x + (long long)u * kBlock;
-        ok[u] = e < twoN;
-        gi[u] = ok[u] ? elem_index(s, NT, e) : 0;
-        wv[u] = ok[u] ? w[gi[u]] : zd{0.0, 0.0};
-    }
-    if constexpr (PROJECT) {
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (l < nv) {
-                const zd c = cf[l];
-#pragma unroll
-                for (int u = 0; u < EPT; ++u)
-                    if (ok[u]) wv[u] = wv[u] - cmul(c, V[l * vstride + gi[u]]);
-            }
-    }
+    if (threadIdx.x < NV)
+        cf[threadIdx.x] = (int)threadIdx.x < nv ? zd{coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x],
+                                                    coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x + 1]}
+                                                : zd{0.0, 0.0};
+    __syncthreads();
     double acc[2 * NV + 1];
 #pragma unroll
     for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+    for (int u = 0; u < EPT; ++u) {
+        const long long e = (long long)ch.e0 + threadIdx.x + (long long)u * kBlock;
+        if (e >= twoN) break;
+        const long long gi = elem_index(s, NT, e);
+        zd vv[NV];
 #pragma unroll
-    for (int l = 0; l < NV; ++l)
-        if (l < nv) {
+        for (int l = 0; l < NV; ++l) vv[l] = l < nv ? V[l * vstride + gi] : zd{0.0, 0.0};
+        zd wv = w[gi];
 #pragma unroll
-            for (int u = 0; u < EPT; ++u)
-                if (ok[u]) {
-                    const zd t = cdot(V[l * vstride + gi[u]], wv[u]);
-                    acc[2 * l] += t.x;
-                    acc[2 * l + 1] += t.y;
-                }
+        for (int l = 0; l < NV; ++l) wv = wv - cmul(cf[l], vv[l]);
+#pragma unroll
+        for (int l = 0; l < NV; ++l) {
+            const zd t = cdot(vv[l], wv);
+            acc[2 * l] += t.x;
+            acc[2 * l + 1] += t.y;
         }
-    if constexpr (PROJECT) {
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) acc[2 * NV] += abs2(wv[u]);
+        acc[2 * NV] += abs2(wv);
     }
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
@@ -666,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
             part[(2 * l) * (long long)nchunks + blockIdx.x] = acc[2 * l];
             part[(2 * l + 1) * (long long)nchunks + blockIdx.x] = acc[2 * l + 1];
         }
-        if (PROJECT) part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
+        part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
     }
 }
 
@@ -771,11 +919,34 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
     for (int i = 1; i <= kr.m; ++i) g[2 * i] = g[2 * i + 1] = 0.0;
 }
 
+// After the first pass: re-orthogonalise only if it removed more than half of |w|^2 (the
+// "twice is enough" test); otherwise the second pass is skipped and its results set to
+// h2 = 0, |w'|^2 = |w|^2 - |h1|^2.
+__global__ void k_reorth_flag(Krylov kr, int S, int k) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (!kr.iter_active[s]) {
+        kr.reorth[s] = 0;
+        return;
+    }
+    const double* h1 = kr.red1 + (long long)s * (kr.nv1 + 1);
+    double hn = 0.0;
+    for (int i = 0; i <= k; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
+    const double wn2 = h1[2 * (k + 1)];
+    const int need = (kr.always_reorth || wn2 - hn < 0.5 * wn2) ? 1 : 0;
+    kr.reorth[s] = need;
+    if (!need) {
+        double* h2 = kr.red2 + (long long)s * (kr.nv1 + 1);
+        for (int i = 0; i <= k; ++i) h2[2 * i] = h2[2 * i + 1] = 0.0;
+        h2[2 * (k + 1)] = wn2 - hn;
+    }
+}
+
 __global__ void k_arnoldi(Krylov kr, int S, int k) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S || !kr.iter_active[s]) return;
     const int m = kr.m, nv1 = kr.nv1;
-    const double* h1 = kr.red1 + (long long)s * nv1;
+    const double* h1 = kr.red1 + (long long)s * (nv1 + 1);
     const double* h2 = kr.red2 + (long long)s * (nv1 + 1);
     double* col = kr.H + ((long long)s * m + k) * 2 * (m + 1);
     double* hs = kr.hsum + (long long)s * 2 * (m + 1);
@@ -1038,8 +1209,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Ti
 // ------------------------------------------------------------------------------------------
 // launch plumbing
 // ------------------------------------------------------------------------------------------
-static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init",   "pc_final", "apply",  "residual",
-                                        "mdot",     "proj_final", "xupdate",    "reduce",   "small",  "other"};
+static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init", "pc_final", "apply", "residual",
+                                        "mdot",     "proj_final", "xupdate",  "reduce",   "small", "other",
+                                        "cheb"};
 const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : "none"; }
 int kernel_id(const char* name) {
     if (!name) return KID_NONE;
@@ -1117,6 +1289,16 @@ void launch_fill_zero(zd* p, long long n, hipStream_t st) {
     long long blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+}
+__global__ __launch_bounds__(kBlock) void k_widen(const zf* in, zd* out, long long n) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = zd{(double)in[i].x, (double)in[i].y};
+}
+void launch_widen(const zf* in, zd* out, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks), dim3(kBlock), 0, st, in, out, n);
 }
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
@@ -1220,6 +1402,31 @@ template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, 
 template void launch_precond<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
                                     const int*, hipStream_t);
 
+template <typename T>
+void launch_precond_cheb(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
+                         cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+    constexpr int NTH = 512;
+    const dim3 g(nctiles), b(NTH);
+    const double pts = (double)d.NT;
+    {
+        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + sizeof(cx<T>)));
+        hipLaunchKernelGGL((k_cheb2d<T, 0, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+                           diff_iters, halo, d.NT);
+    }
+    {
+        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + 2 * sizeof(cx<T>)));
+        hipLaunchKernelGGL((k_cheb2d<T, 1, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+                           diff_iters, halo, d.NT);
+    }
+    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>));
+    hipLaunchKernelGGL((k_cheb2d<T, 2, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+                       diff_iters, halo, d.NT);
+}
+template void launch_precond_cheb<double>(const Dev&, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
+                                          const int*, hipStream_t);
+template void launch_precond_cheb<float>(const Dev&, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
+                                         const int*, hipStream_t);
+
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
                        hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
@@ -1240,30 +1447,45 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
                        out, ld);
 }
 
-template <int NV, bool PROJECT>
-static void mdot_launch(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef,
-                        int coef_ld, double* part, const int* mask, hipStream_t st) {
-    hipLaunchKernelGGL((k_mdot<NV, PROJECT>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, coef, coef_ld,
-                       part, d.nchunks, d.NT);
-}
-
 void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 bool project, double* part, const int* mask, hipStream_t st) {
+                 double* part, const int* mask, hipStream_t st) {
     // reads w and nv basis vectors (full vectors of 2 NT complex doubles)
     ProbeScope ps(d, KID_MDOT, st, (double)(nv + 1) * 2.0 * d.NT * sizeof(zd));
-    auto go = [&](auto nvc, auto pc) {
-        mdot_launch<decltype(nvc)::value, decltype(pc)::value>(d, V, vstride, nv, w, coef, coef_ld, part, mask, st);
+    auto go = [&](auto nvc) {
+        hipLaunchKernelGGL((k_mdot<decltype(nvc)::value>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
+                           coef, coef_ld, part, d.nchunks, d.NT);
     };
-    auto sel = [&](auto pc) {
-        if (nv <= 4) go(std::integral_constant<int, 4>{}, pc);
-        else if (nv <= 8) go(std::integral_constant<int, 8>{}, pc);
-        else if (nv <= 16) go(std::integral_constant<int, 16>{}, pc);
-        else go(std::integral_constant<int, 32>{}, pc);
-    };
-    if (project)
-        sel(std::true_type{});
-    else
-        sel(std::false_type{});
+    if (nv <= 4) go(std::integral_constant<int, 4>{});
+    else if (nv <= 8) go(std::integral_constant<int, 8>{});
+    else if (nv <= 16) go(std::integral_constant<int, 16>{});
+    else go(std::integral_constant<int, 32>{});
+}
+
+template <typename T>
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const zd* V, long long vstride, int nv,
+                      double* part, const int* mask, hipStream_t st) {
+    // reads z, d, nv basis vectors; writes w
+    ProbeScope ps(d, KID_APPLY, st,
+                  (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) * (1 + nv) + 8.0 / d.J));
+    dispatch(d, [&](auto D, auto TY) {
+        auto go = [&](auto nvc) {
+            hipLaunchKernelGGL((k_apply_dot<D(), TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
+                               dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+        };
+        if (nv <= 4) go(std::integral_constant<int, 4>{});
+        else if (nv <= 8) go(std::integral_constant<int, 8>{});
+        else if (nv <= 16) go(std::integral_constant<int, 16>{});
+        else go(std::integral_constant<int, 32>{});
+    });
+}
+template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*, const zd*, long long, int, double*,
+                                       const int*, hipStream_t);
+template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zd*, long long, int, double*,
+                                      const int*, hipStream_t);
+
+void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
+    ProbeScope ps(d, KID_SMALL, st);
+    hipLaunchKernelGGL(k_reorth_flag, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, k);
 }
 
 void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,

@@ -30,15 +30,17 @@ def run_gpu(solver, etas, dt, steps, zetas=None):
     return [from_dev(e) for e in et], [from_dev(z) for z in zt], infos
 
 
-@pytest.mark.parametrize("precision", [apfc.APFC_FP64, apfc.APFC_MIXED])
-def test_grain_64_matches_oracle(precision):
+@pytest.mark.parametrize("precision,inner", [(apfc.APFC_FP64, apfc.APFC_INNER_PCG), (apfc.APFC_MIXED, apfc.APFC_INNER_PCG),
+                                             (apfc.APFC_FP64, apfc.APFC_INNER_CHEB), (apfc.APFC_MIXED, apfc.APFC_INNER_CHEB)])
+def test_grain_64_matches_oracle(precision, inner):
     """64^2 triangular grain (radius 6 spacings, 5 degrees), dt = 1, 10 steps."""
     wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
     o = oracle_for(wl.mesh, tri_k(), wl.dB)
     ref = wl.eta0
     for _ in range(wl.steps):
         _, ref = o.step(ref, wl.dt)
-    s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB], rtol=1e-12, precision=precision)
+    kw = {"mass_iters": 4, "diff_iters": 4} if inner == apfc.APFC_INNER_CHEB else {}
+    s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB], rtol=1e-12, precision=precision, inner_kind=inner, **kw)
     got, _, infos = run_gpu(s, [wl.eta0], wl.dt, wl.steps)
     err = rel_l2(got[0], ref)
     print("rel-L2", err, "iters", [i["max_iters"] for i in infos])
@@ -216,3 +218,52 @@ def test_nonfinite_input_is_rejected():
         s.step([et], [zt], 1.0)
     assert ei.value.status == apfc.APFC_ERR_NONFINITE
     assert torch.equal(torch.nan_to_num(et, nan=7.0), torch.nan_to_num(before, nan=7.0))
+
+
+def _rand_pair(J, N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=(J, N)) + 1j * rng.normal(size=(J, N)),
+            rng.normal(size=(J, N)) + 1j * rng.normal(size=(J, N)))
+
+
+def test_operator_A_matches_oracle():
+    """apfc_apply(APFC_OP_A) = the oracle's assembled block matrix times the same vector."""
+    mesh = inputs.Mesh(2, (40, 28, 1), (40 * H_TRI, 28 * H_TRI, 1.0))
+    lin = inputs.single_grain(mesh, tri_k(), phi_of(tri_k())(0.02), math.radians(7.0), 8 * H_TRI, seed=3)
+    zin, ein = _rand_pair(3, mesh.N, 21)
+    o = oracle_for(mesh, tri_k(), 0.02)
+    d, _ = o.nodal(lin)
+    s = solver_for([mesh], apfc.APFC_TRI2D, [0.02])
+    zo, eo = torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda"), torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda")
+    s.apply(apfc.APFC_OP_A, [to_dev(zin)], [to_dev(ein)], [zo], [eo], 0.7, lin_etas=[to_dev(lin)])
+    gz, ge = from_dev(zo), from_dev(eo)
+    for j in range(3):
+        ref = o.block_matrix(j, d, 0.7) @ np.concatenate([zin[j], ein[j]])
+        got = np.concatenate([gz[j], ge[j]])
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("inner,precision,tol", [(apfc.APFC_INNER_PCG, apfc.APFC_FP64, 1e-12),
+                                                 (apfc.APFC_INNER_PCG, apfc.APFC_MIXED, 2e-5),
+                                                 (apfc.APFC_INNER_CHEB, apfc.APFC_FP64, 1e-12),
+                                                 (apfc.APFC_INNER_CHEB, apfc.APFC_MIXED, 2e-5)])
+@pytest.mark.parametrize("n", [(40, 28), (256, 192)])
+def test_preconditioner_matches_oracle(inner, precision, tol, n):
+    """P^{-1} by its four steps on the GPU vs the oracle's four steps with the same inner solver
+    (Jacobi-PCG 3/5 or Chebyshev 4/4), element by element."""
+    nx, ny = n
+    mesh = inputs.Mesh(2, (nx, ny, 1), (nx * H_TRI, ny * H_TRI, 1.0))
+    zin, ein = _rand_pair(3, mesh.N, 22)
+    o = oracle_for(mesh, tri_k(), 0.02)
+    its = (4, 4) if inner == apfc.APFC_INNER_CHEB else (3, 5)
+    s = solver_for([mesh], apfc.APFC_TRI2D, [0.02], inner_kind=inner, precision=precision,
+                   mass_iters=its[0], diff_iters=its[1])
+    zo, eo = torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda"), torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda")
+    s.apply(apfc.APFC_OP_PINV, [to_dev(zin)], [to_dev(ein)], [zo], [eo], 0.7)
+    gz, ge = from_dev(zo), from_dev(eo)
+    for j in range(3):
+        c1, c2 = o.precond_apply(j, zin[j], ein[j], 0.7, inner="cheb" if inner == apfc.APFC_INNER_CHEB else "pcg",
+                                 mass_iters=its[0], diff_iters=its[1])
+        ref = np.concatenate([c1, c2])
+        got = np.concatenate([gz[j], ge[j]])
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), (j, np.linalg.norm(got - ref) / np.linalg.norm(ref))

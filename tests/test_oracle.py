@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from oracle.apfc_oracle import (BulkEnergy, Grid, Oracle, Params, assemble, bcc_k, element_matrices,
+from oracle.apfc_oracle import (BulkEnergy, Grid, Oracle, Params, assemble, bcc_k, chebyshev, element_matrices,
                                 fourier_symbols, jacobi_pcg, kappas, kron_matrices, model_spectrum,
                                 plane_wave, tri_bulk_closed_form, tri_k, uniform_amplitude)
 
@@ -495,3 +495,37 @@ def test_adjoint_dot_product_identity():
     N = g.N
     S = np.diag(np.concatenate([np.full(N, -o.kappa[0]), np.ones(N)]))
     np.testing.assert_allclose(A.conj().T, S @ A @ np.linalg.inv(S), atol=1e-13)
+
+
+def test_chebyshev_on_fourier_mode_matches_polynomial():
+    """On an eigenvector of D^{-1} A with eigenvalue lam, s Chebyshev steps leave the error
+    T_s((theta - lam)/delta) / T_s(theta/delta) times the initial error x* (x0 = 0)."""
+    from numpy.polynomial import chebyshev as C
+    g = Grid(2, (16, 12), (30.0, 22.5))
+    o = Oracle(g, tri_k(), Params())
+    (lmM, lxM), (lmL, lxL) = o.jacobi_bounds(0, 0.7)
+    assert math.isclose(lmM, 0.25, rel_tol=1e-14) and math.isclose(lxM, 2.25, rel_tol=1e-14)
+    L = (o.M / math.sqrt(0.7) + math.sqrt(o.kappa[0]) * o.K).tocsr()
+    for A, lo, hi in ((o.M, lmM, lxM), (L, lmL, lxL)):
+        D = A.diagonal()[0]
+        for mode in ((0, 0), (3, -2), (8, 6)):
+            e = plane_wave(g, mode)
+            lam = ((A @ e) / e).real[0] / D
+            assert lo - 1e-12 <= lam <= hi + 1e-12
+            th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+            for s in (1, 3, 5):
+                x = chebyshev(A, e, s, lo, hi)
+                xstar = e / (lam * D)
+                T = lambda z: C.chebval(z, [0] * s + [1])
+                err = T((th - lam) / de) / T(th / de)
+                np.testing.assert_allclose(x, (1.0 - err) * xstar, atol=1e-12 * np.abs(xstar).max())
+
+
+def test_chebyshev_converges_to_direct():
+    g = Grid(2, (10, 10), (25.0, 25.0))
+    o = Oracle(g, tri_k(), Params())
+    (lo, hi), _ = o.jacobi_bounds(0, 1.0)
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    x = chebyshev(o.M, b, 60, lo, hi)
+    np.testing.assert_allclose(o.M @ x, b, atol=1e-10)
