@@ -1,19 +1,25 @@
 """Throughput of the APFC time step on one MI355X.
 
-A step is one apfc_step (Algorithm 1 with K = 1: nodal nonlinearity, then restarted FGMRES with
-the block preconditioner on every amplitude to rtol 1e-8) on the 1024^2 triangular-lattice
-polycrystal (16 periodic Voronoi grains within +-10 degrees, side 400 lattice spacings, dt = 1).
-Inputs are seeded and synthetic and live in HBM before the timed region starts.
+A step is one apfc_step: Algorithm 1 with K = 1 (nodal nonlinearity, right-hand sides, then
+restarted FGMRES with the block preconditioner on every amplitude to ||b - A x|| <= 1e-8 ||b||).
+Workloads (seeded, synthetic, resident in HBM before the timed region starts):
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
-                    [--probe KERNEL] [--no-cpu-baseline]
+  tri1024  (default) 1024^2 triangular-lattice polycrystal, 16 periodic Voronoi grains within +-10
+           degrees, side 400 lattice spacings, 3 amplitudes, dt = 1
+  batch64  64 independent triangular instances of seeded size n^2, n in {128,...,512}, one rotated grain
+           each, Delta B ~ U[0.01, 0.05], all in one batched context
+  bcc128   128^3 bcc lattice (6 amplitudes), spherical grain rotated 5 degrees about [001]
 
-Prints one JSON line.  value = J * N * K / (seconds of the K timed steps).
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tri1024|batch64|bcc128]
+                    [--precision mixed|fp64] [--compare] [--probe KERNEL] [--no-cpu-baseline]
+
+Prints one JSON line; value = (sum over instances of J * N) * K / seconds of the K timed steps.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -22,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "amplitude DOF-steps/s at 1e-8 rel. residual + % HBM peak; plain vs mixed/batch"
 HBM_PEAK_GBS = 8000.0
+KERNELS_SRC = os.path.join(ROOT, "paper_1902_09761_amd", "csrc", "kernels.hip")
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "apply_dot_tri1024_mixed_hbm_counters.md")
 
 
 def parse():
@@ -29,89 +37,120 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--workload", default="tri1024", choices=["tri1024", "batch64", "bcc128"])
+    ap.add_argument("--n", type=int, default=None, help="override the mesh side (tri1024 / bcc128)")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
-    ap.add_argument("--compare", action="store_true", help="also time the other precision")
+    ap.add_argument("--compare", action="store_true", help="also time the other precision on the same workload")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=4)
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)
-    ap.add_argument("--probe", default="pcg_spmv", help="kernel timed with HIP events for the roofline")
-    ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--probe", default="apply", help="kernel timed with HIP events for the roofline ('none': off)")
+    ap.add_argument("--graphs", action="store_true", help="replay restart cycles as hipGraphs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=192, help="mesh side of the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, copy 256 MiB device-to-device (reference for HBM counters)")
     return ap.parse_args()
 
 
-def make_workload(n):
-    from paper_1902_09761_amd import apfc, inputs
-    lat = apfc.apfc_lattice_default(apfc.APFC_TRI2D)
-    k = apfc.lattice_k(lat, 2)
+def make_workload(args):
+    """Returns (lattice, list of inputs.Workload, dim)."""
     import numpy as np
-    kk = np.array(k)
+    from paper_1902_09761_amd import apfc, inputs
+    kind = apfc.APFC_BCC3D if args.workload == "bcc128" else apfc.APFC_TRI2D
+    lat = apfc.apfc_lattice_default(kind)
+    dim = 3 if kind == apfc.APFC_BCC3D else 2
+    kk = np.array(apfc.lattice_k(lat, dim))
 
     def phi_of(dB):
         return apfc.apfc_uniform_amplitude(lat, apfc.apfc_params_default(a1=0.5 * dB))
-    return inputs.voronoi_2d(kk, phi_of, n=n, seed=1), lat
+    if args.workload == "tri1024":
+        wls = [inputs.voronoi_2d(kk, phi_of, n=args.n or 1024, seed=1)]
+    elif args.workload == "batch64":
+        wls = inputs.batch_2d(kk, phi_of, count=64, seed=1)
+    else:
+        wls = [inputs.sphere_3d(kk, phi_of, n=args.n or 128, seed=1)]
+    return lat, wls, dim
 
 
 def run_gpu(args, precision, probe=None):
     import torch
     from paper_1902_09761_amd import apfc, inputs
-    wl, lat = make_workload(args.n)
+    lat, wls, dim = make_workload(args)
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
     inner = apfc.APFC_INNER_CHEB if args.inner == "cheb" else apfc.APFC_INNER_PCG
     mi = args.mass_iters or (4 if args.inner == "cheb" else 3)
     di = args.diff_iters or (4 if args.inner == "cheb" else 5)
-    p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=wl.rtol, precision=prec, inner_kind=inner,
-                                 restart=args.restart, mass_iters=mi, diff_iters=di)
-    m = apfc.make_mesh(2, wl.mesh.n, wl.mesh.length)
-    s = apfc.Solver([m], lat, [p])
-    if args.no_graphs:
-        s.set_graphs(False)
+    ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=prec, inner_kind=inner,
+                                   restart=args.restart, mass_iters=mi, diff_iters=di) for w in wls]
+    ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
+    s = apfc.Solver(ms, lat, ps)
+    s.set_graphs(args.graphs)
     ty = None if args.no_autotune else s.autotune()
-    et = torch.tensor(inputs.to_planar(wl.eta0), dtype=torch.float64, device="cuda")
-    zt = torch.zeros_like(et)
-    s.init_zeta([et], [zt])
+    ets = [torch.tensor(inputs.to_planar(w.eta0), dtype=torch.float64, device="cuda") for w in wls]
+    zts = [torch.zeros_like(e) for e in ets]
+    s.init_zeta(ets, zts)
+    dt = wls[0].dt
     for _ in range(args.warmup):
-        s.step([et], [zt], wl.dt)
+        s.step(ets, zts, dt)
     if probe:
         s.probe_enable(probe)
-    iters = []
+    iters, total = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        info = s.step([et], [zt], wl.dt)
+        info = s.step(ets, zts, dt)
         iters.append(info["max_iters"])
+        total.append(info["total_iters"])
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    out = {"sec": sec, "iters": iters, "tile_rows": ty, "N": wl.mesh.N, "J": 3, "relres": info["max_relres"]}
+    J = lat.J
+    dofs = sum(J * w.mesh.N for w in wls)
+    out = {"sec": sec, "iters": iters, "total_iters": total, "tile_rows": ty, "dofs": dofs, "J": J,
+           "relres": info["max_relres"], "instances": len(wls), "mesh": wls[0].name}
     if probe:
-        n, ms, bpl = s.probe_read()
-        out["probe"] = {"kernel": probe, "launches": n, "ms": ms, "bytes_per_launch": bpl}
+        n, ms_, bpl = s.probe_read()
+        out["probe"] = {"kernel": probe, "launches": n, "ms": ms_, "bytes_per_launch": bpl}
         s.probe_enable(None)
-    E = s.energy([et])[0]
-    out["energy"] = E
-    out["eta_host"] = et.cpu().numpy()
+    out["energy"] = s.energy(ets)
+    out["eta_host"] = [e.cpu().numpy() for e in ets]
     return out
 
 
+def traffic_from_profile():
+    """HBM bytes per k_apply_dot launch from the committed counter summary, if it was taken with the
+    current kernel source (null otherwise)."""
+    if not os.path.exists(TRAFFIC_MD):
+        return None, None
+    text = open(TRAFFIC_MD).read()
+    m1 = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
+    m2 = re.search(r"kernels_hip_sha256:\s*([0-9a-f]+)", text)
+    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    if not (m1 and m2) or m2.group(1) != sha:
+        return None, os.path.relpath(TRAFFIC_MD, ROOT)
+    return float(m1.group(1)), os.path.relpath(TRAFFIC_MD, ROOT)
+
+
 def cpu_baseline(args):
-    """The oracle (SuperLU direct solves, single-threaded) on one step of the same workload recipe
-    at a reduced mesh side with the same h."""
-    import numpy as np
-    from oracle.apfc_oracle import BulkEnergy, Grid, Oracle, Params, tri_k, uniform_amplitude
+    """The oracle (SuperLU factor + solve per amplitude, single-threaded) on one step of the same
+    workload recipe at a reduced size with the same h."""
+    from oracle.apfc_oracle import BulkEnergy, Grid, Oracle, Params, bcc_k, tri_k, uniform_amplitude
     from paper_1902_09761_amd import inputs
-    n = args.cpu_n
-    wl = inputs.voronoi_2d(tri_k(), lambda dB: uniform_amplitude(BulkEnergy(tri_k(), Params.from_dB(dB))), n=n, seed=1)
-    o = Oracle(Grid(2, (n, n), wl.mesh.length[:2]), tri_k(), Params.from_dB(wl.dB))
+    if args.workload == "bcc128":
+        k, n = bcc_k(), 16
+        wl = inputs.sphere_3d(k, lambda dB: uniform_amplitude(BulkEnergy(k, Params.from_dB(dB))), n=n, seed=1)
+        what = f"1 step of the bcc sphere recipe at {n}^3 nodes (same h, 6 amplitudes)"
+    else:
+        k, n = tri_k(), 192
+        wl = inputs.voronoi_2d(k, lambda dB: uniform_amplitude(BulkEnergy(k, Params.from_dB(dB))), n=n, seed=1)
+        what = f"1 step of the Voronoi recipe at {n}^2 nodes (same h, 3 amplitudes)"
+    o = Oracle(Grid(wl.mesh.dim, wl.mesh.n[: wl.mesh.dim], wl.mesh.length[: wl.mesh.dim]), k, Params.from_dB(wl.dB))
     t0 = time.perf_counter()
     o.step(wl.eta0, wl.dt)
     sec = time.perf_counter() - t0
-    return {"value": 3 * n * n / sec, "unit": "amplitude-DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 step of the Voronoi recipe at {n}^2 nodes (same h, 3 amplitudes; SuperLU "
-                      f"factor+solve per amplitude, single-threaded), {sec:.1f} s"}
+    return {"value": len(k) * wl.mesh.N / sec, "unit": "amplitude-DOF-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what}; SuperLU factor + solve per amplitude, single-threaded; {sec:.1f} s"}
 
 
 def main():
@@ -122,8 +161,8 @@ def main():
     import numpy as np
     probe = None if args.probe in ("", "none") else args.probe
     res = run_gpu(args, args.precision, probe=probe)
-    J, N, K = res["J"], res["N"], args.steps
-    value = J * N * K / res["sec"]
+    K = args.steps
+    value = res["dofs"] * K / res["sec"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -137,10 +176,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"tri{args.n}_voronoi16", "mesh": f"{args.n}x{args.n} periodic Q1", "J": 3,
-                   "dt": 1.0, "rtol": 1e-8, "precision": args.precision, "restart": args.restart,
-                   "inner": args.inner, "tile_rows": res["tile_rows"],
-                   "graphs": not args.no_graphs},
+        "config": {"workload": args.workload, "instances": res["instances"], "first_instance": res["mesh"],
+                   "amplitude_dofs": res["dofs"], "J": res["J"], "dt": 1.0, "rtol": 1e-8,
+                   "precision": args.precision, "inner": args.inner, "restart": args.restart,
+                   "tile_rows": res["tile_rows"], "graphs": bool(args.graphs)},
         "fgmres_iters_per_step": float(np.mean(res["iters"])),
         "final_relres": res["relres"],
     }
@@ -148,20 +187,29 @@ def main():
     if pr and pr["launches"] > 0:
         avg_ms = pr["ms"] / pr["launches"]
         ach = pr["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-        line["roofline"] = {"bound": "hbm", "kernel": pr["kernel"], "achieved": ach, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                            "avg_launch_us": 1e3 * avg_ms, "launches": pr["launches"],
-                            "bytes_per_launch": pr["bytes_per_launch"]}
+        traffic, src = traffic_from_profile() if (pr["kernel"] == "apply" and args.workload == "tri1024"
+                                                 and args.precision == "mixed") else (None, None)
+        line["roofline"] = {"bound": "hbm", "kernel": "k_apply_dot" if pr["kernel"] == "apply" else pr["kernel"],
+                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                            "traffic": traffic, "traffic_source": src, "avg_launch_us": 1e3 * avg_ms,
+                            "launches": pr["launches"], "bytes_per_launch": pr["bytes_per_launch"]}
     if args.compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
         r2 = run_gpu(args, other)
-        v2 = J * N * K / r2["sec"]
         a, b = (res, r2) if args.precision == "fp64" else (r2, res)
-        diff = float(np.linalg.norm(b["eta_host"] - a["eta_host"]) / np.linalg.norm(a["eta_host"]))
-        line["variants"] = {other: {"value": v2, "ms_per_step": 1e3 * r2["sec"] / K,
+        diffs = [float(np.linalg.norm(y - x) / np.linalg.norm(x)) for x, y in zip(a["eta_host"], b["eta_host"])]
+        ediff = [abs(y - x) / abs(x) for x, y in zip(a["energy"], b["energy"])]
+        line["variants"] = {other: {"value": res["dofs"] * K / r2["sec"], "ms_per_step": 1e3 * r2["sec"] / K,
                                     "fgmres_iters_per_step": float(np.mean(r2["iters"]))},
-                            "mixed_vs_fp64_eta_rel_l2": diff,
-                            "mixed_vs_fp64_energy_rel": abs(b["energy"] - a["energy"]) / abs(a["energy"])}
+                            "mixed_vs_fp64_eta_rel_l2": max(diffs),
+                            "mixed_vs_fp64_energy_rel": max(ediff)}
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

@@ -110,6 +110,7 @@ struct Krylov {
     int* iter_active;   // [S]
     int* reorth;        // [S] second Gram-Schmidt pass needed in this iteration
     int always_reorth;  // 1: classical Gram-Schmidt twice on every iteration
+    double reorth_theta;  // second pass when |w'|^2 < reorth_theta |w|^2
     int* kcount;        // [S]
     int* iters;         // [S]
     int* cycles;        // [S]
@@ -145,6 +146,10 @@ template <typename T>
 void launch_precond_cheb(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
                          cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
+template <typename T>
+void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
+                                 cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
 void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
@@ -163,6 +168,7 @@ void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t s
 void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st);
 void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
+void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,
                        int iters, hipStream_t st);

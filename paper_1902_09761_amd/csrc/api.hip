@@ -151,7 +151,10 @@ struct apfc_ctx {
 
     // host staging (pinned)
     double** h_tab = nullptr;
+    std::vector<const void*> tab_shadow;   // pointer tables currently in d_tab
     int* h_flags = nullptr;
+    int* h_pub = nullptr;                  // mapped host flags written by k_publish
+    int* d_pub = nullptr;
     double* h_dbl = nullptr;
 
     Probe probe;
@@ -300,6 +303,11 @@ size_t carve(apfc_ctx& c, char* base) {
     k.nv1 = 2 * (m + 1);
     k.rtol = c.solver.rtol;
     k.always_reorth = 0;
+    // keep the orthogonality loss of one classical pass (~eps |w|/|w'|) below rtol/100
+    {
+        const double r = 100.0 * 2.2e-16 / c.solver.rtol;
+        k.reorth_theta = std::min(0.5, std::max(1e-6, r * r));
+    }
     k.H = (double*)take(sizeof(double) * S * m * 2 * (m + 1));
     k.cs = (double*)take(sizeof(double) * S * m);
     k.sn = (double*)take(sizeof(double) * S * 2 * m);
@@ -486,11 +494,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
         return rc;
     }
     if (params[0].inner_kind == APFC_INNER_CHEB) {
-        if (dim != 2) {
-            delete c;
-            return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB (fused 2D tiles) needs dim == 2");
-        }
-        if (cheb_halo(params[0]) > 12) {
+        if (dim == 2 && cheb_halo(params[0]) > 12) {
             delete c;
             return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB needs mass_iters <= 13 and diff_iters <= 12");
         }
@@ -547,7 +551,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
     c->TY = 16;
     build_tiles(*c, c->TY, c->tiles);
     set_dt_scalars(*c, 1.0);
-    if (params[0].inner_kind == APFC_INNER_CHEB) build_ctiles(*c);
+    if (params[0].inner_kind == APFC_INNER_CHEB && dim == 2) build_ctiles(*c);
     *out = c;
     return APFC_OK;
 }
@@ -561,6 +565,7 @@ size_t apfc_workspace_bytes(const apfc_ctx* c) {
     apfc_ctx tmp_view = *c;   // carve on a copy: only sizes are computed
     tmp_view.h_tab = nullptr;
     tmp_view.h_flags = nullptr;
+    tmp_view.h_pub = nullptr;
     tmp_view.h_dbl = nullptr;
     tmp_view.graphs.clear();
     size_t n = carve(tmp_view, nullptr);
@@ -576,8 +581,10 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
         // pinned host staging for pointer tables and flag / scalar read-back
         if (hipHostMalloc((void**)&c->h_tab, sizeof(double*) * 4 * c->count) != hipSuccess ||
             hipHostMalloc((void**)&c->h_flags, sizeof(int) * (4 * c->S + 8)) != hipSuccess ||
-            hipHostMalloc((void**)&c->h_dbl, sizeof(double) * (kSlots * c->S + 8)) != hipSuccess)
+            hipHostMalloc((void**)&c->h_dbl, sizeof(double) * (kSlots * c->S + 8)) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_pub, sizeof(int) * 8, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
             return fail(APFC_ERR_HIP, "hipHostMalloc of host staging buffers failed");
+        HIPCHK(hipHostGetDevicePointer((void**)&c->d_pub, c->h_pub, 0));
     }
     c->ws = (char*)ptr;
     c->ws_bytes = bytes;
@@ -593,6 +600,7 @@ int apfc_destroy(apfc_ctx* c) {
         for (auto& e : c->probe.ev) (void)hipEventDestroy(e);
     if (c->h_tab) (void)hipHostFree(c->h_tab);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
+    if (c->h_pub) (void)hipHostFree(c->h_pub);
     if (c->h_dbl) (void)hipHostFree(c->h_dbl);
     delete c;
     return APFC_OK;
@@ -623,12 +631,34 @@ int refresh_dt(apfc_ctx* c, double dt, hipStream_t st) {
 
 // upload up to 4 tables of per-instance device pointers
 int upload_ptrs(apfc_ctx* c, const std::vector<const void*>* tabs, int ntabs, hipStream_t st) {
-    for (int t = 0; t < ntabs; ++t)
-        for (int b = 0; b < c->count; ++b) c->h_tab[t * c->count + b] = (double*)tabs[t][b];
-    HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(double*) * ntabs * c->count, hipMemcpyHostToDevice, st));
+    std::vector<const void*> flat;
+    for (int t = 0; t < ntabs; ++t) flat.insert(flat.end(), tabs[t].begin(), tabs[t].end());
+    if (flat.size() <= c->tab_shadow.size() && std::equal(flat.begin(), flat.end(), c->tab_shadow.begin()))
+        return APFC_OK;   // the device tables already hold these pointers
+    // the pinned staging buffer may still feed an earlier copy
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < flat.size(); ++i) c->h_tab[i] = (double*)flat[i];
+    HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(double*) * flat.size(), hipMemcpyHostToDevice, st));
+    c->tab_shadow = flat;
     return APFC_OK;
 }
 double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
+
+// P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
+// Chebyshev (3D), or the paper's Jacobi-PCG.
+template <typename T>
+void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, hipStream_t st) {
+    cx<T>** pc = (cx<T>**)c->pc;
+    if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
+        launch_precond_cheb<T>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z, pc[0], pc[1],
+                               c->solver.mass_iters, c->solver.diff_iters, mask, st);
+    else if (c->solver.inner_kind == APFC_INNER_CHEB)
+        launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
+                                       c->solver.diff_iters, mask, st);
+    else
+        launch_precond<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart, c->solver.mass_iters,
+                          c->solver.diff_iters, mask, st);
+}
 
 template <typename T>
 void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
@@ -637,12 +667,7 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     cx<T>* Z = (cx<T>*)c->Z;
     cx<T>** pc = (cx<T>**)c->pc;
     const int* act = kr.iter_active;
-    if (c->solver.inner_kind == APFC_INNER_CHEB)
-        launch_precond_cheb<T>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V + k * vs,
-                               Z + k * vs, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, act, st);
-    else
-        launch_precond<T>(d, c->V + k * vs, Z + k * vs, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                          c->solver.mass_iters, c->solver.diff_iters, act, st);
+    precond<T>(c, d, c->V + k * vs, Z + k * vs, act, st);
     const int nv = k + 1;
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
@@ -661,23 +686,40 @@ void run_iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
         iteration<double>(c, d, k, st);
 }
 
+// One restart cycle: m Arnoldi iterations (masked per system once it has converged or broken
+// down), the solution update, the true FP64 residual, the next cycle's start vector and the
+// published flags.
+void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
+    Krylov& kr = c->kr;
+    const long long vs = c->vstride();
+    for (int k = 0; k < c->m; ++k) run_iteration(c, d, k, st);
+    launch_solve_y(d, kr, st);
+    if (c->mixed)
+        launch_xupdate<float>(d, (const zf*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
+    else
+        launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
+    launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
+    launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
+    launch_cycle_init(d, kr, false, st);
+    launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    launch_publish(d, kr, c->d_pub, st);
+}
+
 int capture_graphs(apfc_ctx* c) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     invalidate_graphs(*c);
     Dev d = c->dev();
     d.probe = nullptr;
-    c->graphs.assign(c->m, nullptr);
-    for (int k = 0; k < c->m; ++k) {
-        hipGraph_t g;
-        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        run_iteration(c, d, k, c->cap_stream);
-        HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
-        hipGraphExec_t ge;
-        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(APFC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        c->graphs[k] = ge;
-    }
+    c->graphs.assign(1, nullptr);
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    run_cycle(c, d, c->cap_stream);
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+    hipGraphExec_t ge;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(APFC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    c->graphs[0] = ge;
     c->graphs_valid = true;
     return APFC_OK;
 }
@@ -696,39 +738,22 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     launch_cycle_init(d, kr, true, st);
     launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
     int launched = 0;
-    const int S = c->S;
     for (int cyc = 0;; ++cyc) {
-        for (int k = 0; k < c->m; ++k) {
-            if (graphs)
-                HIPCHK(hipGraphLaunch(c->graphs[k], st));
-            else
-                run_iteration(c, d, k, st);
-            ++launched;
-            // poll the per-system flags; cheap relative to one iteration of these sizes
-            HIPCHK(hipMemcpyAsync(c->h_flags, kr.iter_active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            bool any = false;
-            for (int s = 0; s < S; ++s) any |= c->h_flags[s] != 0;
-            if (!any) break;
-        }
-        launch_solve_y(d, kr, st);
-        if (c->mixed)
-            launch_xupdate<float>(d, (const zf*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
+        if (graphs)
+            HIPCHK(hipGraphLaunch(c->graphs[0], st));
         else
-            launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
-        launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
-        launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
-        launch_cycle_init(d, kr, false, st);
-        launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
-        HIPCHK(hipMemcpyAsync(c->h_flags, kr.solve_active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(c->h_flags + S, kr.err, sizeof(int), hipMemcpyDeviceToHost, st));
+            run_cycle(c, d, st);
+        launched += c->m;
         HIPCHK(hipStreamSynchronize(st));
-        if (c->h_flags[S]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
-        bool any = false;
-        for (int s = 0; s < S; ++s) any |= c->h_flags[s] != 0;
-        if (!any) break;
-        if (launched >= c->solver.max_iters) {
-            if (total_iters) *total_iters = launched;
+        // k_publish wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
+        const volatile int* pub = c->h_pub;
+        if (pub[1]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
+        if (!pub[0]) {
+            launched = pub[2];
+            break;
+        }
+        if (pub[2] >= c->solver.max_iters) {
+            if (total_iters) *total_iters = pub[2];
             return fail(APFC_ERR_NOT_CONVERGED, "FGMRES reached max_iters");
         }
     }
@@ -952,24 +977,10 @@ int apfc_apply(apfc_ctx* c, int which, const apfc_state* lin, const apfc_state* 
         const long long vs = c->vstride();
         (void)vs;
         if (c->mixed) {
-            zf** pc = (zf**)c->pc;
-            if (c->solver.inner_kind == APFC_INNER_CHEB)
-                launch_precond_cheb<float>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V,
-                                           (zf*)c->Z, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters,
-                                           nullptr, st);
-            else
-                launch_precond<float>(d, c->V, (zf*)c->Z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                                      c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+            precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
             launch_widen((const zf*)c->Z, c->R, 2 * c->NT, st);
         } else {
-            zd** pc = (zd**)c->pc;
-            if (c->solver.inner_kind == APFC_INNER_CHEB)
-                launch_precond_cheb<double>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), c->V,
-                                            c->R, pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters,
-                                            nullptr, st);
-            else
-                launch_precond<double>(d, c->V, c->R, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart,
-                                       c->solver.mass_iters, c->solver.diff_iters, nullptr, st);
+            precond<double>(c, d, c->V, c->R, nullptr, st);
         }
         launch_state_out(d, c->R, tab(c, 2), tab(c, 3), st);
     }

@@ -650,36 +650,54 @@ __device__ __forceinline__ int wrapi(int g, int n) {
     return g < 0 ? g + n : g;
 }
 
-template <typename T, bool WK, bool WT>
-__device__ __forceinline__ void lds_stencil(const cx<T>* buf, int px, int py, int RX, int RY, T h, T k0, T k1,
-                                            cx<T>& Mu, cx<T>& Ku, cx<T>& Tu) {
+// Stencils at NP consecutive rows r0..r0+NP-1 of column px of an LDS region (RX x RY, clamped at
+// the region border), streamed row by row: the x pass of each of the NP+2 rows involved is
+// evaluated once, and f(i, Mu, Ku, Tu) is called for row r0+i as soon as its three rows are known,
+// so only three rows of x-pass values are live at a time.
+template <typename T, int NP, bool WK, bool WT, typename F>
+__device__ __forceinline__ void col_sweep(const cx<T>* buf, int px, int r0, int RX, int RY, T h, T k0, T k1,
+                                          F&& f) {
+    const T m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h, half = T(0.5);
     const int xm = px > 0 ? px - 1 : px, xp = px < RX - 1 ? px + 1 : px;
-    const int ym = py > 0 ? py - 1 : py, yp = py < RY - 1 ? py + 1 : py;
-    const int xs[3] = {xm, px, xp};
-    const int ys[3] = {ym, py, yp};
-    stencil<2, WK, WT, T>([&](int a, int b, int c) { return buf[ys[b] * RX + xs[a]]; }, h, k0, k1, T(0), Mu, Ku, Tu);
+    const cx<T> zero{T(0), T(0)};
+    cx<T> mA = zero, mB = zero, kA = zero, kB = zero, dA = zero, dB = zero;
+#pragma unroll
+    for (int a = 0; a < NP + 2; ++a) {
+        int row = r0 - 1 + a;
+        row = row < 0 ? 0 : (row > RY - 1 ? RY - 1 : row);
+        const cx<T> l = buf[row * RX + xm], c = buf[row * RX + px], r = buf[row * RX + xp];
+        const cx<T> mC = m0 * (l + r) + m1 * c;
+        const cx<T> kC = WK ? ih * ((c + c) - (l + r)) : zero;
+        const cx<T> dC = WT ? half * (r - l) : zero;
+        if (a >= 2) {
+            const cx<T> Mu = m0 * (mA + mC) + m1 * mB;
+            const cx<T> Ku = WK ? m0 * (kA + kC) + m1 * kB + ih * ((mB + mB) - (mA + mC)) : zero;
+            const cx<T> Tu = WT ? T(2) * (k0 * (m0 * (dA + dC) + m1 * dB) + k1 * half * (mC - mA)) : zero;
+            f(a - 2, Mu, Ku, Tu);
+        }
+        mA = mB; mB = mC;
+        kA = kB; kB = kC;
+        dA = dB; dB = dC;
+    }
 }
 
 template <typename T, int STAGE, int NTH>
-__global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
+__global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
                                                cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
                                                long long NT) {
     constexpr int RX = kChebRX, RY = kChebRY, RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
-    constexpr int ROWS = NTH / RX;                 // region rows covered by one pass of the workgroup
     __shared__ cx<T> buf[RP];
     const CTile tile = tiles[blockIdx.x];
     if (mask && !mask[tile.sys]) return;
     const Sys s = sys[tile.sys];
     const int IX = RX - 2 * halo, IY = RY - 2 * halo;
     const T h = T(s.h);
-    // thread -> region column px (fixed) and rows py = ty + ROWS * i
-    const int px = threadIdx.x % RX, ty = threadIdx.x / RX;
+    // thread -> region column px and NP consecutive rows r0 .. r0 + NP - 1
+    const int px = threadIdx.x % RX, r0 = (threadIdx.x / RX) * NP;
     const long long gx = wrapi(tile.x0 - halo + px, s.nx);
-    auto gidx = [&](int i) {
-        const int py = ty + ROWS * i;
-        return s.off + (long long)wrapi(tile.y0 - halo + py, s.ny) * s.nx + gx;
-    };
+    auto gidx = [&](int i) { return s.off + (long long)wrapi(tile.y0 - halo + r0 + i, s.ny) * s.nx + gx; };
+    auto lidx = [&](int i) { return (r0 + i) * RX + px; };
     cx<T> X[NP], R[NP], Dd[NP];
     // right-hand side of the inner solve
     if constexpr (STAGE == 0) {
@@ -687,19 +705,17 @@ __global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* til
         for (int i = 0; i < NP; ++i) R[i] = ld<T>(v, gidx(i));
     } else {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) buf[threadIdx.x + NTH * i] = STAGE == 1 ? x1[gidx(i)] : x2[gidx(i)];
+        for (int i = 0; i < NP; ++i) buf[lidx(i)] = STAGE == 1 ? x1[gidx(i)] : x2[gidx(i)];
         __syncthreads();
+        if constexpr (STAGE == 1) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const int py = ty + ROWS * i;
-            cx<T> Mu, Ku, Tu;
-            if constexpr (STAGE == 1) {
-                lds_stencil<T, true, true>(buf, px, py, RX, RY, h, T(s.kv[0]), T(s.kv[1]), Mu, Ku, Tu);
-                R[i] = ld<T>(v, NT + gidx(i)) - T(s.kappa) * gop(Ku, Tu);
-            } else {
-                lds_stencil<T, false, false>(buf, px, py, RX, RY, h, T(0), T(0), Mu, Ku, Tu);
-                R[i] = Mu;
-            }
+            for (int i = 0; i < NP; ++i) R[i] = ld<T>(v, NT + gidx(i));
+            const T kap = T(s.kappa);
+            col_sweep<T, NP, true, true>(buf, px, r0, RX, RY, h, T(s.kv[0]), T(s.kv[1]),
+                                         [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) { R[i] = R[i] - kap * gop(Ku, Tu); });
+        } else {
+            col_sweep<T, NP, false, false>(buf, px, r0, RX, RY, h, T(0), T(0),
+                                           [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) { R[i] = Mu; });
         }
     }
     // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
@@ -718,20 +734,16 @@ __global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* til
     for (int k = 1; k < its; ++k) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NP; ++i) buf[threadIdx.x + NTH * i] = Dd[i];
+        for (int i = 0; i < NP; ++i) buf[lidx(i)] = Dd[i];
         __syncthreads();
         const T rn = T(1) / (T(2) * sig - rho);
         const T c1 = rn * rho, c2 = T(2) * rn / de * iD;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const int py = ty + ROWS * i;
-            cx<T> Mu, Ku, Tu;
-            lds_stencil<T, !isM, false>(buf, px, py, RX, RY, h, T(0), T(0), Mu, Ku, Tu);
+        col_sweep<T, NP, !isM, false>(buf, px, r0, RX, RY, h, T(0), T(0), [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) {
             const cx<T> q = isM ? Mu : cM * Mu + cK * Ku;
             R[i] = R[i] - q;
             Dd[i] = c1 * Dd[i] + c2 * R[i];
             X[i] = X[i] + Dd[i];
-        }
+        });
         rho = rn;
     }
     // interior output (no wrap: each mesh node is written by exactly one tile)
@@ -739,7 +751,7 @@ __global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* til
     if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        const int iy = ty + ROWS * i - halo;
+        const int iy = r0 + i - halo;
         if (iy < 0 || iy >= IY || tile.y0 + iy >= s.ny) continue;
         const long long g = gidx(i);
         if constexpr (STAGE == 0) {
@@ -750,6 +762,78 @@ __global__ __launch_bounds__(NTH) void k_cheb2d(const Sys* sys, const CTile* til
             const cx<T> chi2 = X[i];
             z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
             z[NT + g] = chi2;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Block preconditioner with Chebyshev-Jacobi inner solves, one launch per inner iteration (any
+// dimension; used in 3D, where a halo of several layers of a 27-point stencil does not fit LDS).
+// Same recurrence as k_cheb2d; the scalars rho_j follow from (theta, delta) of each system.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void cheb_coef(double th, double de, int j, double& c1, double& c2) {
+    // rho_0 = delta/theta, rho_j = 1/(2 theta/delta - rho_{j-1}); c1 = rho_j rho_{j-1}, c2 = 2 rho_j/delta
+    const double sig = th / de;
+    double rho = 1.0 / sig, rn = rho;
+    for (int i = 1; i <= j; ++i) {
+        rn = 1.0 / (2.0 * sig - rho);
+        if (i < j) rho = rn;
+    }
+    c1 = rn * rho;
+    c2 = 2.0 * rn / de;
+}
+
+// r0 of the inner solve (STAGE 0: beta1; 1: beta2 - kappa G x1; 2: M x2), d0 = r0/(theta D), x = d0
+template <int DIM, int TY, typename T, int STAGE>
+__global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* tiles, const int* mask, const zd* v,
+                                                   const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
+    TILE_PROLOGUE();
+    constexpr bool isM = STAGE == 0;
+    const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
+        cx<T> rv;
+        if constexpr (STAGE == 0) {
+            rv = ld<T>(v, i);
+        } else {
+            cx<T> Mu, Ku, Tu;
+            stencil<DIM, STAGE == 1, STAGE == 1, T>(
+                [&](int a, int b, int c) { return ld<T>(src, s.off + nb_index<DIM>(n, a, b, c)); }, T(s.h),
+                T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
+            rv = STAGE == 1 ? ld<T>(v, NT + i) - T(s.kappa) * gop(Ku, Tu) : Mu;
+        }
+        const cx<T> dv = scale * rv;
+        r[i] = rv;
+        d[i] = dv;
+        xv[i] = dv;
+    }
+}
+
+// iteration j >= 1: q = OP d_{j-1}; r -= q; d_j = c1 d_{j-1} + c2 D^{-1} r; x += d_j
+template <int DIM, int TY, typename T, int OP, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* tiles, const int* mask, int j,
+                                                   const cx<T>* din, cx<T>* dout, cx<T>* r, cx<T>* xv) {
+    TILE_PROLOGUE();
+    double c1d, c2d;
+    cheb_coef(OP == 0 ? s.thM : s.thL, OP == 0 ? s.deM : s.deL, j, c1d, c2d);
+    const T c1 = T(c1d), c2 = T(c2d / (OP == 0 ? s.diagM : s.diagL));
+    const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        cx<T> Mu, Ku, Tu;
+        stencil<DIM, OP == 1, false, T>([&](int a, int b, int c) { return ld<T>(din, s.off + nb_index<DIM>(n, a, b, c)); },
+                                        T(s.h), T(0), T(0), T(0), Mu, Ku, Tu);
+        const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
+        const cx<T> q = OP == 0 ? Mu : cM * Mu + cK * Ku;
+        const cx<T> rv = ld<T>(r, i) - q;
+        const cx<T> dv = c1 * ld<T>(din, i) + c2 * rv;
+        xv[i] = ld<T>(xv, i) + dv;
+        if constexpr (!LAST) {
+            r[i] = rv;
+            dout[i] = dv;
         }
     }
 }
@@ -919,9 +1003,10 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
     for (int i = 1; i <= kr.m; ++i) g[2 * i] = g[2 * i + 1] = 0.0;
 }
 
-// After the first pass: re-orthogonalise only if it removed more than half of |w|^2 (the
-// "twice is enough" test); otherwise the second pass is skipped and its results set to
-// h2 = 0, |w'|^2 = |w|^2 - |h1|^2.
+// After the first pass: re-orthogonalise only if |w'|^2 = |w|^2 - |h1|^2 fell below
+// reorth_theta |w|^2.  One classical Gram-Schmidt pass leaves the new basis vector orthogonal to
+// about eps |w| / |w'|, so theta is chosen from rtol (api.hip); otherwise the second pass is
+// skipped and its results set to h2 = 0, |w'|^2 = |w|^2 - |h1|^2.
 __global__ void k_reorth_flag(Krylov kr, int S, int k) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
@@ -933,7 +1018,7 @@ __global__ void k_reorth_flag(Krylov kr, int S, int k) {
     double hn = 0.0;
     for (int i = 0; i <= k; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
     const double wn2 = h1[2 * (k + 1)];
-    const int need = (kr.always_reorth || wn2 - hn < 0.5 * wn2) ? 1 : 0;
+    const int need = (kr.always_reorth || wn2 - hn < kr.reorth_theta * wn2) ? 1 : 0;
     kr.reorth[s] = need;
     if (!need) {
         double* h2 = kr.red2 + (long long)s * (kr.nv1 + 1);
@@ -1017,6 +1102,20 @@ __global__ void k_arnoldi(Krylov kr, int S, int k) {
         kr.kcount[s] = k + 1;
         kr.iter_active[s] = 0;
     }
+}
+
+// Summary flags for the host, written to mapped host memory: any system still solving, the
+// non-finite flag, the largest per-system iteration count.
+__global__ void k_publish(Krylov kr, int S, int* pub) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int any = 0, mx = 0;
+    for (int s = 0; s < S; ++s) {
+        any |= kr.solve_active[s];
+        mx = kr.iters[s] > mx ? kr.iters[s] : mx;
+    }
+    pub[0] = any;
+    pub[1] = kr.err[0];
+    pub[2] = mx;
 }
 
 __global__ void k_solve_y(Krylov kr, int S) {
@@ -1427,6 +1526,51 @@ template void launch_precond_cheb<double>(const Dev&, const CTile*, int, int, co
 template void launch_precond_cheb<float>(const Dev&, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
                                          const int*, hipStream_t);
 
+template <int DIM, int TYv, typename T, int OP>
+static void cb_iterations(const Dev& d, int its, cx<T>* d0, cx<T>* d1, cx<T>* r, cx<T>* xv, const int* mask,
+                          hipStream_t st) {
+    cx<T>* D[2] = {d0, d1};
+    for (int j = 1; j < its; ++j) {
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (j == its - 1 ? 3.0 : 6.0));
+        if (j == its - 1)
+            hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j, D[(j - 1) & 1],
+                               D[j & 1], r, xv);
+        else
+            hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, j,
+                               D[(j - 1) & 1], D[j & 1], r, xv);
+    }
+}
+
+template <typename T>
+void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
+                                 cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        constexpr int DIM = D(), TYv = TY();
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 3.0 * sizeof(cx<T>)));
+            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 0>), TILE_GRID, d.sys, d.tiles, mask, v, x1, r, d0, x1, d.NT);
+        }
+        cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 4.0 * sizeof(cx<T>)));
+            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 1>), TILE_GRID, d.sys, d.tiles, mask, v, x1, r, d0, x2, d.NT);
+        }
+        cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, x2, mask, st);
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>));
+            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 2>), TILE_GRID, d.sys, d.tiles, mask, v, x2, r, d0, z + d.NT,
+                               d.NT);
+        }
+        cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, z + d.NT, mask, st);
+        ProbeScope ps(d, KID_PC_FINAL, st);
+        hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);
+    });
+}
+template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, int, int,
+                                                  const int*, hipStream_t);
+template void launch_precond_cheb_unfused<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, int, int,
+                                                 const int*, hipStream_t);
+
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
                        hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
@@ -1515,6 +1659,9 @@ void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t s
 void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);
     hipLaunchKernelGGL(k_arnoldi, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, k);
+}
+void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, kr, d.S, pub);
 }
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);

@@ -267,3 +267,43 @@ def test_preconditioner_matches_oracle(inner, precision, tol, n):
         ref = np.concatenate([c1, c2])
         got = np.concatenate([gz[j], ge[j]])
         assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), (j, np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("inner,precision,tol", [(apfc.APFC_INNER_CHEB, apfc.APFC_FP64, 1e-12),
+                                                 (apfc.APFC_INNER_CHEB, apfc.APFC_MIXED, 2e-5),
+                                                 (apfc.APFC_INNER_PCG, apfc.APFC_FP64, 1e-12)])
+def test_preconditioner_3d_matches_oracle(inner, precision, tol):
+    """bcc lattice on a 12 x 10 x 8 hex mesh: the 3D preconditioner (one launch per Chebyshev
+    iteration, or Jacobi-PCG) vs the oracle's four steps."""
+    h = 60.0 * inputs.BCC_SPACING / 128.0
+    mesh = inputs.Mesh(3, (12, 10, 8), (12 * h, 10 * h, 8 * h))
+    zin, ein = _rand_pair(6, mesh.N, 23)
+    o = oracle_for(mesh, bcc_k(), 0.02)
+    its = (4, 4) if inner == apfc.APFC_INNER_CHEB else (3, 5)
+    s = solver_for([mesh], apfc.APFC_BCC3D, [0.02], inner_kind=inner, precision=precision,
+                   mass_iters=its[0], diff_iters=its[1])
+    zo = torch.zeros((6, 2, mesh.N), dtype=torch.float64, device="cuda")
+    eo = torch.zeros_like(zo)
+    s.apply(apfc.APFC_OP_PINV, [to_dev(zin)], [to_dev(ein)], [zo], [eo], 0.9)
+    gz, ge = from_dev(zo), from_dev(eo)
+    for j in range(6):
+        c1, c2 = o.precond_apply(j, zin[j], ein[j], 0.9, inner="cheb" if inner == apfc.APFC_INNER_CHEB else "pcg",
+                                 mass_iters=its[0], diff_iters=its[1])
+        ref = np.concatenate([c1, c2])
+        got = np.concatenate([gz[j], ge[j]])
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), j
+
+
+@pytest.mark.parametrize("precision", [apfc.APFC_FP64, apfc.APFC_MIXED])
+def test_bcc_3d_chebyshev_step_matches_oracle(precision):
+    h = 60.0 * inputs.BCC_SPACING / 128.0
+    mesh = inputs.Mesh(3, (12, 10, 8), (12 * h, 10 * h, 8 * h))
+    eta0 = inputs.single_grain(mesh, bcc_k(), phi_of(bcc_k())(0.02), math.radians(5.0), 4 * h, seed=5)
+    o = oracle_for(mesh, bcc_k(), 0.02)
+    ref = eta0
+    for _ in range(2):
+        _, ref = o.step(ref, 1.0)
+    s = solver_for([mesh], apfc.APFC_BCC3D, [0.02], rtol=1e-12, precision=precision,
+                   inner_kind=apfc.APFC_INNER_CHEB, mass_iters=4, diff_iters=4, restart=6)
+    got, _, _ = run_gpu(s, [eta0], 1.0, 2)
+    assert rel_l2(got[0], ref) < 1e-9
