@@ -671,11 +671,10 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     const int nv = k + 1;
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
-    launch_reduce(d, c->apart, 0, 2 * nv + 1, false, kr.red1, kr.nv1 + 1, act, st);
-    launch_reorth_flag(d, kr, k, st);
+    // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
+    launch_gs_reduce(d, kr, k, 1, c->apart, st);
     launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, st);
-    launch_reduce(d, c->cpart, 0, 2 * nv + 1, true, kr.red2, kr.nv1 + 1, kr.reorth, st);
-    launch_arnoldi(d, kr, k, st);
+    launch_gs_reduce(d, kr, k, 2, c->cpart, st);
     launch_proj_final(d, c->V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), c->V + (k + 1) * vs, act, st);
 }
 
@@ -1029,40 +1028,56 @@ int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_
 int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
     if (int rc = need_ws(c); rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const int cand[4] = {4, 8, 16, 32};
-    float best = 1e30f;
-    int best_ty = c->TY;
+    // candidates for the tile height of the stencil kernels (operator apply, residual, PCG/3D
+    // Chebyshev sweeps); every candidate is timed on the same unmasked kernel mix, three
+    // interleaved rounds, best round kept
+    const int cand[3] = {8, 16, 32};
+    float best_ms[3] = {1e30f, 1e30f, 1e30f};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     launch_fill_zero(c->V, 2 * c->NT, st);
-    hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, c->kr, c->S);
-    for (int ty : cand) {
-        c->TY = ty;
-        build_tiles(*c, ty, c->tiles);
-        if (int rc = upload_tables(*c); rc) return rc;
-        Dev d = c->dev();
-        d.probe = nullptr;
-        auto body = [&]() { run_iteration(c, d, 0, st); };
-        body();
-        HIPCHK(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r) body();
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_ty = ty;
+    launch_fill_zero(c->X, 2 * c->NT, st);
+    launch_fill_zero(c->B, 2 * c->NT, st);
+    const long long vs = c->vstride();
+    for (int round = 0; round < 3; ++round)
+        for (int ci = 0; ci < 3; ++ci) {
+            const int ty = cand[ci];
+            c->TY = ty;
+            build_tiles(*c, ty, c->tiles);
+            if (int rc = upload_tables(*c); rc) return rc;
+            Dev d = c->dev();
+            d.probe = nullptr;
+            auto body = [&]() {
+                if (c->mixed) {
+                    precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
+                    launch_apply_dot<float>(d, (const zf*)c->Z, c->dnode, c->W, c->V, vs, 2, c->apart, nullptr, st);
+                } else {
+                    precond<double>(c, d, c->V, (zd*)c->Z, nullptr, st);
+                    launch_apply_dot<double>(d, (const zd*)c->Z, c->dnode, c->W, c->V, vs, 2, c->apart, nullptr, st);
+                }
+                launch_reduce(d, c->apart, 0, 5, false, c->kr.red1, c->kr.nv1 + 1, nullptr, st);
+                launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
+            };
+            body();
+            HIPCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; ++r) body();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best_ms[ci] = std::min(best_ms[ci], ms);
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->TY = best_ty;
-    build_tiles(*c, best_ty, c->tiles);
+    int bi = 0;
+    for (int ci = 1; ci < 3; ++ci)
+        if (best_ms[ci] < best_ms[bi]) bi = ci;
+    c->TY = cand[bi];
+    build_tiles(*c, c->TY, c->tiles);
     if (int rc = upload_tables(*c); rc) return rc;
     invalidate_graphs(*c);
-    if (chosen) *chosen = best_ty;
+    if (chosen) *chosen = c->TY;
     return APFC_OK;
 }
 

@@ -459,6 +459,87 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(const Sys* sys, const Tile
     }
 }
 
+// 2D version of k_apply_dot that marches each thread down TY/4 consecutive rows of one column: the
+// x pass (mass, stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept
+// for the next two rows, so each input row is loaded once per field (3 loads instead of 9).
+template <int TY, typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                       long long vstride, int nv, double* part, long long NT,
+                                                       int ntiles) {
+    constexpr int RR = TY / 4;
+    __shared__ double lds[4 * (2 * NV + 1)];
+    TILE_PROLOGUE();
+    (void)ty;
+    const int y0 = tile.y0 + (int)(threadIdx.x >> 6) * RR;
+    const int xc = x < s.nx ? x : s.nx - 1;                  // clamp for loads of ragged tiles
+    const int xm = xc == 0 ? s.nx - 1 : xc - 1, xp = xc == s.nx - 1 ? 0 : xc + 1;
+    const double h = s.h, m0 = h / 6.0, m1 = 4.0 * h / 6.0, ih = 1.0 / h;
+    const double kx = s.kv[0], ky = s.kv[1];
+    const cx<T>* zz = Z + s.off;
+    const cx<T>* ze = Z + NT + s.off;
+    zd mz[3], kz[3], dz[3], me[3], ke[3], de[3], ce[3];
+    double acc[2 * NV + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int a = 0; a < RR + 2; ++a) {
+        int row = y0 - 1 + a;
+        row = row < 0 ? row + s.ny : (row >= s.ny ? row - s.ny : row);
+        const long long rb = (long long)row * s.nx;
+        {
+            const zd l = ld<double>(zz, rb + xm), c = ld<double>(zz, rb + xc), r = ld<double>(zz, rb + xp);
+            mz[2] = m0 * (l + r) + m1 * c;
+            kz[2] = ih * ((c + c) - (l + r));
+            dz[2] = 0.5 * (r - l);
+        }
+        {
+            const zd l = ld<double>(ze, rb + xm), c = ld<double>(ze, rb + xc), r = ld<double>(ze, rb + xp);
+            me[2] = m0 * (l + r) + m1 * c;
+            ke[2] = ih * ((c + c) - (l + r));
+            de[2] = 0.5 * (r - l);
+            ce[2] = c;
+        }
+        if (a >= 2) {
+            const int y = y0 + a - 2;
+            if (x < s.nx && y < s.ny) {
+                auto Msum = [&](const zd* u) { return m0 * (u[0] + u[2]) + m1 * u[1]; };
+                const zd Mz = Msum(mz), Me = Msum(me);
+                const zd Kz = Msum(kz) + ih * ((mz[1] + mz[1]) - (mz[0] + mz[2]));
+                const zd Ke = Msum(ke) + ih * ((me[1] + me[1]) - (me[0] + me[2]));
+                const zd Tz = 2.0 * (kx * Msum(dz) + ky * (0.5 * (mz[2] - mz[0])));
+                const zd Te = 2.0 * (kx * Msum(de) + ky * (0.5 * (me[2] - me[0])));
+                const long long il = (long long)y * s.nx + x;
+                const zd y1 = Mz - gop(Ke, Te);
+                const zd y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dnode[s.doff + il]) * ce[1];
+                W[s.off + il] = y1;
+                W[NT + s.off + il] = y2;
+                acc[2 * NV] += abs2(y1) + abs2(y2);
+#pragma unroll
+                for (int l = 0; l < NV; ++l)
+                    if (l < nv) {
+                        const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
+                        acc[2 * l] += p.x + q.x;
+                        acc[2 * l + 1] += p.y + q.y;
+                    }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            mz[j] = mz[j + 1]; kz[j] = kz[j + 1]; dz[j] = dz[j + 1];
+            me[j] = me[j + 1]; ke[j] = ke[j + 1]; de[j] = de[j + 1]; ce[j] = ce[j + 1];
+        }
+    }
+    block_sum<2 * NV + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < nv; ++l) {
+            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
+            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
+        }
+        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Block preconditioner (Eq. (12), four steps) with fixed-count Jacobi-PCG inner solves.
 // Operator of an inner solve: OP = 0 -> M (diag diagM), OP = 1 -> L = M/sqrt(dt) + sqrt(kappa) K.
@@ -783,12 +864,14 @@ __device__ __forceinline__ void cheb_coef(double th, double de, int j, double& c
     c2 = 2.0 * rn / de;
 }
 
-// r0 of the inner solve (STAGE 0: beta1; 1: beta2 - kappa G x1; 2: M x2), d0 = r0/(theta D), x = d0
+// r0 of the inner solve (STAGE 0: beta1; 1: beta2 - kappa G x1; 2: M x2; 3: G src for the accurate
+// mass solve M zeta = G eta), d0 = r0/(theta D), x = d0
 template <int DIM, int TY, typename T, int STAGE>
 __global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* tiles, const int* mask, const zd* v,
                                                    const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
     TILE_PROLOGUE();
-    constexpr bool isM = STAGE == 0;
+    constexpr bool isM = STAGE == 0 || STAGE == 3;
+    constexpr bool WG = STAGE == 1 || STAGE == 3;
     const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
     FOR_ROWS(TY) {
         Nbr<DIM> n;
@@ -799,10 +882,15 @@ __global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* 
             rv = ld<T>(v, i);
         } else {
             cx<T> Mu, Ku, Tu;
-            stencil<DIM, STAGE == 1, STAGE == 1, T>(
+            stencil<DIM, WG, WG, T>(
                 [&](int a, int b, int c) { return ld<T>(src, s.off + nb_index<DIM>(n, a, b, c)); }, T(s.h),
                 T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
-            rv = STAGE == 1 ? ld<T>(v, NT + i) - T(s.kappa) * gop(Ku, Tu) : Mu;
+            if constexpr (STAGE == 1)
+                rv = ld<T>(v, NT + i) - T(s.kappa) * gop(Ku, Tu);
+            else if constexpr (STAGE == 3)
+                rv = gop(Ku, Tu);
+            else
+                rv = Mu;
         }
         const cx<T> dv = scale * rv;
         r[i] = rv;
@@ -1007,13 +1095,7 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
 // reorth_theta |w|^2.  One classical Gram-Schmidt pass leaves the new basis vector orthogonal to
 // about eps |w| / |w'|, so theta is chosen from rtol (api.hip); otherwise the second pass is
 // skipped and its results set to h2 = 0, |w'|^2 = |w|^2 - |h1|^2.
-__global__ void k_reorth_flag(Krylov kr, int S, int k) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    if (!kr.iter_active[s]) {
-        kr.reorth[s] = 0;
-        return;
-    }
+__device__ int reorth_decide(const Krylov& kr, int s, int k) {
     const double* h1 = kr.red1 + (long long)s * (kr.nv1 + 1);
     double hn = 0.0;
     for (int i = 0; i <= k; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
@@ -1025,11 +1107,22 @@ __global__ void k_reorth_flag(Krylov kr, int S, int k) {
         for (int i = 0; i <= k; ++i) h2[2 * i] = h2[2 * i + 1] = 0.0;
         h2[2 * (k + 1)] = wn2 - hn;
     }
+    return need;
 }
 
-__global__ void k_arnoldi(Krylov kr, int S, int k) {
+__global__ void k_reorth_flag(Krylov kr, int S, int k) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S || !kr.iter_active[s]) return;
+    if (s >= S) return;
+    if (!kr.iter_active[s]) {
+        kr.reorth[s] = 0;
+        return;
+    }
+    (void)reorth_decide(kr, s, k);
+}
+
+// Column k of the Hessenberg matrix from the two projections, Givens rotations, residual estimate,
+// convergence / breakdown / restart decision for system s.
+__device__ void arnoldi_update(const Krylov& kr, int s, int k) {
     const int m = kr.m, nv1 = kr.nv1;
     const double* h1 = kr.red1 + (long long)s * (nv1 + 1);
     const double* h2 = kr.red2 + (long long)s * (nv1 + 1);
@@ -1101,6 +1194,42 @@ __global__ void k_arnoldi(Krylov kr, int S, int k) {
     if (res <= kr.target[s] || breakdown || k + 1 == m) {
         kr.kcount[s] = k + 1;
         kr.iter_active[s] = 0;
+    }
+}
+
+__global__ void k_arnoldi(Krylov kr, int S, int k) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S || !kr.iter_active[s]) return;
+    arnoldi_update(kr, s, k);
+}
+
+// One workgroup per system: sum the 2(k+1)+1 partials of a Gram-Schmidt pass in a fixed order, then
+// (thread 0) PHASE 1: decide on the second pass and, if it is skipped, finish the Arnoldi step;
+// PHASE 2: finish the Arnoldi step with both passes.
+template <int PHASE>
+__global__ __launch_bounds__(kBlock) void k_gs_reduce(const Sys* sys, Krylov kr, int k, const double* part,
+                                                     long long P) {
+    const int si = blockIdx.x;
+    if (PHASE == 1 && !kr.iter_active[si]) {
+        if (threadIdx.x == 0) kr.reorth[si] = 0;
+        return;
+    }
+    if (PHASE == 2 && !kr.reorth[si]) return;
+    const Sys s = sys[si];
+    const int beg = PHASE == 1 ? s.tbeg : s.cbeg, end = PHASE == 1 ? s.tend : s.cend;
+    const int nvals = 2 * (k + 1) + 1;
+    double* out = (PHASE == 1 ? kr.red1 : kr.red2) + (long long)si * (kr.nv1 + 1);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int v = wv; v < nvals; v += 4) {
+        double a = 0.0;
+        for (int t = beg + lane; t < end; t += 64) a += part[v * P + t];
+        a = wave_sum(a);
+        if (lane == 0) out[v] = a;
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (PHASE == 2 || !reorth_decide(kr, si, k)) arnoldi_update(kr, si, k);
     }
 }
 
@@ -1573,11 +1702,15 @@ template void launch_precond_cheb_unfused<float>(const Dev&, const zd*, zf*, zf*
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
                        hipStream_t st) {
+    // zeta = M^{-1} G eta by Chebyshev-Jacobi iterations with the exact bounds of D^{-1} M
+    // ([1/2, 3/2]^dim): the error contracts by (sqrt(3^dim) - 1)/(sqrt(3^dim) + 1) per iteration.
+    (void)q;
+    (void)part;
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
-        hipLaunchKernelGGL((k_cg_init_m<DIM, TYv, double, true>), TILE_GRID, d.sys, d.tiles, nullptr, eta, r, p0,
-                           part, d.ntiles);
-        cg_iterations<DIM, TYv, double, 0>(d, zeta, r, p0, p1, q, part, iters, nullptr, st);
+        hipLaunchKernelGGL((k_cb_init<DIM, TYv, double, 3>), TILE_GRID, d.sys, d.tiles, nullptr, nullptr, eta, r, p0,
+                           zeta, d.NT);
+        cb_iterations<DIM, TYv, double, 0>(d, iters, p0, p1, r, zeta, nullptr, st);
     });
 }
 
@@ -1613,8 +1746,12 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
                   (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) * (1 + nv) + 8.0 / d.J));
     dispatch(d, [&](auto D, auto TY) {
         auto go = [&](auto nvc) {
-            hipLaunchKernelGGL((k_apply_dot<D(), TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
-                               dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+            if constexpr (D() == 2)
+                hipLaunchKernelGGL((k_apply_dot2d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
+                                   dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+            else
+                hipLaunchKernelGGL((k_apply_dot<D(), TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask,
+                                   Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
         };
         if (nv <= 4) go(std::integral_constant<int, 4>{});
         else if (nv <= 8) go(std::integral_constant<int, 8>{});
@@ -1626,6 +1763,14 @@ template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*
                                        const int*, hipStream_t);
 template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zd*, long long, int, double*,
                                       const int*, hipStream_t);
+
+void launch_gs_reduce(const Dev& d, const Krylov& kr, int k, int phase, const double* part, hipStream_t st) {
+    ProbeScope ps(d, KID_REDUCE, st);
+    if (phase == 1)
+        hipLaunchKernelGGL(k_gs_reduce<1>, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, k, part, (long long)d.ntiles);
+    else
+        hipLaunchKernelGGL(k_gs_reduce<2>, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, k, part, (long long)d.nchunks);
+}
 
 void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);
