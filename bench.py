@@ -80,14 +80,16 @@ def run_gpu(args, precision, probe=None):
     lat, wls, dim = make_workload(args)
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
     inner = apfc.APFC_INNER_CHEB if args.inner == "cheb" else apfc.APFC_INNER_PCG
-    mi = args.mass_iters or (4 if args.inner == "cheb" else 3)
-    di = args.diff_iters or (4 if args.inner == "cheb" else 5)
+    mi = args.mass_iters or (5 if args.inner == "cheb" else 3)
+    di = args.diff_iters or (3 if args.inner == "cheb" else 5)
     ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=prec, inner_kind=inner,
                                    restart=args.restart, mass_iters=mi, diff_iters=di) for w in wls]
     ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
     s = apfc.Solver(ms, lat, ps)
     s.set_graphs(args.graphs)
-    ty = None if args.no_autotune else s.autotune()
+    if not args.no_autotune:
+        s.autotune()
+    ty = s.get_tiles()
     ets = [torch.tensor(inputs.to_planar(w.eta0), dtype=torch.float64, device="cuda") for w in wls]
     zts = [torch.zeros_like(e) for e in ets]
     s.init_zeta(ets, zts)
@@ -179,7 +181,9 @@ def main():
         "config": {"workload": args.workload, "instances": res["instances"], "first_instance": res["mesh"],
                    "amplitude_dofs": res["dofs"], "J": res["J"], "dt": 1.0, "rtol": 1e-8,
                    "precision": args.precision, "inner": args.inner, "restart": args.restart,
-                   "tile_rows": res["tile_rows"], "graphs": bool(args.graphs)},
+                   "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
+                   "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
+                   "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "graphs": bool(args.graphs)},
         "fgmres_iters_per_step": float(np.mean(res["iters"])),
         "final_relres": res["relres"],
     }

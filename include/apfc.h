@@ -174,6 +174,26 @@ enum { APFC_OP_A = 0, APFC_OP_PINV = 1 };
 int apfc_apply(apfc_ctx* ctx, int which, const apfc_state* lin, const apfc_state* in, apfc_state* out,
                double dt, void* stream);
 
+/* Parameters of the refinement indicator of Sec. II.C (Eq. (16)-(17)). */
+typedef struct {
+    double n_per_wavelength;  /* n: h_amp = min_j lambda_j(theta) / n (the paper uses n >= 10)   */
+    double grad_A_eps;        /* epsilon: h = h_int where |grad A| >= epsilon                    */
+    double A_min;             /* a node is solid ("A > 0") where A > A_min                        */
+    double h_int, h_max;      /* finest and coarsest mesh size                                    */
+    double tiny;              /* amplitudes with |eta_j|^2 <= tiny carry no phase                 */
+} apfc_refine_params;
+
+/* Local lattice rotation and target mesh size at every node (a post-step analysis; Eq. (14)-(17)).
+ * omega_ab = (du_a/dx_b - du_b/dx_a)/2 where k_j . u = arg eta_j (Eq. (14)-(15)); the phase gradients
+ * are Im(conj(eta_j) grad eta_j)/|eta_j|^2 with central differences, and du/dx_b is the least-squares
+ * solution over the amplitudes with |eta_j|^2 > tiny (omega = 0 where fewer than dim remain).
+ * omega[count]: device arrays of N doubles (2D: omega_12) or [3][N] (3D: omega_23, omega_31,
+ * omega_12).  h[count] (may be NULL): device arrays of N doubles with
+ *   h = h_int if |grad A| >= eps;  min(max(h_amp, h_int), h_max) if A > A_min;  h_max otherwise,
+ * h_amp = min_j 2 pi / (2 |k_j| sin(theta/2)) / n, theta = asin(max_d |omega_d|) (Eq. (16)-(17)). */
+int apfc_rotation(apfc_ctx* ctx, const apfc_state* states, double* const* omega, double* const* h,
+                  const apfc_refine_params* params, void* stream);
+
 /* Kernel timing probe: when enabled, every launch of the kernel named `name` inside
  * apfc_step is bracketed by HIP events on the launch stream; apfc_probe_read returns the
  * number of launches and their summed duration since the last reset. */
@@ -184,7 +204,13 @@ int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* byte
  * workspace and keeps the fastest.  Optional; the default tile is used otherwise. */
 int apfc_autotune(apfc_ctx* ctx, void* stream, int* chosen_tile_rows);
 
-/* Use hipGraph replays for the FGMRES iterations (1, default) or direct launches (0). */
+/* Set the tiling by hand instead of apfc_autotune: tile_rows in {4, 8, 16, 32} (rows of the 64-wide
+ * stencil tiles) and precond_region in {0, 1, 2} (LDS region of the fused 2D Chebyshev
+ * preconditioner: 128x32 nodes / 512 threads, 64x32 / 256, 64x64 / 512).  Needs the workspace. */
+int apfc_set_tiles(apfc_ctx* ctx, int tile_rows, int precond_region);
+int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
+
+/* Use hipGraph replays of whole restart cycles (1) or direct launches (0, default). */
 int apfc_set_graphs(apfc_ctx* ctx, int enable);
 
 int apfc_destroy(apfc_ctx* ctx);

@@ -599,3 +599,64 @@ def model_spectrum(q: np.ndarray, k: float = 1.0, kappa: float = 1.0, tau: float
         P = np.array([[1.0, 0.0], [-kappa * g, s]]) @ np.array([[1.0, -qq * qq], [0.0, s]])
         out.append(np.linalg.eigvals(A @ np.linalg.inv(P)))
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------------------
+# Local lattice rotation and the refinement indicator (Sec. II.C, Eq. (13)-(17))
+# ---------------------------------------------------------------------------------------
+
+def nodal_gradient(grid: Grid, f: np.ndarray) -> np.ndarray:
+    """Central differences on the periodic grid: (f(x + h e_d) - f(x - h e_d)) / (2h), shape (dim, ...)."""
+    shape = tuple(grid.n[: grid.dim][::-1])            # numpy order (z, y, x) / (y, x)
+    F = f.reshape(f.shape[:-1] + shape)
+    out = []
+    for d in range(grid.dim):
+        ax = F.ndim - 1 - d
+        out.append(((np.roll(F, -1, axis=ax) - np.roll(F, 1, axis=ax)) / (2.0 * grid.h)).reshape(f.shape))
+    return np.stack(out)
+
+
+def rotation_field(grid: Grid, k: np.ndarray, eta: np.ndarray, tiny: float = 1e-12):
+    """Rotation omega_ab = (du_a/dx_b - du_b/dx_a)/2 (Eq. (14)) of the displacement u defined by
+    k_j . u = arg eta_j (Eq. (15)).  Phase gradients avoid unwrapping:
+    grad arg eta_j = Im(conj(eta_j) grad eta_j)/|eta_j|^2 with central differences; the per-node
+    system k_j . (du/dx_b) = d arg eta_j/dx_b is solved in the least-squares sense over the
+    amplitudes with |eta_j|^2 > tiny (reading: the paper cites explicit formulas elsewhere).
+    Returns omega with shape (N,) in 2D (omega_12) and (3, N) in 3D (omega_23, omega_31, omega_12)."""
+    dim = grid.dim
+    J = len(k)
+    kk = np.asarray(k, float)[:, :dim]
+    grad_eta = nodal_gradient(grid, eta)                          # (dim, J, N)
+    mag2 = np.abs(eta) ** 2
+    ok = mag2 > tiny
+    dtheta = np.where(ok[None], np.imag(np.conj(eta)[None] * grad_eta) / np.where(ok, mag2, 1.0)[None], 0.0)
+    N = eta.shape[1]
+    Gu = np.zeros((N, dim, dim))                                  # Gu[n, a, b] = du_a/dx_b
+    for n in range(N):
+        sel = ok[:, n]
+        if sel.sum() < dim:
+            continue
+        Ks = kk[sel]
+        Ainv = np.linalg.inv(Ks.T @ Ks)
+        for b in range(dim):
+            Gu[n, :, b] = Ainv @ (Ks.T @ dtheta[b, sel, n])
+    if dim == 2:
+        return 0.5 * (Gu[:, 0, 1] - Gu[:, 1, 0])
+    return np.stack([0.5 * (Gu[:, 1, 2] - Gu[:, 2, 1]), 0.5 * (Gu[:, 2, 0] - Gu[:, 0, 2]),
+                     0.5 * (Gu[:, 0, 1] - Gu[:, 1, 0])])
+
+
+def refinement_h(grid: Grid, k: np.ndarray, eta: np.ndarray, omega: np.ndarray, n_per_wavelength: float,
+                 eps: float, A_min: float, h_int: float, h_max: float):
+    """Target mesh size of Eq. (17): h_int where |grad A| >= eps; min(max(h_amp, h_int), h_max) where
+    A > A_min; h_max elsewhere, with h_amp = min_j lambda_j(theta)/n (Eq. (16)), theta = asin of the
+    largest rotation component, lambda_j(theta) = 2 pi/|dk_j(theta)| and |dk_j| = 2 |k_j| sin(theta/2)."""
+    A = 2.0 * np.sum(np.abs(eta) ** 2, axis=0)
+    gA = np.sqrt(np.sum(nodal_gradient(grid, A[None])[:, 0] ** 2, axis=0))
+    om = np.abs(omega) if omega.ndim == 1 else np.max(np.abs(omega), axis=0)
+    theta = np.arcsin(np.minimum(om, 1.0))
+    kmax = np.max(np.linalg.norm(np.asarray(k, float), axis=1))
+    with np.errstate(divide="ignore"):
+        lam = np.where(theta > 0, 2.0 * np.pi / (2.0 * kmax * np.sin(0.5 * theta)), np.inf)
+    h_amp = lam / n_per_wavelength
+    return np.where(gA >= eps, h_int, np.where(A > A_min, np.minimum(np.maximum(h_amp, h_int), h_max), h_max))

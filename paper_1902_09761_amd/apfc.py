@@ -30,8 +30,8 @@ APFC_OP_A, APFC_OP_PINV = 0, 1
 
 EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_create",
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
-           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_probe_enable", "apfc_probe_read",
-           "apfc_autotune", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
+           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read",
+           "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
 
 
 class apfc_mesh(ctypes.Structure):
@@ -55,6 +55,11 @@ class apfc_state(ctypes.Structure):
 class apfc_stats(ctypes.Structure):
     _fields_ = [("total_iters", c_int), ("max_iters", c_int), ("cycles", c_int), ("max_relres", c_double),
                 ("ms", c_double), ("iters", POINTER(c_int))]
+
+
+class apfc_refine_params(ctypes.Structure):
+    _fields_ = [("n_per_wavelength", c_double), ("grad_A_eps", c_double), ("A_min", c_double), ("h_int", c_double),
+                ("h_max", c_double), ("tiny", c_double)]
 
 
 class APFCError(RuntimeError):
@@ -94,9 +99,12 @@ def lib() -> ctypes.CDLL:
         "apfc_step_adjoint": (c_int, [c_void_p, P(apfc_state), P(apfc_state), c_double, P(c_void_p),
                                       P(c_void_p), P(c_double), c_void_p, P(apfc_stats)]),
         "apfc_apply": (c_int, [c_void_p, c_int, P(apfc_state), P(apfc_state), P(apfc_state), c_double, c_void_p]),
+        "apfc_rotation": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_void_p), P(apfc_refine_params), c_void_p]),
         "apfc_probe_enable": (c_int, [c_void_p, c_char_p]),
         "apfc_probe_read": (c_int, [c_void_p, P(c_int), P(c_double), P(c_double)]),
         "apfc_autotune": (c_int, [c_void_p, c_void_p, P(c_int)]),
+        "apfc_set_tiles": (c_int, [c_void_p, c_int, c_int]),
+        "apfc_get_tiles": (c_int, [c_void_p, P(c_int), P(c_int)]),
         "apfc_set_graphs": (c_int, [c_void_p, c_int]),
         "apfc_destroy": (c_int, [c_void_p]),
         "apfc_status_string": (c_char_p, [c_int]),
@@ -278,10 +286,27 @@ class Solver:
         _check(lib().apfc_apply(self.ctx, which, lin, self._states(in_etas, in_zetas),
                                 self._states(out_etas, out_zetas), float(dt), _stream_handle(stream)))
 
+    def rotation(self, etas, omegas, hs=None, n_per_wavelength=10.0, grad_A_eps=1e-2, A_min=1e-3, h_int=2.0,
+                 h_max=40.0, tiny=1e-12, stream=None):
+        """Local rotation omega (and the refinement indicator h) of every instance; omegas[b] is a
+        float64 CUDA tensor of N (2D) or 3*N (3D) values, hs[b] of N values."""
+        rp = apfc_refine_params(n_per_wavelength, grad_A_eps, A_min, h_int, h_max, tiny)
+        om = (c_void_p * self.count)(*[o.data_ptr() for o in omegas])
+        hp = (c_void_p * self.count)(*[t.data_ptr() for t in hs]) if hs is not None else None
+        _check(lib().apfc_rotation(self.ctx, self._states(etas), om, hp, byref(rp), _stream_handle(stream)))
+
     def autotune(self, stream=None) -> int:
         ty = c_int()
         _check(lib().apfc_autotune(self.ctx, _stream_handle(stream), byref(ty)))
         return ty.value
+
+    def set_tiles(self, tile_rows: int, precond_region: int = 0):
+        _check(lib().apfc_set_tiles(self.ctx, int(tile_rows), int(precond_region)))
+
+    def get_tiles(self):
+        ty, reg = c_int(), c_int()
+        _check(lib().apfc_get_tiles(self.ctx, byref(ty), byref(reg)))
+        return ty.value, reg.value
 
     def set_graphs(self, enable: bool):
         _check(lib().apfc_set_graphs(self.ctx, 1 if enable else 0))

@@ -44,8 +44,9 @@ struct Sys {
 struct Tile { int sys, x0, y0, z; };
 // Interior tile of the fused Chebyshev preconditioner kernels (region = interior + halo).
 struct CTile { int sys, x0, y0, z; };
-constexpr int kChebRX = 128;      // region width (x) of the fused preconditioner tiles
-constexpr int kChebRY = 32;       // region height (y)
+// LDS region shapes (width, height, threads) of the fused preconditioner kernels.
+constexpr int kChebShapes = 3;
+constexpr int kChebShape[kChebShapes][3] = {{128, 32, 512}, {64, 32, 256}, {64, 64, 512}};
 struct Chunk { int sys; int e0; };     // element offset inside the system's 2N-element full vector
 
 // Resonant products of the bulk energy with distinct amplitude indices: term value
@@ -143,8 +144,8 @@ void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, c
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
 template <typename T>
-void launch_precond_cheb(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
-                         cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
+                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
@@ -176,6 +177,12 @@ void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd*
 void launch_energy_parts(const Dev& d, const zd* eta, const zd* zeta, double* part, hipStream_t st);
 void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* const* grad_tab, double* part,
                         hipStream_t st);
+struct RefineArgs {
+    double inv_KtK[3][3];      // (sum_j k_j k_j^T)^{-1} is formed per node; kmax = max_j |k_j|
+    double kmax, nwl, eps, Amin, hint, hmax, tiny;
+};
+void launch_rotation(const Dev& d, const zd* eta, double* const* omega_tab, double* const* h_tab, const RefineArgs& ra,
+                     hipStream_t st);
 void launch_adjoint_rhs(const Dev& d, double* const* lam_tab, zd* B, hipStream_t st);
 void launch_adjoint_out(const Dev& d, const zd* Y, const zd* eta_prev, double* const* eta_new_tab,
                         double* const* lam_out_tab, double* part, hipStream_t st);

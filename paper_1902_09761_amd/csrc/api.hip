@@ -125,6 +125,8 @@ struct apfc_ctx {
     std::vector<Chunk> chunks;
     std::vector<CTile> ctiles;
     CTile* d_ctiles = nullptr;
+    int cheb_shape = 0;
+    size_t max_ctiles = 0;
     long long NT = 0, NI = 0;
     int TY = 16;
     int max_tiles = 0;
@@ -158,7 +160,7 @@ struct apfc_ctx {
     double* h_dbl = nullptr;
 
     Probe probe;
-    bool use_graphs = true;
+    bool use_graphs = false;
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs;
     bool graphs_valid = false;
@@ -244,7 +246,7 @@ int cheb_halo(const apfc_params& p) { return std::max(p.mass_iters - 1, p.diff_i
 void build_ctiles(apfc_ctx& c) {
     c.ctiles.clear();
     const int H = cheb_halo(c.solver);
-    const int IX = kChebRX - 2 * H, IY = kChebRY - 2 * H;
+    const int IX = kChebShape[c.cheb_shape][0] - 2 * H, IY = kChebShape[c.cheb_shape][1] - 2 * H;
     for (int s = 0; s < c.S; ++s) {
         const Sys& y = c.sys[s];
         for (int z = 0; z < y.nz; ++z)
@@ -284,7 +286,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.d_sys = (Sys*)take(sizeof(Sys) * S);
     c.d_tiles = (Tile*)take(sizeof(Tile) * c.max_tiles);
     c.d_chunks = (Chunk*)take(sizeof(Chunk) * c.chunks.size());
-    c.d_ctiles = (CTile*)take(sizeof(CTile) * std::max<size_t>(1, c.ctiles.size()));
+    c.d_ctiles = (CTile*)take(sizeof(CTile) * std::max<size_t>(1, c.max_ctiles));
     c.d_tab = (double**)take(sizeof(double*) * 4 * c.count);
     c.X = (zd*)take(sizeof(zd) * 2 * NT);
     c.B = (zd*)take(sizeof(zd) * 2 * NT);
@@ -498,6 +500,11 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
             delete c;
             return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB needs mass_iters <= 13 and diff_iters <= 12");
         }
+        if (dim == 2 && cheb_halo(params[0]) > 8) {
+            // the smaller region shapes need interior tiles of at least 16 x 16
+            delete c;
+            return fail(APFC_ERR_INVALID, "APFC_INNER_CHEB in 2D needs mass_iters <= 9 and diff_iters <= 8");
+        }
     }
     c->S = count * c->J;
     long long off = 0, doff = 0;
@@ -551,7 +558,15 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
     c->TY = 16;
     build_tiles(*c, c->TY, c->tiles);
     set_dt_scalars(*c, 1.0);
-    if (params[0].inner_kind == APFC_INNER_CHEB && dim == 2) build_ctiles(*c);
+    if (params[0].inner_kind == APFC_INNER_CHEB && dim == 2) {
+        for (int sh = 0; sh < kChebShapes; ++sh) {
+            c->cheb_shape = sh;
+            build_ctiles(*c);
+            c->max_ctiles = std::max(c->max_ctiles, c->ctiles.size());
+        }
+        c->cheb_shape = 0;
+        build_ctiles(*c);
+    }
     *out = c;
     return APFC_OK;
 }
@@ -650,7 +665,8 @@ template <typename T>
 void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, hipStream_t st) {
     cx<T>** pc = (cx<T>**)c->pc;
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
-        launch_precond_cheb<T>(d, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z, pc[0], pc[1],
+        launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
+                               pc[0], pc[1],
                                c->solver.mass_iters, c->solver.diff_iters, mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB)
         launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
@@ -988,6 +1004,66 @@ int apfc_apply(apfc_ctx* c, int which, const apfc_state* lin, const apfc_state* 
     return APFC_OK;
 }
 
+int apfc_rotation(apfc_ctx* c, const apfc_state* states, double* const* omega, double* const* h,
+                  const apfc_refine_params* rp, void* stream) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, false); rc) return rc;
+    if (!omega || !rp) return fail(APFC_ERR_INVALID, "omega and params are required");
+    if (!(rp->n_per_wavelength > 0.0) || !(rp->h_int > 0.0) || !(rp->h_max >= rp->h_int) || !(rp->tiny >= 0.0))
+        return fail(APFC_ERR_INVALID, "refine params: need n > 0, 0 < h_int <= h_max, tiny >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<const void*> t[3];
+    for (int b = 0; b < c->count; ++b) {
+        if (!omega[b] || (h && !h[b])) return fail(APFC_ERR_INVALID, "omega[b] / h[b] is NULL");
+        t[0].push_back(states[b].eta);
+        t[1].push_back(omega[b]);
+        t[2].push_back(h ? h[b] : nullptr);
+    }
+    if (int rc = upload_ptrs(c, t, 3, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    RefineArgs ra{};
+    ra.kmax = 0.0;
+    for (int j = 0; j < c->J; ++j) {
+        double n2 = 0.0;
+        for (int q = 0; q < 3; ++q) n2 += c->lattice.k[j][q] * c->lattice.k[j][q];
+        ra.kmax = std::max(ra.kmax, std::sqrt(n2));
+    }
+    ra.nwl = rp->n_per_wavelength;
+    ra.eps = rp->grad_A_eps;
+    ra.Amin = rp->A_min;
+    ra.hint = rp->h_int;
+    ra.hmax = rp->h_max;
+    ra.tiny = rp->tiny;
+    launch_state_in(d, tab(c, 0), nullptr, c->X, st);
+    launch_rotation(d, c->X + c->NT, tab(c, 1), h ? tab(c, 2) : nullptr, ra, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return APFC_OK;
+}
+
+int apfc_set_tiles(apfc_ctx* c, int tile_rows, int precond_region) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (tile_rows != 4 && tile_rows != 8 && tile_rows != 16 && tile_rows != 32)
+        return fail(APFC_ERR_INVALID, "tile_rows must be 4, 8, 16 or 32");
+    if (precond_region < 0 || precond_region >= kChebShapes) return fail(APFC_ERR_INVALID, "precond_region must be 0, 1 or 2");
+    c->TY = tile_rows;
+    build_tiles(*c, c->TY, c->tiles);
+    if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2) {
+        c->cheb_shape = precond_region;
+        build_ctiles(*c);
+    }
+    invalidate_graphs(*c);
+    return upload_tables(*c);
+}
+
+int apfc_get_tiles(const apfc_ctx* c, int* tile_rows, int* precond_region) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    if (tile_rows) *tile_rows = c->TY;
+    if (precond_region) *precond_region = c->cheb_shape;
+    return APFC_OK;
+}
+
 int apfc_set_graphs(apfc_ctx* c, int enable) {
     if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
     c->use_graphs = enable != 0;
@@ -1076,6 +1152,43 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
     c->TY = cand[bi];
     build_tiles(*c, c->TY, c->tiles);
     if (int rc = upload_tables(*c); rc) return rc;
+    // region shape of the fused 2D Chebyshev preconditioner
+    if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2) {
+        float best_sh[kChebShapes];
+        for (int sh = 0; sh < kChebShapes; ++sh) best_sh[sh] = 1e30f;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (int round = 0; round < 3; ++round)
+            for (int sh = 0; sh < kChebShapes; ++sh) {
+                c->cheb_shape = sh;
+                build_ctiles(*c);
+                if (int rc = upload_tables(*c); rc) return rc;
+                Dev d = c->dev();
+                d.probe = nullptr;
+                auto body = [&]() {
+                    if (c->mixed)
+                        precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
+                    else
+                        precond<double>(c, d, c->V, (zd*)c->Z, nullptr, st);
+                };
+                body();
+                HIPCHK(hipEventRecord(e0, st));
+                for (int r = 0; r < 3; ++r) body();
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                best_sh[sh] = std::min(best_sh[sh], ms);
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        int bs = 0;
+        for (int sh = 1; sh < kChebShapes; ++sh)
+            if (best_sh[sh] < best_sh[bs]) bs = sh;
+        c->cheb_shape = bs;
+        build_ctiles(*c);
+        if (int rc = upload_tables(*c); rc) return rc;
+    }
     invalidate_graphs(*c);
     if (chosen) *chosen = c->TY;
     return APFC_OK;

@@ -762,11 +762,11 @@ __device__ __forceinline__ void col_sweep(const cx<T>* buf, int px, int r0, int 
     }
 }
 
-template <typename T, int STAGE, int NTH>
+template <typename T, int STAGE, int RX, int RY, int NTH>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
                                                cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
                                                long long NT) {
-    constexpr int RX = kChebRX, RY = kChebRY, RP = RX * RY, NP = RP / NTH;
+    constexpr int RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
     __shared__ cx<T> buf[RP];
     const CTile tile = tiles[blockIdx.x];
@@ -1343,6 +1343,101 @@ __global__ __launch_bounds__(kBlock) void k_energy_grad(const Sys* sys, const Ti
     if (threadIdx.x == 0) part[kE1 * (long long)ntiles + blockIdx.x] = acc[0];
 }
 
+// Local rotation (Eq. (14)-(15)) and target mesh size (Eq. (16)-(17)) at every node of an instance
+// (launched on the amplitude-0 tiles).  Phase gradients from central differences of eta_j,
+// du/dx_b by least squares over the amplitudes carrying a phase.
+template <int DIM, int TY>
+__global__ __launch_bounds__(kBlock) void k_rotation(const Sys* sys, const Tile* tiles, const Terms T, const zd* eta,
+                                                    double* const* omega_tab, double* const* h_tab, RefineArgs ra) {
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    if (s.j != 0) return;
+    double* om = omega_tab[s.inst];
+    double* hh = h_tab ? h_tab[s.inst] : nullptr;
+    const int J = T.J;
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, tile.z, n);
+        const long long il = nb_index<DIM>(n, 1, 1, 1);
+        double KtK[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double rhs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};     // rhs[b][a'] = sum_j k_{j,a'} d theta_j/dx_b
+        double Ac = 0.0, gA[3] = {0, 0, 0};
+        for (int l = 0; l < J; ++l) {
+            const Sys& sl = sys[tile.sys + l];
+            const zd* e = eta + sl.off;
+            const zd c = e[il];
+            const double m2 = abs2(c);
+            Ac += 2.0 * m2;
+            const bool ok = m2 > ra.tiny;
+            for (int b = 0; b < DIM; ++b) {
+                const long long ip = b == 0 ? nb_index<DIM>(n, 2, 1, 1) : (b == 1 ? nb_index<DIM>(n, 1, 2, 1) : nb_index<DIM>(n, 1, 1, 2));
+                const long long im = b == 0 ? nb_index<DIM>(n, 0, 1, 1) : (b == 1 ? nb_index<DIM>(n, 1, 0, 1) : nb_index<DIM>(n, 1, 1, 0));
+                const zd ep = e[ip], em = e[im];
+                gA[b] += 2.0 * (abs2(ep) - abs2(em)) / (2.0 * s.h);
+                if (ok) {
+                    const zd de = (0.5 / s.h) * (ep - em);
+                    const double dth = cdot(c, de).y / m2;
+                    for (int a = 0; a < DIM; ++a) rhs[b][a] += sl.kv[a] * dth;
+                }
+            }
+            if (ok)
+                for (int a = 0; a < DIM; ++a)
+                    for (int a2 = 0; a2 < DIM; ++a2) KtK[a][a2] += sl.kv[a] * sl.kv[a2];
+        }
+        // invert the symmetric DIM x DIM matrix
+        double inv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double det, tr = 0.0;
+        for (int a = 0; a < DIM; ++a) tr += KtK[a][a];
+        if constexpr (DIM == 2) {
+            det = KtK[0][0] * KtK[1][1] - KtK[0][1] * KtK[1][0];
+            inv[0][0] = KtK[1][1];
+            inv[1][1] = KtK[0][0];
+            inv[0][1] = -KtK[0][1];
+            inv[1][0] = -KtK[1][0];
+        } else {
+            inv[0][0] = KtK[1][1] * KtK[2][2] - KtK[1][2] * KtK[2][1];
+            inv[0][1] = KtK[0][2] * KtK[2][1] - KtK[0][1] * KtK[2][2];
+            inv[0][2] = KtK[0][1] * KtK[1][2] - KtK[0][2] * KtK[1][1];
+            inv[1][0] = KtK[1][2] * KtK[2][0] - KtK[1][0] * KtK[2][2];
+            inv[1][1] = KtK[0][0] * KtK[2][2] - KtK[0][2] * KtK[2][0];
+            inv[1][2] = KtK[0][2] * KtK[1][0] - KtK[0][0] * KtK[1][2];
+            inv[2][0] = KtK[1][0] * KtK[2][1] - KtK[1][1] * KtK[2][0];
+            inv[2][1] = KtK[0][1] * KtK[2][0] - KtK[0][0] * KtK[2][1];
+            inv[2][2] = KtK[0][0] * KtK[1][1] - KtK[0][1] * KtK[1][0];
+            det = KtK[0][0] * inv[0][0] + KtK[0][1] * inv[1][0] + KtK[0][2] * inv[2][0];
+        }
+        const bool solvable = tr > 0.0 && det > 1e-12 * pow(tr / DIM, (double)DIM);
+        double Gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};         // Gu[a][b] = du_a/dx_b
+        if (solvable)
+            for (int a = 0; a < DIM; ++a)
+                for (int b = 0; b < DIM; ++b) {
+                    double v = 0.0;
+                    for (int a2 = 0; a2 < DIM; ++a2) v += inv[a][a2] * rhs[b][a2];
+                    Gu[a][b] = v / det;
+                }
+        double omax;
+        if constexpr (DIM == 2) {
+            const double w = 0.5 * (Gu[0][1] - Gu[1][0]);
+            om[il] = w;
+            omax = fabs(w);
+        } else {
+            const double w0 = 0.5 * (Gu[1][2] - Gu[2][1]), w1 = 0.5 * (Gu[2][0] - Gu[0][2]), w2 = 0.5 * (Gu[0][1] - Gu[1][0]);
+            om[il] = w0;
+            om[s.N + il] = w1;
+            om[2 * s.N + il] = w2;
+            omax = fmax(fabs(w0), fmax(fabs(w1), fabs(w2)));
+        }
+        if (hh) {
+            double g2 = 0.0;
+            for (int b = 0; b < DIM; ++b) g2 += gA[b] * gA[b];
+            const double theta = asin(fmin(omax, 1.0));
+            const double lam = theta > 0.0 ? 2.0 * 3.14159265358979323846 / (2.0 * ra.kmax * sin(0.5 * theta)) : INFINITY;
+            const double hamp = lam / ra.nwl;
+            hh[il] = sqrt(g2) >= ra.eps ? ra.hint : (Ac > ra.Amin ? fmin(fmax(hamp, ra.hint), ra.hmax) : ra.hmax);
+        }
+    }
+}
+
 // adjoint right-hand side [0 ; lam_j]
 template <int DIM, int TY>
 __global__ __launch_bounds__(kBlock) void k_adjoint_rhs(const Sys* sys, const Tile* tiles, double* const* lam_tab,
@@ -1630,29 +1725,38 @@ template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, 
 template void launch_precond<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
                                     const int*, hipStream_t);
 
-template <typename T>
-void launch_precond_cheb(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
-                         cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
-    constexpr int NTH = 512;
+template <typename T, int RX, int RY, int NTH>
+static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
+                        cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
     const double pts = (double)d.NT;
     {
         ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + sizeof(cx<T>)));
-        hipLaunchKernelGGL((k_cheb2d<T, 0, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+        hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                            diff_iters, halo, d.NT);
     }
     {
         ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + 2 * sizeof(cx<T>)));
-        hipLaunchKernelGGL((k_cheb2d<T, 1, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+        hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                            diff_iters, halo, d.NT);
     }
     ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>));
-    hipLaunchKernelGGL((k_cheb2d<T, 2, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+    hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                        diff_iters, halo, d.NT);
 }
-template void launch_precond_cheb<double>(const Dev&, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
+
+template <typename T>
+void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
+                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+    switch (shape) {
+        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
+        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
+        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
+    }
+}
+template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
                                           const int*, hipStream_t);
-template void launch_precond_cheb<float>(const Dev&, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
+template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
                                          const int*, hipStream_t);
 
 template <int DIM, int TYv, typename T, int OP>
@@ -1823,6 +1927,12 @@ void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* con
     dispatch(d, [&](auto D, auto TY) {
         hipLaunchKernelGGL((k_energy_grad<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta, zeta, grad_tab, part,
                            d.ntiles);
+    });
+}
+void launch_rotation(const Dev& d, const zd* eta, double* const* omega_tab, double* const* h_tab, const RefineArgs& ra,
+                     hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        hipLaunchKernelGGL((k_rotation<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta, omega_tab, h_tab, ra);
     });
 }
 void launch_adjoint_rhs(const Dev& d, double* const* lam_tab, zd* B, hipStream_t st) {

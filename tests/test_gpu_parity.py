@@ -247,8 +247,8 @@ def test_operator_A_matches_oracle():
                                                  (apfc.APFC_INNER_PCG, apfc.APFC_MIXED, 2e-5),
                                                  (apfc.APFC_INNER_CHEB, apfc.APFC_FP64, 1e-12),
                                                  (apfc.APFC_INNER_CHEB, apfc.APFC_MIXED, 2e-5)])
-@pytest.mark.parametrize("n", [(40, 28), (256, 192)])
-def test_preconditioner_matches_oracle(inner, precision, tol, n):
+@pytest.mark.parametrize("n,tiles", [((40, 28), (16, 0)), ((256, 192), (8, 1)), ((256, 192), (32, 2)), ((96, 80), (4, 1))])
+def test_preconditioner_matches_oracle(inner, precision, tol, n, tiles):
     """P^{-1} by its four steps on the GPU vs the oracle's four steps with the same inner solver
     (Jacobi-PCG 3/5 or Chebyshev 4/4), element by element."""
     nx, ny = n
@@ -258,6 +258,7 @@ def test_preconditioner_matches_oracle(inner, precision, tol, n):
     its = (4, 4) if inner == apfc.APFC_INNER_CHEB else (3, 5)
     s = solver_for([mesh], apfc.APFC_TRI2D, [0.02], inner_kind=inner, precision=precision,
                    mass_iters=its[0], diff_iters=its[1])
+    s.set_tiles(*tiles)
     zo, eo = torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda"), torch.zeros((3, 2, mesh.N), dtype=torch.float64, device="cuda")
     s.apply(apfc.APFC_OP_PINV, [to_dev(zin)], [to_dev(ein)], [zo], [eo], 0.7)
     gz, ge = from_dev(zo), from_dev(eo)

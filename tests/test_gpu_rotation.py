@@ -1,0 +1,55 @@
+"""Local rotation and refinement indicator (Eq. (14)-(17)) on the GPU vs the oracle's definitions,
+element by element, and the closed form of a rotated crystal.  Needs an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.apfc_oracle import Grid, bcc_k, refinement_h, rotation_field, tri_k
+from paper_1902_09761_amd import apfc, inputs
+from tests.gpu_util import H_TRI, oracle_for, phi_of, solver_for, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+RP = dict(n_per_wavelength=10.0, grad_A_eps=1e-3, A_min=1e-3, h_int=2.0, h_max=40.0, tiny=1e-12)
+
+
+def _gpu(s, eta, ncomp, N):
+    om = torch.zeros(ncomp * N, dtype=torch.float64, device="cuda")
+    h = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s.rotation([to_dev(eta)], [om], [h], **RP)
+    return om.cpu().numpy().reshape(ncomp, N) if ncomp > 1 else om.cpu().numpy(), h.cpu().numpy()
+
+
+def test_rotation_2d_grain_matches_oracle():
+    wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
+    o = oracle_for(wl.mesh, tri_k(), wl.dB)
+    _, eta = o.step(wl.eta0, 1.0)
+    g = o.grid
+    om_ref = rotation_field(g, tri_k(), eta, RP["tiny"])
+    h_ref = refinement_h(g, tri_k(), eta, om_ref, RP["n_per_wavelength"], RP["grad_A_eps"], RP["A_min"],
+                         RP["h_int"], RP["h_max"])
+    s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB])
+    om, h = _gpu(s, eta, 1, g.N)
+    np.testing.assert_allclose(om, om_ref, rtol=1e-10, atol=1e-13)
+    assert np.mean(np.isclose(h, h_ref, rtol=1e-10, atol=0.0)) > 0.999
+    # inside the rotated grain omega is close to sin(5 degrees)
+    r = np.linalg.norm(np.stack(np.meshgrid(np.arange(64), np.arange(64), indexing="xy"), -1).reshape(-1, 2) * g.h
+                       - 0.5 * wl.mesh.length[0], axis=1)
+    core = r < 3.0 * inputs.TRI_SPACING
+    assert abs(np.median(om[core]) - math.sin(math.radians(5.0))) < 0.01
+
+
+def test_rotation_3d_matches_oracle():
+    h = 60.0 * inputs.BCC_SPACING / 128.0
+    mesh = inputs.Mesh(3, (12, 10, 8), (12 * h, 10 * h, 8 * h))
+    eta = inputs.single_grain(mesh, bcc_k(), phi_of(bcc_k())(0.02), math.radians(5.0), 4 * h, seed=5)
+    g = Grid(3, (12, 10, 8), (12 * h, 10 * h, 8 * h))
+    om_ref = rotation_field(g, bcc_k(), eta, RP["tiny"])
+    h_ref = refinement_h(g, bcc_k(), eta, om_ref, RP["n_per_wavelength"], RP["grad_A_eps"], RP["A_min"],
+                         RP["h_int"], RP["h_max"])
+    s = solver_for([mesh], apfc.APFC_BCC3D, [0.02])
+    om, hh = _gpu(s, eta, 3, g.N)
+    np.testing.assert_allclose(om, om_ref, rtol=1e-10, atol=1e-13)
+    assert np.mean(np.isclose(hh, h_ref, rtol=1e-10, atol=0.0)) > 0.999

@@ -529,3 +529,78 @@ def test_chebyshev_converges_to_direct():
     b = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
     x = chebyshev(o.M, b, 60, lo, hi)
     np.testing.assert_allclose(o.M @ x, b, atol=1e-10)
+
+
+# ----------------------------------------------------------------------------------------
+# Local rotation (Eq. (14)-(15)) and refinement indicator (Eq. (16)-(17))
+# ----------------------------------------------------------------------------------------
+
+def _rotated_crystal(g, k, theta, phi=0.2, axis=(0.0, 0.0, 1.0)):
+    from paper_1902_09761_amd import inputs
+    coords = np.stack(np.meshgrid(*[np.arange(g.n[d]) * g.h for d in range(g.dim)][::-1], indexing="ij")[::-1], -1)
+    coords = coords.reshape(-1, g.dim)
+    dk = inputs.delta_k(np.asarray(k, float), theta, axis)
+    return phi * np.exp(1j * coords @ dk.T).T, dk
+
+
+@pytest.mark.parametrize("theta_deg", [3.0, -7.0, 12.0])
+def test_rotation_of_a_rotated_crystal(theta_deg):
+    """eta_j = phi exp(i dk_j . r) with dk_j = R k_j - k_j: the phase gradient is dk_j, u = (R^T - I) r and
+    omega = sin(theta) exactly in the continuum.  With central differences the discrete phase gradient is
+    sin(dk_{j,d} h)/h, so omega is known in closed form at every node away from the periodic seam."""
+    from oracle.apfc_oracle import rotation_field
+    g = Grid(2, (32, 32), (32 * 1.2, 32 * 1.2))
+    th = math.radians(theta_deg)
+    eta, dk = _rotated_crystal(g, tri_k(), th)
+    om = rotation_field(g, tri_k(), eta)
+    K = tri_k()
+    dth = np.sin(dk * g.h) / g.h                                  # (J, dim): d theta_j / dx_d
+    Gu = np.linalg.solve(K.T @ K, K.T @ dth)                      # Gu[a, d] = du_a/dx_d
+    closed = 0.5 * (Gu[0, 1] - Gu[1, 0])
+    inner = np.zeros((32, 32), bool)
+    inner[1:-1, 1:-1] = True
+    np.testing.assert_allclose(om[inner.reshape(-1)], closed, rtol=1e-12)
+    assert abs(closed - math.sin(th)) < 0.01 * abs(math.sin(th))
+
+
+def test_rotation_3d_and_invariances():
+    """bcc crystal rotated about [001]: omega_12 = sin(theta), omega_23 = omega_31 = 0 (to O(h^2));
+    constant phase shifts eta_j -> eta_j exp(i k_j.a) leave omega unchanged; a uniform crystal and
+    the liquid have omega = 0."""
+    from oracle.apfc_oracle import rotation_field
+    g = Grid(3, (12, 12, 12), (12 * 0.8,) * 3)
+    th = math.radians(6.0)
+    eta, _ = _rotated_crystal(g, bcc_k(), th)
+    om = rotation_field(g, bcc_k(), eta)
+    inner = np.zeros((12, 12, 12), bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    m = inner.reshape(-1)
+    np.testing.assert_allclose(om[2][m], math.sin(th), rtol=2e-3)
+    np.testing.assert_allclose(om[0][m], 0.0, atol=1e-12)
+    np.testing.assert_allclose(om[1][m], 0.0, atol=1e-12)
+    shift = np.exp(1j * (bcc_k() @ np.array([0.3, -1.1, 0.7])))[:, None]
+    np.testing.assert_allclose(rotation_field(g, bcc_k(), eta * shift), om, atol=1e-12)
+    np.testing.assert_allclose(rotation_field(g, bcc_k(), np.full((6, g.N), 0.1 + 0j)), 0.0, atol=1e-14)
+    np.testing.assert_allclose(rotation_field(g, bcc_k(), np.zeros((6, g.N), complex)), 0.0, atol=0)
+
+
+def test_refinement_indicator_cases():
+    """Eq. (17) case by case: rotated grain interior -> h_amp = lambda/n clipped to [h_int, h_max];
+    uniform crystal (omega = 0) -> h_max; liquid -> h_max; steep |grad A| -> h_int."""
+    from oracle.apfc_oracle import refinement_h, rotation_field
+    g = Grid(2, (32, 32), (32 * 1.2, 32 * 1.2))
+    th = math.radians(5.0)
+    eta, _ = _rotated_crystal(g, tri_k(), th)
+    om = rotation_field(g, tri_k(), eta)
+    h = refinement_h(g, tri_k(), eta, om, 10.0, 1e-2, 1e-3, 0.5, 40.0)
+    lam = 2 * math.pi / (2 * 1.0 * math.sin(0.5 * math.asin(om[33 * 1 + 40])))
+    assert math.isclose(h[33 + 40], min(max(lam / 10.0, 0.5), 40.0), rel_tol=1e-12)
+    assert 1.0 < lam / 10.0 < 40.0
+    assert np.all(refinement_h(g, tri_k(), np.full((3, g.N), 0.2 + 0j), np.zeros(g.N), 10, 1e-2, 1e-3, 0.5, 40.0) == 40.0)
+    assert np.all(refinement_h(g, tri_k(), np.zeros((3, g.N), complex), np.zeros(g.N), 10, 1e-2, 1e-3, 0.5, 40.0) == 40.0)
+    # a step in A across x: |grad A| large at the step
+    e = np.full((3, g.N), 0.2 + 0j)
+    e[:, (np.arange(g.N) % 32) < 16] = 0.0
+    hs = refinement_h(g, tri_k(), e, np.zeros(g.N), 10, 1e-2, 1e-3, 0.5, 40.0)
+    xs = np.arange(g.N) % 32
+    assert np.all(hs[(xs == 15) | (xs == 16)] == 0.5)
