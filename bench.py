@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--compare", action="store_true", help="also time the other precision on the same workload")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
     ap.add_argument("--restart", type=int, default=4)
+    ap.add_argument("--x0", type=int, default=2, choices=[0, 1, 2],
+                    help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) "
+                         "extrapolation in time")
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)
     ap.add_argument("--probe", default="apply", help="kernel timed with HIP events for the roofline ('none': off)")
@@ -83,7 +86,8 @@ def run_gpu(args, precision, probe=None):
     mi = args.mass_iters or (5 if args.inner == "cheb" else 3)
     di = args.diff_iters or (3 if args.inner == "cheb" else 5)
     ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=prec, inner_kind=inner,
-                                   restart=args.restart, mass_iters=mi, diff_iters=di) for w in wls]
+                                   restart=args.restart, mass_iters=mi, diff_iters=di, x0_order=args.x0)
+          for w in wls]
     ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
     s = apfc.Solver(ms, lat, ps)
     s.set_graphs(args.graphs)
@@ -183,7 +187,8 @@ def main():
                    "precision": args.precision, "inner": args.inner, "restart": args.restart,
                    "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
                    "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
-                   "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "graphs": bool(args.graphs)},
+                   "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "x0_order": args.x0,
+                   "graphs": bool(args.graphs)},
         "fgmres_iters_per_step": float(np.mean(res["iters"])),
         "final_relres": res["relres"],
     }

@@ -30,6 +30,7 @@ APFC_OP_A, APFC_OP_PINV = 0, 1
 
 EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_create",
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
+           "apfc_reset_history",
            "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read",
            "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
 
@@ -45,7 +46,8 @@ class apfc_lattice(ctypes.Structure):
 class apfc_params(ctypes.Structure):
     _fields_ = [("a0", c_double), ("a1", c_double), ("a2", c_double), ("a3", c_double),
                 ("picard_iters", c_int), ("rtol", c_double), ("restart", c_int), ("max_iters", c_int),
-                ("precision", c_int), ("mass_iters", c_int), ("diff_iters", c_int), ("inner_kind", c_int)]
+                ("precision", c_int), ("mass_iters", c_int), ("diff_iters", c_int), ("inner_kind", c_int),
+                ("x0_order", c_int)]
 
 
 class apfc_state(ctypes.Structure):
@@ -94,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "apfc_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
         "apfc_init_zeta": (c_int, [c_void_p, P(apfc_state), c_void_p]),
         "apfc_step": (c_int, [c_void_p, P(apfc_state), c_double, P(c_void_p), c_void_p, P(apfc_stats)]),
+        "apfc_reset_history": (c_int, [c_void_p]),
         "apfc_energy": (c_int, [c_void_p, P(apfc_state), P(c_double), c_void_p]),
         "apfc_energy_grad": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_double), c_void_p]),
         "apfc_step_adjoint": (c_int, [c_void_p, P(apfc_state), P(apfc_state), c_double, P(c_void_p),
@@ -243,6 +246,10 @@ class Solver:
     # -- entry points --------------------------------------------------------------------
     def init_zeta(self, etas, zetas, stream=None):
         _check(lib().apfc_init_zeta(self.ctx, self._states(etas, zetas), _stream_handle(stream)))
+
+    def reset_history(self):
+        """Start a new trajectory for the extrapolated initial guess (params.x0_order > 0)."""
+        _check(lib().apfc_reset_history(self.ctx))
 
     def step(self, etas, zetas, dt: float, source=None, stream=None) -> dict:
         st = apfc_stats()

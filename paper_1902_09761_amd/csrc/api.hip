@@ -150,6 +150,11 @@ struct apfc_ctx {
     double* apart = nullptr;
     Krylov kr{};
     int m = 30;
+    // states passed to the last steps, for the extrapolated initial guess (x0_order > 0):
+    // hist[newest] = x^{m-1}, hist[1 - newest] = x^{m-2}; hist_n of them are valid
+    zd* hist[2] = {nullptr, nullptr};
+    int hist_newest = 0, hist_n = 0;
+    double hist_dt = 0.0;
 
     // host staging (pinned)
     double** h_tab = nullptr;
@@ -193,9 +198,14 @@ void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
     for (int s = 0; s < c.S; ++s) {
         Sys& y = c.sys[s];
         y.tbeg = (int)tiles.size();
-        for (int z = 0; z < y.nz; ++z)
+        if (y.dim == 3) {   // 64 x 4 x TY/4 bricks
+            for (int z0 = 0; z0 < y.nz; z0 += TY / 4)
+                for (int y0 = 0; y0 < y.ny; y0 += 4)
+                    for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, z0});
+        } else {
             for (int y0 = 0; y0 < y.ny; y0 += TY)
-                for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, z});
+                for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, 0});
+        }
         y.tend = (int)tiles.size();
     }
 }
@@ -296,6 +306,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.V = (zd*)take(sizeof(zd) * 2 * NT * (m + 1));
     c.Z = take(zs * 2 * NT * m);
     for (int i = 0; i < 6; ++i) c.pc[i] = take(zs * NT);
+    for (int i = 0; i < 2; ++i) c.hist[i] = c.solver.x0_order > 0 ? (zd*)take(sizeof(zd) * 2 * NT) : nullptr;
     c.dnode = (double*)take(sizeof(double) * c.NI);
     c.tpart = (double*)take(sizeof(double) * kSlots * c.max_tiles);
     c.cpart = (double*)take(sizeof(double) * (2 * kMaxRestart + 2) * c.chunks.size());
@@ -370,6 +381,7 @@ int check_params(const apfc_params& p) {
         return fail(APFC_ERR_INVALID, "params: inner iterations must be in [1,64]");
     if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB)
         return fail(APFC_ERR_INVALID, "params.inner_kind");
+    if (p.x0_order < 0 || p.x0_order > 2) return fail(APFC_ERR_INVALID, "params.x0_order must be 0, 1 or 2");
     return APFC_OK;
 }
 
@@ -422,6 +434,7 @@ void apfc_params_default(apfc_params* p) {
     p->mass_iters = 3;
     p->diff_iters = 5;
     p->inner_kind = APFC_INNER_PCG;
+    p->x0_order = 0;
 }
 
 int apfc_lattice_default(int kind, apfc_lattice* L) {
@@ -477,7 +490,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
         const apfc_params& p = params[b];
         if (p.picard_iters != a.picard_iters || p.rtol != a.rtol || p.restart != a.restart ||
             p.max_iters != a.max_iters || p.precision != a.precision || p.mass_iters != a.mass_iters ||
-            p.diff_iters != a.diff_iters || p.inner_kind != a.inner_kind)
+            p.diff_iters != a.diff_iters || p.inner_kind != a.inner_kind || p.x0_order != a.x0_order)
             return fail(APFC_ERR_INVALID, "solver fields of params[] must be equal across instances");
     }
     if (int rc = check_lattice(*lattice, dim); rc) return rc;
@@ -603,6 +616,7 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
     }
     c->ws = (char*)ptr;
     c->ws_bytes = bytes;
+    c->hist_n = 0;
     carve(*c, c->ws);
     return upload_tables(*c);
 }
@@ -828,10 +842,23 @@ int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* s
     launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
     launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
     int iters = 0;
+    const int order = c->solver.x0_order;
+    if (order > 0 && c->hist_n > 0 && dt != c->hist_dt) c->hist_n = 0;
     for (int k = 0; k < c->solver.picard_iters; ++k) {
         // all amplitudes linearised at the previous iterate (Jacobi splitting)
         launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
+        if (k == 0 && order > 0) {
+            // initial guess extrapolated from the kept states; the state passed in replaces the
+            // oldest one
+            const int use = std::min(order, c->hist_n);
+            zd* older = c->hist[1 - c->hist_newest];
+            launch_extrapolate(d, c->X, c->hist[c->hist_newest], older, use, st);
+            c->hist_newest = 1 - c->hist_newest;
+            c->hist_n = std::min(c->hist_n + 1, 2);
+            c->hist_dt = dt;
+        }
         if (int rc = fgmres(c, st, &iters); rc) {
+            c->hist_n = 0;
             (void)fill_stats(c, st, stats, 0.0);
             return rc;
         }
@@ -842,9 +869,16 @@ int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* s
     return fill_stats(c, st, stats, ms);
 }
 
+int apfc_reset_history(apfc_ctx* c) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    c->hist_n = 0;
+    return APFC_OK;
+}
+
 int apfc_init_zeta(apfc_ctx* c, apfc_state* states, void* stream) {
     if (int rc = need_ws(c); rc) return rc;
     if (int rc = check_states(c, states, true); rc) return rc;
+    c->hist_n = 0;
     hipStream_t st = (hipStream_t)stream;
     std::vector<const void*> t[2];
     for (int b = 0; b < c->count; ++b) {

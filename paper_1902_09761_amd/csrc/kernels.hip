@@ -182,7 +182,93 @@ __device__ __forceinline__ cx<R> gop(cx<R> Ku, cx<R> Tu) {
 }
 
 // ------------------------------------------------------------------------------------------
-// tile iteration: a workgroup covers x in [x0, x0+64) and rows y0 + ty + 4 r (r < TY/4)
+// 3D z-marching.  The x and y passes of the separable stencil at one (x, y) column of one plane are
+// needed by the three output planes z-1, z, z+1; a thread that walks consecutive planes of its
+// column takes them once per plane and keeps the last three in registers, so each input plane is
+// loaded once per field (9 loads instead of 27 per node).  The arithmetic is that of stencil().
+// ------------------------------------------------------------------------------------------
+template <typename R>
+struct Plane {
+    cx<R> m, k, dx, dy, c;   // over x, y: (m m) u, (k m + m k) u, (d m) u, (m d) u; u at (x, y)
+};
+
+template <bool WK, bool WT, typename R, typename F>
+__device__ __forceinline__ Plane<R> plane_pass(const F& f, long long base, const int (&xs)[3],
+                                               const long long (&rs)[3], R m0, R m1, R ih) {
+    const R half = R(0.5);
+    cx<R> mx[3], kx[3], dx[3];
+    Plane<R> p{};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const cx<R> l = f(base + rs[b] + xs[0]), c = f(base + rs[b] + xs[1]), r = f(base + rs[b] + xs[2]);
+        mx[b] = m0 * (l + r) + m1 * c;
+        if (WK) kx[b] = ih * ((c + c) - (l + r));
+        if (WT) dx[b] = half * (r - l);
+        if (b == 1) p.c = c;
+    }
+    p.m = m0 * (mx[0] + mx[2]) + m1 * mx[1];
+    if (WK) p.k = (m0 * (kx[0] + kx[2]) + m1 * kx[1]) + ih * ((mx[1] + mx[1]) - (mx[0] + mx[2]));
+    if (WT) {
+        p.dx = m0 * (dx[0] + dx[2]) + m1 * dx[1];
+        p.dy = half * (mx[2] - mx[0]);
+    }
+    return p;
+}
+
+// z pass: (M u, K u, T_j u) at the middle plane from the plane passes of planes z-1, z, z+1.
+template <bool WK, bool WT, typename R>
+__device__ __forceinline__ void zcombine(const Plane<R>& a, const Plane<R>& b, const Plane<R>& c, R m0, R m1, R ih,
+                                         R k0, R k1, R k2, cx<R>& Mu, cx<R>& Ku, cx<R>& Tu) {
+    Mu = m0 * (a.m + c.m) + m1 * b.m;
+    if (WK) Ku = (m0 * (a.k + c.k) + m1 * b.k) + ih * ((b.m + b.m) - (a.m + c.m));
+    if (WT)
+        Tu = R(2) * (k0 * (m0 * (a.dx + c.dx) + m1 * b.dx) + k1 * (m0 * (a.dy + c.dy) + m1 * b.dy) +
+                     k2 * (R(0.5) * (c.m - a.m)));
+}
+
+// Walks planes z0-1 .. z0+RR of column (xc, yc) (periodic), load(f, i) returning node i of field f;
+// calls emit(z, P) for the output planes z = z0 .. z0+RR-1 (which may pass nz on a ragged brick),
+// P[f][0..2] holding the plane passes of planes z-1, z, z+1.
+template <int RR, int NF, bool WK, bool WT, typename R, typename LOAD, typename EMIT>
+__device__ __forceinline__ void zmarch(const Sys& s, int xc, int yc, int z0, R m0, R m1, R ih, const LOAD& load,
+                                       const EMIT& emit) {
+    const int xs[3] = {xc == 0 ? s.nx - 1 : xc - 1, xc, xc == s.nx - 1 ? 0 : xc + 1};
+    const long long rs[3] = {(long long)(yc == 0 ? s.ny - 1 : yc - 1) * s.nx, (long long)yc * s.nx,
+                             (long long)(yc == s.ny - 1 ? 0 : yc + 1) * s.nx};
+    const long long plane = (long long)s.nx * s.ny;
+    Plane<R> P[NF][3];
+    int zz = z0 == 0 ? s.nz - 1 : z0 - 1;
+#pragma unroll
+    for (int a = 0; a < RR + 2; ++a) {
+        const long long base = zz * plane;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            P[f][2] = plane_pass<WK, WT, R>([&](long long i) { return load(f, i); }, base, xs, rs, m0, m1, ih);
+        if (a >= 2) emit(z0 + a - 2, P);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            P[f][0] = P[f][1];
+            P[f][1] = P[f][2];
+        }
+        zz = zz + 1 == s.nz ? 0 : zz + 1;
+    }
+}
+
+// A_j applied at the middle plane of P (field 0: zeta part, field 1: eta part), as apply_A.
+template <typename PL>
+__device__ __forceinline__ void apply_A_planes(const Sys& s, const PL& P, double m0, double m1, double ih, double dn,
+                                               zd& y1, zd& y2) {
+    zd Mz, Kz, Tz, Me, Ke, Te;
+    zcombine<true, true, double>(P[0][0], P[0][1], P[0][2], m0, m1, ih, s.kv[0], s.kv[1], s.kv[2], Mz, Kz, Tz);
+    zcombine<true, true, double>(P[1][0], P[1][1], P[1][2], m0, m1, ih, s.kv[0], s.kv[1], s.kv[2], Me, Ke, Te);
+    y1 = Mz - gop(Ke, Te);
+    y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dn) * P[1][1].c;
+}
+
+// ------------------------------------------------------------------------------------------
+// tile iteration.  2D: a workgroup covers x in [x0, x0+64) and rows y0 + ty + 4 r (r < TY/4).
+// 3D: a brick x in [x0, x0+64), y = y0 + ty (ty < 4), planes z0 + r (r < TY/4), so a thread walks
+// consecutive planes of one (x, y) column (the order the z-marching stencil kernels rely on).
 // ------------------------------------------------------------------------------------------
 #define TILE_PROLOGUE()                                        \
     const Tile tile = tiles[blockIdx.x];                       \
@@ -191,9 +277,11 @@ __device__ __forceinline__ cx<R> gop(cx<R> Ku, cx<R> Tu) {
     const int x = tile.x0 + (int)(threadIdx.x & 63);           \
     const int ty = (int)(threadIdx.x >> 6);
 
-#define FOR_ROWS(TY)                                           \
-    _Pragma("unroll") for (int rr_ = 0; rr_ < (TY) / 4; ++rr_) \
-        if (const int y = tile.y0 + ty + 4 * rr_; x < s.nx && y < s.ny)
+#define FOR_ROWS(TY)                                                                  \
+    _Pragma("unroll") for (int rr_ = 0; rr_ < (TY) / 4; ++rr_)                        \
+        if (const int y = DIM == 3 ? tile.y0 + ty : tile.y0 + ty + 4 * rr_,             \
+                      pz = DIM == 3 ? tile.z + rr_ : 0;                                 \
+            x < s.nx && y < s.ny && pz < s.nz)
 
 // ------------------------------------------------------------------------------------------
 // state <-> batched vector
@@ -206,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_state_in(const Sys* sys, const Tile*
     const double* e = eta_tab[s.inst] + (long long)s.j * 2 * s.N;
     const double* z = zeta_tab ? zeta_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
     FOR_ROWS(TY) {
-        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         X[NT + s.off + i] = zd{e[i], e[s.N + i]};
         if (z) X[s.off + i] = zd{z[i], z[s.N + i]};
     }
@@ -219,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_state_out(const Sys* sys, const Tile
     double* e = eta_tab[s.inst] + (long long)s.j * 2 * s.N;
     double* z = zeta_tab ? zeta_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
     FOR_ROWS(TY) {
-        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         const zd ve = X[NT + s.off + i];
         e[i] = ve.x;
         e[s.N + i] = ve.y;
@@ -238,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_planar(const Sys* sys, const Tile* t
     TILE_PROLOGUE();
     double* p = tab[s.inst] + (long long)s.j * 2 * s.N;
     FOR_ROWS(TY) {
-        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         if constexpr (IN) {
             half[s.off + i] = zd{p[i], p[s.N + i]};
         } else {
@@ -316,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_base(const Sys* sys, const Tile*
     const double* src = src_tab ? src_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         zd Mu, Ku, Tu;
         stencil<DIM, false, false, double>(
             [&](int a, int b, int c) { return Xeta[s.off + nb_index<DIM>(n, a, b, c)]; }, s.h, s.kv[0], s.kv[1],
@@ -345,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile
     TILE_PROLOGUE();
     if (s.j != 0) return;
     FOR_ROWS(TY) {
-        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         zd eta[kMaxJ], h[kMaxJ];
         for (int l = 0; l < T.J; ++l) eta[l] = eta_half[s.off + l * s.N + i];
         double d;
@@ -387,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Sys* sys, const Tile*
     double acc[2] = {0.0, 0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         const long long il = nb_index<DIM>(n, 1, 1, 1);
         zd y1, y2;
         apply_A<DIM, double>(s, n, X, X + NT, dnode[s.doff + il], y1, y2);
@@ -411,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* ti
     TILE_PROLOGUE();
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         const long long il = nb_index<DIM>(n, 1, 1, 1);
         zd y1, y2;
         apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + il], y1, y2);
@@ -434,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(const Sys* sys, const Tile
     for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         const long long il = s.off + nb_index<DIM>(n, 1, 1, 1);
         zd y1, y2;
         apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + nb_index<DIM>(n, 1, 1, 1)], y1, y2);
@@ -540,6 +628,83 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
     }
 }
 
+// 3D versions of k_apply_dot and k_residual on z-marching bricks (64 x 4 x TY/4 nodes).
+#define BRICK_PROLOGUE()                                                     \
+    TILE_PROLOGUE();                                                         \
+    const int y = tile.y0 + ty;                                              \
+    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;    \
+    const double m0 = s.h * (1.0 / 6.0), m1 = s.h * (4.0 / 6.0), ih = 1.0 / s.h;
+
+template <int TY, typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                       long long vstride, int nv, double* part, long long NT,
+                                                       int ntiles) {
+    __shared__ double lds[4 * (2 * NV + 1)];
+    BRICK_PROLOGUE();
+    const cx<T>* zz = Z + s.off;
+    const cx<T>* ze = Z + NT + s.off;
+    double acc[2 * NV + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+    zmarch<TY / 4, 2, true, true, double>(
+        s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long il = ((long long)z * s.ny + y) * s.nx + x;
+            zd y1, y2;
+            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
+            W[s.off + il] = y1;
+            W[NT + s.off + il] = y2;
+            acc[2 * NV] += abs2(y1) + abs2(y2);
+#pragma unroll
+            for (int l = 0; l < NV; ++l)
+                if (l < nv) {
+                    const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
+                    acc[2 * l] += p.x + q.x;
+                    acc[2 * l + 1] += p.y + q.y;
+                }
+        });
+    block_sum<2 * NV + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < nv; ++l) {
+            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
+            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
+        }
+        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
+    }
+}
+
+template <int TY>
+__global__ __launch_bounds__(kBlock) void k_residual3d(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
+                                                      const zd* B, const double* dnode, zd* R, double* part,
+                                                      long long NT, int ntiles) {
+    __shared__ double lds[8];
+    BRICK_PROLOGUE();
+    const zd* xz = X + s.off;
+    const zd* xe = X + NT + s.off;
+    double acc[2] = {0.0, 0.0};
+    zmarch<TY / 4, 2, true, true, double>(
+        s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return (f == 0 ? xz : xe)[i]; },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long il = ((long long)z * s.ny + y) * s.nx + x;
+            zd y1, y2;
+            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
+            const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
+            const zd r1 = b1 - y1, r2 = b2 - y2;
+            R[s.off + il] = r1;
+            R[NT + s.off + il] = r2;
+            acc[0] += abs2(r1) + abs2(r2);
+            acc[1] += abs2(b1) + abs2(b2);
+        });
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
+        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Block preconditioner (Eq. (12), four steps) with fixed-count Jacobi-PCG inner solves.
 // Operator of an inner solve: OP = 0 -> M (diag diagM), OP = 1 -> L = M/sqrt(dt) + sqrt(kappa) K.
@@ -559,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_copy(const Sys* sys, const T
     const double iD = 1.0 / s.diagM;
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
-        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = s.off + ((long long)pz * s.ny + y) * s.nx + x;
         const cx<T> rv = ld<T>(v, i);
         r[i] = rv;
         p0[i] = T(iD) * rv;
@@ -580,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_g(const Sys* sys, const Tile
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         cx<T> Mu, Ku, Tu;
         stencil<DIM, true, true, T>([&](int a, int b, int c) { return ld<T>(x1, s.off + nb_index<DIM>(n, a, b, c)); },
                                     T(s.h), T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
@@ -607,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_m(const Sys* sys, const Tile
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         cx<T> Mu, Ku, Tu;
         stencil<DIM, GETA, GETA, T>([&](int a, int b, int c) { return ld<T>(x2, s.off + nb_index<DIM>(n, a, b, c)); },
                                     T(s.h), T(s.kv[0]), T(s.kv[1]), T(s.kv[2]), Mu, Ku, Tu);
@@ -641,7 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const Sys* sys, const Tile* 
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         auto fp = [&](int a, int b, int c) {
             const long long i = s.off + nb_index<DIM>(n, a, b, c);
             if constexpr (FIRST)
@@ -677,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const Sys* sys, const Tile
     const double D = op_diag<OP>(s);
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
-        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = s.off + ((long long)pz * s.ny + y) * s.nx + x;
         const cx<T> pv = ld<T>(p, i);
         if constexpr (FIRST)
             xv[i] = alpha * pv;
@@ -702,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_pc_final(const Sys* sys, const Tile*
     TILE_PROLOGUE();
     const T isd = T(s.isq_dt), isk = T(s.isq_kap);
     FOR_ROWS(TY) {
-        const long long i = s.off + ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = s.off + ((long long)pz * s.ny + y) * s.nx + x;
         z[i] = ld<T>(x1, i) - isk * (ld<T>(x2, i) - isd * ld<T>(z, NT + i));
     }
 }
@@ -875,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* 
     const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         const long long i = s.off + nb_index<DIM>(n, 1, 1, 1);
         cx<T> rv;
         if constexpr (STAGE == 0) {
@@ -910,7 +1075,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* 
     const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         cx<T> Mu, Ku, Tu;
         stencil<DIM, OP == 1, false, T>([&](int a, int b, int c) { return ld<T>(din, s.off + nb_index<DIM>(n, a, b, c)); },
                                         T(s.h), T(0), T(0), T(0), Mu, Ku, Tu);
@@ -924,6 +1089,70 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* 
             dout[i] = dv;
         }
     }
+}
+
+// 3D versions of k_cb_init (STAGE 1..3, the stages with a stencil) and k_cb_iter on z-marching
+// bricks; same arithmetic per node.
+template <int TY, typename T, int STAGE>
+__global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile* tiles, const int* mask, const zd* v,
+                                                     const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
+    static_assert(STAGE >= 1 && STAGE <= 3, "stage 0 has no stencil");
+    TILE_PROLOGUE();
+    constexpr bool isM = STAGE == 3;
+    constexpr bool WG = STAGE == 1 || STAGE == 3;
+    const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
+    const int y = tile.y0 + ty;
+    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;
+    const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
+    const T k0 = T(s.kv[0]), k1 = T(s.kv[1]), k2 = T(s.kv[2]);
+    zmarch<TY / 4, 1, WG, WG, T>(
+        s, xc, yc, tile.z, m0, m1, ih, [&](int, long long i) { return ld<T>(src, s.off + i); },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
+            cx<T> Mu, Ku, Tu;
+            zcombine<WG, WG, T>(P[0][0], P[0][1], P[0][2], m0, m1, ih, k0, k1, k2, Mu, Ku, Tu);
+            cx<T> rv;
+            if constexpr (STAGE == 1)
+                rv = ld<T>(v, NT + i) - T(s.kappa) * gop(Ku, Tu);
+            else if constexpr (STAGE == 3)
+                rv = gop(Ku, Tu);
+            else
+                rv = Mu;
+            const cx<T> dv = scale * rv;
+            r[i] = rv;
+            d[i] = dv;
+            xv[i] = dv;
+        });
+}
+
+template <int TY, typename T, int OP, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
+                                                     const cx<T>* din, cx<T>* dout, cx<T>* r, cx<T>* xv) {
+    TILE_PROLOGUE();
+    double c1d, c2d;
+    cheb_coef(OP == 0 ? s.thM : s.thL, OP == 0 ? s.deM : s.deL, j, c1d, c2d);
+    const T c1 = T(c1d), c2 = T(c2d / (OP == 0 ? s.diagM : s.diagL));
+    const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
+    const int y = tile.y0 + ty;
+    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;
+    const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
+    zmarch<TY / 4, 1, OP == 1, false, T>(
+        s, xc, yc, tile.z, m0, m1, ih, [&](int, long long i) { return ld<T>(din, s.off + i); },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
+            cx<T> Mu, Ku, Tu;
+            zcombine<OP == 1, false, T>(P[0][0], P[0][1], P[0][2], m0, m1, ih, T(0), T(0), T(0), Mu, Ku, Tu);
+            const cx<T> q = OP == 0 ? Mu : cM * Mu + cK * Ku;
+            const cx<T> rv = ld<T>(r, i) - q;
+            const cx<T> dv = c1 * P[0][1].c + c2 * rv;
+            xv[i] = ld<T>(xv, i) + dv;
+            if constexpr (!LAST) {
+                r[i] = rv;
+                dout[i] = dv;
+            }
+        });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1284,7 +1513,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const Sys* sys, const Tile* t
     double acc[2] = {0.0, 0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         zd Me, Ke, Te, Mz, Kz, Tz;
         stencil<DIM, true, true, double>([&](int a, int b, int c) { return eta[s.off + nb_index<DIM>(n, a, b, c)]; },
                                          s.h, s.kv[0], s.kv[1], s.kv[2], Me, Ke, Te);
@@ -1319,7 +1548,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_grad(const Sys* sys, const Ti
     double acc[1] = {0.0};
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         zd Mz, Kz, Tz;
         stencil<DIM, true, true, double>([&](int a, int b, int c) { return zeta[s.off + nb_index<DIM>(n, a, b, c)]; },
                                          s.h, s.kv[0], s.kv[1], s.kv[2], Mz, Kz, Tz);
@@ -1357,7 +1586,7 @@ __global__ __launch_bounds__(kBlock) void k_rotation(const Sys* sys, const Tile*
     const int J = T.J;
     FOR_ROWS(TY) {
         Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, tile.z, n);
+        make_nbr<DIM>(s, x, y, pz, n);
         const long long il = nb_index<DIM>(n, 1, 1, 1);
         double KtK[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         double rhs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};     // rhs[b][a'] = sum_j k_{j,a'} d theta_j/dx_b
@@ -1446,7 +1675,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_rhs(const Sys* sys, const Ti
     TILE_PROLOGUE();
     const double* lam = lam_tab[s.inst] + (long long)s.j * 2 * s.N;
     FOR_ROWS(TY) {
-        const long long i = ((long long)tile.z * s.ny + y) * s.nx + x;
+        const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         B[s.off + i] = zd{0.0, 0.0};
         B[NT + s.off + i] = zd{lam[i], lam[s.N + i]};
     }
@@ -1470,7 +1699,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Ti
         const int J = T.J;
         FOR_ROWS(TY) {
             Nbr<DIM> n;
-            make_nbr<DIM>(s, x, y, tile.z, n);
+            make_nbr<DIM>(s, x, y, pz, n);
             const long long il = nb_index<DIM>(n, 1, 1, 1);
             zd ep[kMaxJ], nu[kMaxJ], gr[kMaxJ];
             double C = 0.0;
@@ -1617,6 +1846,28 @@ __global__ __launch_bounds__(kBlock) void k_widen(const zf* in, zd* out, long lo
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
         out[i] = zd{(double)in[i].x, (double)in[i].y};
 }
+// Initial guess from the kept states (order = how many of them are used): x0 = x (order 0),
+// x + (x - h1) (1), h2 + 3 (x - h1) (2), the polynomial through the last order + 1 states evaluated
+// one step ahead.  The state x is written over h2, which becomes the newest kept state.
+__global__ __launch_bounds__(kBlock) void k_extrapolate(zd* X, const zd* h1, zd* h2, long long n, int order) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+        const zd x = X[i];
+        if (order == 1) {
+            X[i] = x + (x - h1[i]);
+        } else if (order == 2) {
+            X[i] = h2[i] + 3.0 * (x - h1[i]);
+        }
+        h2[i] = x;
+    }
+}
+void launch_extrapolate(const Dev& d, zd* X, const zd* h1, zd* h2, int order, hipStream_t st) {
+    ProbeScope ps(d, KID_OTHER, st);
+    const long long n = 2 * d.NT;
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h1, h2, n, order);
+}
+
 void launch_widen(const zf* in, zd* out, long long n, hipStream_t st) {
     if (n <= 0) return;
     long long blocks = (n + kBlock - 1) / kBlock;
@@ -1638,8 +1889,12 @@ void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode
                      const int* mask, hipStream_t st) {
     ProbeScope ps(d, KID_RESIDUAL, st, (double)d.NT * (6.0 * sizeof(zd) + 8.0 / d.J));
     dispatch(d, [&](auto D, auto TY) {
-        hipLaunchKernelGGL((k_residual<D(), TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
-                           d.ntiles);
+        if constexpr (D() == 3)
+            hipLaunchKernelGGL((k_residual3d<TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+                               d.ntiles);
+        else
+            hipLaunchKernelGGL((k_residual<D(), TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+                               d.ntiles);
     });
 }
 template <typename T>
@@ -1759,18 +2014,37 @@ template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, in
 template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
                                          const int*, hipStream_t);
 
+// stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D
+template <int DIM, int TY, typename T, int STAGE>
+static void cb_init_launch(const Dev& d, const int* mask, const zd* v, const cx<T>* src, cx<T>* r, cx<T>* dd,
+                           cx<T>* xv, hipStream_t st) {
+    if constexpr (DIM == 3 && STAGE != 0)
+        hipLaunchKernelGGL((k_cb_init3d<TY, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv, d.NT);
+    else
+        hipLaunchKernelGGL((k_cb_init<DIM, TY, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv, d.NT);
+}
+
 template <int DIM, int TYv, typename T, int OP>
 static void cb_iterations(const Dev& d, int its, cx<T>* d0, cx<T>* d1, cx<T>* r, cx<T>* xv, const int* mask,
                           hipStream_t st) {
     cx<T>* D[2] = {d0, d1};
     for (int j = 1; j < its; ++j) {
         ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (j == its - 1 ? 3.0 : 6.0));
-        if (j == its - 1)
-            hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j, D[(j - 1) & 1],
-                               D[j & 1], r, xv);
-        else
-            hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, j,
-                               D[(j - 1) & 1], D[j & 1], r, xv);
+        if constexpr (DIM == 3) {
+            if (j == its - 1)
+                hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j,
+                                   D[(j - 1) & 1], D[j & 1], r, xv);
+            else
+                hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, j,
+                                   D[(j - 1) & 1], D[j & 1], r, xv);
+        } else {
+            if (j == its - 1)
+                hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j,
+                                   D[(j - 1) & 1], D[j & 1], r, xv);
+            else
+                hipLaunchKernelGGL((k_cb_iter<DIM, TYv, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, j,
+                                   D[(j - 1) & 1], D[j & 1], r, xv);
+        }
     }
 }
 
@@ -1781,18 +2055,17 @@ void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1,
         constexpr int DIM = D(), TYv = TY();
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 3.0 * sizeof(cx<T>)));
-            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 0>), TILE_GRID, d.sys, d.tiles, mask, v, x1, r, d0, x1, d.NT);
+            cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
         }
         cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 4.0 * sizeof(cx<T>)));
-            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 1>), TILE_GRID, d.sys, d.tiles, mask, v, x1, r, d0, x2, d.NT);
+            cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
         }
         cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, x2, mask, st);
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>));
-            hipLaunchKernelGGL((k_cb_init<DIM, TYv, T, 2>), TILE_GRID, d.sys, d.tiles, mask, v, x2, r, d0, z + d.NT,
-                               d.NT);
+            cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, d0, z + d.NT, st);
         }
         cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, z + d.NT, mask, st);
         ProbeScope ps(d, KID_PC_FINAL, st);
@@ -1812,8 +2085,7 @@ void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd*
     (void)part;
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
-        hipLaunchKernelGGL((k_cb_init<DIM, TYv, double, 3>), TILE_GRID, d.sys, d.tiles, nullptr, nullptr, eta, r, p0,
-                           zeta, d.NT);
+        cb_init_launch<DIM, TYv, double, 3>(d, nullptr, nullptr, eta, r, p0, zeta, st);
         cb_iterations<DIM, TYv, double, 0>(d, iters, p0, p1, r, zeta, nullptr, st);
     });
 }
@@ -1854,8 +2126,8 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
                 hipLaunchKernelGGL((k_apply_dot2d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
                                    dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
             else
-                hipLaunchKernelGGL((k_apply_dot<D(), TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask,
-                                   Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+                hipLaunchKernelGGL((k_apply_dot3d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
+                                   dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
         };
         if (nv <= 4) go(std::integral_constant<int, 4>{});
         else if (nv <= 8) go(std::integral_constant<int, 8>{});

@@ -34,6 +34,7 @@ def test_params_default_are_the_papers():
     assert (p.a0, p.a1, p.a2, p.a3) == (0.98, 0.01, 0.25, 0.5)
     assert (p.mass_iters, p.diff_iters) == (3, 5)
     assert p.picard_iters == 1 and p.restart == 30 and p.precision == apfc.APFC_FP64
+    assert p.x0_order == 0   # the state passed in is the initial guess unless asked otherwise
 
 
 def test_lattices():
@@ -84,7 +85,7 @@ def test_argument_checks():
     for m in bad:
         assert _create(m)[0] == apfc.APFC_ERR_INVALID
     for kw in ({"restart": 0}, {"restart": 33}, {"rtol": 0.0}, {"picard_iters": 0}, {"a0": -1.0},
-               {"precision": 5}, {"mass_iters": 0}):
+               {"precision": 5}, {"mass_iters": 0}, {"x0_order": 3}, {"x0_order": -1}):
         assert _create(ok, params=apfc.apfc_params_default(**kw))[0] == apfc.APFC_ERR_INVALID, kw
     # a 3D lattice on a 2D mesh
     assert _create(ok, lat=apfc.apfc_lattice_default(apfc.APFC_BCC3D))[0] == apfc.APFC_ERR_INVALID
@@ -102,6 +103,12 @@ def test_workspace_size_and_missing_workspace():
     # dominated by (2m+1) full vectors of 2 J N complex doubles
     assert 61 * 2 * 3 * 4096 * 16 < b1 < 80 * 2 * 3 * 4096 * 16
     assert 3.5 < b2 / b1 < 4.5
+    # the extrapolated initial guess keeps two more full vectors (2 J N complex doubles each)
+    _, c3 = _create(m1, params=apfc.apfc_params_default(x0_order=2))
+    assert 2 * 2 * 3 * 4096 * 16 <= L.apfc_workspace_bytes(c3) - b1 <= 2 * 2 * 3 * 4096 * 16 + 1024
+    assert L.apfc_reset_history(c3) == apfc.APFC_OK
+    assert L.apfc_reset_history(None) == apfc.APFC_ERR_INVALID
+    L.apfc_destroy(c3)
     st = (apfc.apfc_state * 1)()
     assert L.apfc_step(c1, st, 1.0, None, None, None) == apfc.APFC_ERR_WORKSPACE
     assert L.apfc_set_workspace(c1, ctypes.c_void_p(256), ctypes.c_size_t(16)) == apfc.APFC_ERR_WORKSPACE

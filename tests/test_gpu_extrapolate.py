@@ -1,0 +1,81 @@
+"""Initial guess by extrapolation in time (params.x0_order): the steps still match the oracle's
+direct solves, and after a few steps they need fewer FGMRES iterations than with the state of the
+last step as initial guess.  Needs an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.apfc_oracle import tri_k
+from paper_1902_09761_amd import apfc, inputs
+from tests.gpu_util import H_TRI, from_dev, oracle_for, phi_of, rel_l2, solver_for, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _two_instances():
+    wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
+    m2 = inputs.Mesh(2, (48, 40, 1), (48 * H_TRI, 40 * H_TRI, 1.0))
+    e2 = inputs.single_grain(m2, tri_k(), phi_of(tri_k())(0.03), math.radians(4.0), 12 * H_TRI, seed=5)
+    return [wl.mesh, m2], [wl.dB, 0.03], [wl.eta0, e2]
+
+
+def _oracle_traj(mesh, dB, eta0, dts):
+    o = oracle_for(mesh, tri_k(), dB)
+    out, e = [], eta0
+    for dt in dts:
+        _, e = o.step(e, dt)
+        out.append(e)
+    return out
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_extrapolated_guess_matches_oracle_and_saves_iterations(order):
+    """Two instances (64^2 grain, ragged 48 x 40), 10 FP64 steps at dt = 1, rtol 1e-12."""
+    meshes, dBs, etas = _two_instances()
+    dts = [1.0] * 10
+    refs = [_oracle_traj(m, dB, e, dts) for m, dB, e in zip(meshes, dBs, etas)]
+    iters = {}
+    for x0 in (0, order):
+        s = solver_for(meshes, apfc.APFC_TRI2D, dBs, rtol=1e-12, inner_kind=apfc.APFC_INNER_CHEB,
+                       mass_iters=5, diff_iters=3, x0_order=x0)
+        et = [to_dev(e) for e in etas]
+        zt = [torch.zeros_like(e) for e in et]
+        s.init_zeta(et, zt)
+        its = []
+        for m, dt in enumerate(dts):
+            info = s.step(et, zt, dt)
+            its.append(info["total_iters"])
+            for b in range(2):
+                err = rel_l2(from_dev(et[b]), refs[b][m])
+                assert err < 1e-9, (x0, m, b, err)
+        iters[x0] = its
+    print("iterations per step", iters)
+    # the guess needs order + 1 kept states; compare the steps after that
+    assert sum(iters[order][4:]) < sum(iters[0][4:])
+
+
+def test_history_restarts_on_dt_change_and_reset():
+    """4 steps at dt = 1, 3 at dt = 0.5 (the history restarts), reset_history, 2 more at 0.5;
+    a fresh trajectory (init_zeta) on the same context after that."""
+    meshes, dBs, etas = _two_instances()
+    meshes, dBs, etas = meshes[:1], dBs[:1], etas[:1]
+    dts = [1.0] * 4 + [0.5] * 5
+    ref = _oracle_traj(meshes[0], dBs[0], etas[0], dts)
+    s = solver_for(meshes, apfc.APFC_TRI2D, dBs, rtol=1e-12, x0_order=2)
+    et = [to_dev(etas[0])]
+    zt = [torch.zeros_like(et[0])]
+    s.init_zeta(et, zt)
+    for m, dt in enumerate(dts):
+        if m == 7:
+            s.reset_history()
+        s.step(et, zt, dt)
+        assert rel_l2(from_dev(et[0]), ref[m]) < 1e-9, m
+    # another trajectory from the initial state: init_zeta forgets the kept states
+    et = [to_dev(etas[0])]
+    zt = [torch.zeros_like(et[0])]
+    s.init_zeta(et, zt)
+    for m in range(3):
+        s.step(et, zt, dts[m])
+        assert rel_l2(from_dev(et[0]), ref[m]) < 1e-9, ("second trajectory", m)
