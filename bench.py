@@ -43,8 +43,8 @@ def parse():
     ap.add_argument("--compare", action="store_true", help="also time the other precision on the same workload")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
     ap.add_argument("--restart", type=int, default=4)
-    ap.add_argument("--x0", type=int, default=2, choices=[0, 1, 2],
-                    help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) "
+    ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
+                    help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) / cubic (3) "
                          "extrapolation in time")
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)

@@ -87,12 +87,12 @@ typedef struct {
     int diff_iters;          /* inner iterations of each diffusion solve (paper: 5)      */
     int inner_kind;          /* APFC_INNER_PCG (paper) or APFC_INNER_CHEB                */
     int x0_order;            /* FGMRES initial guess of the first Picard solve of a step:
-                                0 = the state passed in (default); 1 / 2 = linear /
-                                quadratic extrapolation in time from the states passed to the
-                                last 1 / 2 steps of this context (fewer iterations; the stop
-                                test is unchanged).  Assumes consecutive apfc_step calls
-                                continue one trajectory per instance with one dt; see
-                                apfc_reset_history.                                      */
+                                0 = the state passed in (default); 1 / 2 / 3 = linear /
+                                quadratic / cubic extrapolation in time from the states
+                                passed to the last x0_order steps of this context (fewer
+                                iterations; the stop test is unchanged).  Assumes that
+                                consecutive apfc_step calls continue one trajectory per
+                                instance with one dt; see apfc_reset_history.             */
 } apfc_params;
 
 /* Device pointers of one instance, each [J][2][N] float64, owned by the caller. */
@@ -149,9 +149,9 @@ int apfc_init_zeta(apfc_ctx* ctx, apfc_state* states, void* stream);
 /* One time step of Algorithm 1 for every instance: eta, zeta <- eta^m, zeta^m.  source is
  * NULL or a device array per instance ([count] pointers to [J][2][N]) of a manufactured
  * source s added to d eta/dt (enters the RHS as M s).  stats may be NULL.
- * With params.x0_order > 0 the step keeps the states it was given (two device copies of the
- * state, in the workspace) to extrapolate the initial guess of the next steps; a step with
- * another dt than the last, or one that fails, restarts that history. */
+ * With params.x0_order > 0 the step keeps the states it was given (x0_order device copies of
+ * the state, in the workspace) to extrapolate the initial guess of the next steps; a step
+ * with another dt than the last, or one that fails, restarts that history. */
 int apfc_step(apfc_ctx* ctx, apfc_state* states, double dt, const double* const* source,
               void* stream, apfc_stats* stats);
 

@@ -150,9 +150,9 @@ struct apfc_ctx {
     double* apart = nullptr;
     Krylov kr{};
     int m = 30;
-    // states passed to the last steps, for the extrapolated initial guess (x0_order > 0):
-    // hist[newest] = x^{m-1}, hist[1 - newest] = x^{m-2}; hist_n of them are valid
-    zd* hist[2] = {nullptr, nullptr};
+    // states passed to the last x0_order steps, for the extrapolated initial guess: a ring of
+    // K = x0_order buffers, hist[newest] = x^{m-1}, hist[newest - 1] = x^{m-2}, ...; hist_n valid
+    zd* hist[3] = {nullptr, nullptr, nullptr};
     int hist_newest = 0, hist_n = 0;
     double hist_dt = 0.0;
 
@@ -306,7 +306,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.V = (zd*)take(sizeof(zd) * 2 * NT * (m + 1));
     c.Z = take(zs * 2 * NT * m);
     for (int i = 0; i < 6; ++i) c.pc[i] = take(zs * NT);
-    for (int i = 0; i < 2; ++i) c.hist[i] = c.solver.x0_order > 0 ? (zd*)take(sizeof(zd) * 2 * NT) : nullptr;
+    for (int i = 0; i < 3; ++i) c.hist[i] = i < c.solver.x0_order ? (zd*)take(sizeof(zd) * 2 * NT) : nullptr;
     c.dnode = (double*)take(sizeof(double) * c.NI);
     c.tpart = (double*)take(sizeof(double) * kSlots * c.max_tiles);
     c.cpart = (double*)take(sizeof(double) * (2 * kMaxRestart + 2) * c.chunks.size());
@@ -381,7 +381,7 @@ int check_params(const apfc_params& p) {
         return fail(APFC_ERR_INVALID, "params: inner iterations must be in [1,64]");
     if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB)
         return fail(APFC_ERR_INVALID, "params.inner_kind");
-    if (p.x0_order < 0 || p.x0_order > 2) return fail(APFC_ERR_INVALID, "params.x0_order must be 0, 1 or 2");
+    if (p.x0_order < 0 || p.x0_order > 3) return fail(APFC_ERR_INVALID, "params.x0_order must be in [0,3]");
     return APFC_OK;
 }
 
@@ -850,11 +850,13 @@ int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* s
         if (k == 0 && order > 0) {
             // initial guess extrapolated from the kept states; the state passed in replaces the
             // oldest one
-            const int use = std::min(order, c->hist_n);
-            zd* older = c->hist[1 - c->hist_newest];
-            launch_extrapolate(d, c->X, c->hist[c->hist_newest], older, use, st);
-            c->hist_newest = 1 - c->hist_newest;
-            c->hist_n = std::min(c->hist_n + 1, 2);
+            const int K = order, use = std::min(order, c->hist_n);
+            const zd* h[3] = {nullptr, nullptr, nullptr};
+            for (int q = 0; q < use; ++q) h[q] = c->hist[(c->hist_newest - q + K) % K];
+            const int oldest = (c->hist_newest + 1) % K;
+            launch_extrapolate(d, c->X, h, c->hist[oldest], use, st);
+            c->hist_newest = oldest;
+            c->hist_n = std::min(c->hist_n + 1, K);
             c->hist_dt = dt;
         }
         if (int rc = fgmres(c, st, &iters); rc) {

@@ -1846,26 +1846,31 @@ __global__ __launch_bounds__(kBlock) void k_widen(const zf* in, zd* out, long lo
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
         out[i] = zd{(double)in[i].x, (double)in[i].y};
 }
-// Initial guess from the kept states (order = how many of them are used): x0 = x (order 0),
-// x + (x - h1) (1), h2 + 3 (x - h1) (2), the polynomial through the last order + 1 states evaluated
-// one step ahead.  The state x is written over h2, which becomes the newest kept state.
-__global__ __launch_bounds__(kBlock) void k_extrapolate(zd* X, const zd* h1, zd* h2, long long n, int order) {
+// Initial guess from the kept states h_1 (newest) .. h_K: the polynomial through x and the last
+// `order` kept states, evaluated one step ahead (order 0: x; 1: 2x - h1; 2: 3x - 3h1 + h2;
+// 3: 4x - 6h1 + 4h2 - h3).  The state x then replaces the oldest kept state, `oldest` (which is
+// h_order when order = K; each element is read before it is written).
+__global__ __launch_bounds__(kBlock) void k_extrapolate(zd* X, const zd* h1, const zd* h2, const zd* h3, zd* oldest,
+                                                       long long n, int order) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
         const zd x = X[i];
         if (order == 1) {
             X[i] = x + (x - h1[i]);
         } else if (order == 2) {
             X[i] = h2[i] + 3.0 * (x - h1[i]);
+        } else if (order == 3) {
+            X[i] = 4.0 * (x + h2[i]) - (6.0 * h1[i] + h3[i]);
         }
-        h2[i] = x;
+        oldest[i] = x;
     }
 }
-void launch_extrapolate(const Dev& d, zd* X, const zd* h1, zd* h2, int order, hipStream_t st) {
+void launch_extrapolate(const Dev& d, zd* X, const zd* const* h, zd* oldest, int order, hipStream_t st) {
     ProbeScope ps(d, KID_OTHER, st);
     const long long n = 2 * d.NT;
     long long blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h1, h2, n, order);
+    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h[0], h[1], h[2], oldest, n,
+                       order);
 }
 
 void launch_widen(const zf* in, zd* out, long long n, hipStream_t st) {

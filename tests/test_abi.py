@@ -85,7 +85,7 @@ def test_argument_checks():
     for m in bad:
         assert _create(m)[0] == apfc.APFC_ERR_INVALID
     for kw in ({"restart": 0}, {"restart": 33}, {"rtol": 0.0}, {"picard_iters": 0}, {"a0": -1.0},
-               {"precision": 5}, {"mass_iters": 0}, {"x0_order": 3}, {"x0_order": -1}):
+               {"precision": 5}, {"mass_iters": 0}, {"x0_order": 4}, {"x0_order": -1}):
         assert _create(ok, params=apfc.apfc_params_default(**kw))[0] == apfc.APFC_ERR_INVALID, kw
     # a 3D lattice on a 2D mesh
     assert _create(ok, lat=apfc.apfc_lattice_default(apfc.APFC_BCC3D))[0] == apfc.APFC_ERR_INVALID

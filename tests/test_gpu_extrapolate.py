@@ -30,7 +30,7 @@ def _oracle_traj(mesh, dB, eta0, dts):
     return out
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_extrapolated_guess_matches_oracle_and_saves_iterations(order):
     """Two instances (64^2 grain, ragged 48 x 40), 10 FP64 steps at dt = 1, rtol 1e-12."""
     meshes, dBs, etas = _two_instances()
