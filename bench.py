@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)
     ap.add_argument("--probe", default="apply", help="kernel timed with HIP events for the roofline ('none': off)")
+    ap.add_argument("--probe-every", type=int, default=7,
+                    help="time every n-th launch of the probed kernel (an event pair idles the stream briefly; "
+                         "keep n coprime with the restart length so that every Arnoldi index is sampled)")
     ap.add_argument("--graphs", action="store_true", help="replay restart cycles as hipGraphs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,7 +104,7 @@ def run_gpu(args, precision, probe=None):
     for _ in range(args.warmup):
         s.step(ets, zts, dt)
     if probe:
-        s.probe_enable(probe)
+        s.probe_enable(probe, args.probe_every)
     iters, total = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -117,7 +120,8 @@ def run_gpu(args, precision, probe=None):
            "relres": info["max_relres"], "instances": len(wls), "mesh": wls[0].name}
     if probe:
         n, ms_, bpl = s.probe_read()
-        out["probe"] = {"kernel": probe, "launches": n, "ms": ms_, "bytes_per_launch": bpl}
+        out["probe"] = {"kernel": probe, "launches": n, "ms": ms_, "bytes_per_launch": bpl,
+                        "every": args.probe_every}
         s.probe_enable(None)
     out["energy"] = s.energy(ets)
     out["eta_host"] = [e.cpu().numpy() for e in ets]
@@ -201,7 +205,8 @@ def main():
         line["roofline"] = {"bound": "hbm", "kernel": "k_apply_dot" if pr["kernel"] == "apply" else pr["kernel"],
                             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                             "traffic": traffic, "traffic_source": src, "avg_launch_us": 1e3 * avg_ms,
-                            "launches": pr["launches"], "bytes_per_launch": pr["bytes_per_launch"]}
+                            "launches": pr["launches"], "sampled_every": pr["every"],
+                            "bytes_per_launch": pr["bytes_per_launch"]}
     if args.compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
         r2 = run_gpu(args, other)

@@ -209,10 +209,12 @@ typedef struct {
 int apfc_rotation(apfc_ctx* ctx, const apfc_state* states, double* const* omega, double* const* h,
                   const apfc_refine_params* params, void* stream);
 
-/* Kernel timing probe: when enabled, every launch of the kernel named `name` inside
- * apfc_step is bracketed by HIP events on the launch stream; apfc_probe_read returns the
- * number of launches and their summed duration since the last reset. */
-int apfc_probe_enable(apfc_ctx* ctx, const char* name);
+/* Kernel timing probe: when enabled, every `every`-th launch (every >= 1) of the kernel named
+ * `name` inside apfc_step is bracketed by HIP events on the launch stream (an event pair adds
+ * a few microseconds of stream idle, hence the sampling); apfc_probe_read returns the number of
+ * recorded launches, their summed duration and their mean algorithmic bytes since the last
+ * reset.  name = NULL disables the probe. */
+int apfc_probe_enable(apfc_ctx* ctx, const char* name, int every);
 int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* bytes_per_launch);
 
 /* Tile-height autotuner: times the stencil kernels for each candidate tile on the attached

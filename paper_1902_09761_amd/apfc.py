@@ -103,7 +103,7 @@ def lib() -> ctypes.CDLL:
                                       P(c_void_p), P(c_double), c_void_p, P(apfc_stats)]),
         "apfc_apply": (c_int, [c_void_p, c_int, P(apfc_state), P(apfc_state), P(apfc_state), c_double, c_void_p]),
         "apfc_rotation": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_void_p), P(apfc_refine_params), c_void_p]),
-        "apfc_probe_enable": (c_int, [c_void_p, c_char_p]),
+        "apfc_probe_enable": (c_int, [c_void_p, c_char_p, c_int]),
         "apfc_probe_read": (c_int, [c_void_p, P(c_int), P(c_double), P(c_double)]),
         "apfc_autotune": (c_int, [c_void_p, c_void_p, P(c_int)]),
         "apfc_set_tiles": (c_int, [c_void_p, c_int, c_int]),
@@ -318,8 +318,8 @@ class Solver:
     def set_graphs(self, enable: bool):
         _check(lib().apfc_set_graphs(self.ctx, 1 if enable else 0))
 
-    def probe_enable(self, name: Optional[str]):
-        _check(lib().apfc_probe_enable(self.ctx, name.encode() if name else None))
+    def probe_enable(self, name: Optional[str], every: int = 1):
+        _check(lib().apfc_probe_enable(self.ctx, name.encode() if name else None, every))
 
     def probe_read(self):
         n = c_int()

@@ -74,6 +74,8 @@ int kernel_id(const char* name);
 struct Probe {
     int target = KID_NONE;
     int n = 0;
+    int every = 1;            // record every `every`-th launch of the target
+    long long seen = 0;       // launches of the target since the probe was enabled
     double bytes = 0.0;       // algorithmic HBM bytes of the recorded launches
     static constexpr int kMax = 8192;
     hipEvent_t ev[2 * kMax];

@@ -150,6 +150,7 @@ struct apfc_ctx {
     double* apart = nullptr;
     Krylov kr{};
     int m = 30;
+    int cycle_hint = 0;   // restart cycles of the slowest system in the last solve
     // states passed to the last x0_order steps, for the extrapolated initial guess: a ring of
     // K = x0_order buffers, hist[newest] = x^{m-1}, hist[newest - 1] = x^{m-2}, ...; hist_n valid
     zd* hist[3] = {nullptr, nullptr, nullptr};
@@ -767,12 +768,17 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     launch_cycle_init(d, kr, true, st);
     launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
     int launched = 0;
+    // Cycles before the last one of the previous solve are queued without a host round trip:
+    // the iteration count changes slowly from step to step, and a cycle queued for systems that
+    // have converged only runs masked (empty) kernels.
+    const int hint = c->cycle_hint;
     for (int cyc = 0;; ++cyc) {
         if (graphs)
             HIPCHK(hipGraphLaunch(c->graphs[0], st));
         else
             run_cycle(c, d, st);
         launched += c->m;
+        if (cyc + 1 < hint) continue;
         HIPCHK(hipStreamSynchronize(st));
         // k_publish wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
         const volatile int* pub = c->h_pub;
@@ -787,6 +793,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
         }
     }
     if (total_iters) *total_iters = launched;
+    c->cycle_hint = (launched + c->m - 1) / c->m;
     return APFC_OK;
 }
 
@@ -1106,8 +1113,9 @@ int apfc_set_graphs(apfc_ctx* c, int enable) {
     return APFC_OK;
 }
 
-int apfc_probe_enable(apfc_ctx* c, const char* name) {
+int apfc_probe_enable(apfc_ctx* c, const char* name, int every) {
     if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    if (every < 1) return fail(APFC_ERR_INVALID, "probe: every must be >= 1");
     const int kid = name ? kernel_id(name) : KID_NONE;
     if (name && kid == KID_NONE) return fail(APFC_ERR_INVALID, std::string("unknown kernel name: ") + name);
     if (!c->probe.created && kid != KID_NONE) {
@@ -1115,6 +1123,8 @@ int apfc_probe_enable(apfc_ctx* c, const char* name) {
         c->probe.created = true;
     }
     c->probe.target = kid;
+    c->probe.every = every;
+    c->probe.seen = 0;
     c->probe.n = 0;
     c->probe.bytes = 0.0;
     return APFC_OK;

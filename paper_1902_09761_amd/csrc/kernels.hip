@@ -466,33 +466,6 @@ __device__ __forceinline__ void apply_A(const Sys& s, const Nbr<DIM>& n, const c
     y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dn) * ec;
 }
 
-template <int DIM, int TY>
-__global__ __launch_bounds__(kBlock) void k_residual(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
-                                                    const zd* B, const double* dnode, zd* R, double* part,
-                                                    long long NT, int ntiles) {
-    __shared__ double lds[8];
-    TILE_PROLOGUE();
-    double acc[2] = {0.0, 0.0};
-    FOR_ROWS(TY) {
-        Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, pz, n);
-        const long long il = nb_index<DIM>(n, 1, 1, 1);
-        zd y1, y2;
-        apply_A<DIM, double>(s, n, X, X + NT, dnode[s.doff + il], y1, y2);
-        const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
-        const zd r1 = b1 - y1, r2 = b2 - y2;
-        R[s.off + il] = r1;
-        R[NT + s.off + il] = r2;
-        acc[0] += abs2(r1) + abs2(r2);
-        acc[1] += abs2(b1) + abs2(b2);
-    }
-    block_sum<2>(acc, lds);
-    if (threadIdx.x == 0) {
-        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
-        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
-    }
-}
-
 template <int DIM, int TY, typename T>
 __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* tiles, const int* mask,
                                                  const cx<T>* Z, const double* dnode, zd* W, long long NT) {
@@ -508,68 +481,19 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* ti
     }
 }
 
-// W = A Z at every node of the tile and, fused, the first Gram-Schmidt pass: per-tile partials of
-// V_i^H w (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).
-template <int DIM, int TY, typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_apply_dot(const Sys* sys, const Tile* tiles, const int* mask,
-                                                     const cx<T>* Z, const double* dnode, zd* W, const zd* V,
-                                                     long long vstride, int nv, double* part, long long NT,
-                                                     int ntiles) {
-    __shared__ double lds[4 * (2 * NV + 1)];
-    TILE_PROLOGUE();
-    double acc[2 * NV + 1];
-#pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    FOR_ROWS(TY) {
-        Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, pz, n);
-        const long long il = s.off + nb_index<DIM>(n, 1, 1, 1);
-        zd y1, y2;
-        apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + nb_index<DIM>(n, 1, 1, 1)], y1, y2);
-        W[il] = y1;
-        W[NT + il] = y2;
-        acc[2 * NV] += abs2(y1) + abs2(y2);
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (l < nv) {
-                const zd a = cdot(V[l * vstride + il], y1), b = cdot(V[l * vstride + NT + il], y2);
-                acc[2 * l] += a.x + b.x;
-                acc[2 * l + 1] += a.y + b.y;
-            }
-    }
-    block_sum<2 * NV + 1>(acc, lds);
-    if (threadIdx.x == 0) {
-        for (int l = 0; l < nv; ++l) {
-            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
-            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
-        }
-        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
-    }
-}
-
-// 2D version of k_apply_dot that marches each thread down TY/4 consecutive rows of one column: the
-// x pass (mass, stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept
-// for the next two rows, so each input row is loaded once per field (3 loads instead of 9).
-template <int TY, typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
-                                                       long long vstride, int nv, double* part, long long NT,
-                                                       int ntiles) {
-    constexpr int RR = TY / 4;
-    __shared__ double lds[4 * (2 * NV + 1)];
-    TILE_PROLOGUE();
-    (void)ty;
-    const int y0 = tile.y0 + (int)(threadIdx.x >> 6) * RR;
+// 2D column march: a thread walks rows y0-1 .. y0+RR of column x (periodic); the x pass (mass,
+// stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept for the next
+// two rows, so each input row is loaded once per field (3 loads instead of 9).  zz, ze point at the
+// zeta and eta parts of u for the system; emit(il, y1, y2) receives A_j u at node il = (x, y) for
+// y = y0 .. y0+RR-1 inside the mesh.
+template <int RR, typename T, typename EMIT>
+__device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const cx<T>* zz, const cx<T>* ze,
+                                           const double* dnode, const EMIT& emit) {
     const int xc = x < s.nx ? x : s.nx - 1;                  // clamp for loads of ragged tiles
     const int xm = xc == 0 ? s.nx - 1 : xc - 1, xp = xc == s.nx - 1 ? 0 : xc + 1;
     const double h = s.h, m0 = h / 6.0, m1 = 4.0 * h / 6.0, ih = 1.0 / h;
     const double kx = s.kv[0], ky = s.kv[1];
-    const cx<T>* zz = Z + s.off;
-    const cx<T>* ze = Z + NT + s.off;
     zd mz[3], kz[3], dz[3], me[3], ke[3], de[3], ce[3];
-    double acc[2 * NV + 1];
-#pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
 #pragma unroll
     for (int a = 0; a < RR + 2; ++a) {
         int row = y0 - 1 + a;
@@ -600,16 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
                 const long long il = (long long)y * s.nx + x;
                 const zd y1 = Mz - gop(Ke, Te);
                 const zd y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dnode[s.doff + il]) * ce[1];
-                W[s.off + il] = y1;
-                W[NT + s.off + il] = y2;
-                acc[2 * NV] += abs2(y1) + abs2(y2);
-#pragma unroll
-                for (int l = 0; l < NV; ++l)
-                    if (l < nv) {
-                        const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
-                        acc[2 * l] += p.x + q.x;
-                        acc[2 * l + 1] += p.y + q.y;
-                    }
+                emit(il, y1, y2);
             }
         }
 #pragma unroll
@@ -618,6 +533,35 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
             me[j] = me[j + 1]; ke[j] = ke[j + 1]; de[j] = de[j + 1]; ce[j] = ce[j + 1];
         }
     }
+}
+
+// W = A Z at every node and, fused, the first Gram-Schmidt pass: per-tile partials of V_i^H w
+// (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).  2D: column-marching
+// tiles (TY/4 rows per thread); 3D: k_apply_dot3d below.
+template <int TY, typename T, int NV>
+__global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                       long long vstride, int nv, double* part, long long NT,
+                                                       int ntiles) {
+    constexpr int RR = TY / 4;
+    __shared__ double lds[4 * (2 * NV + 1)];
+    TILE_PROLOGUE();
+    const int y0 = tile.y0 + ty * RR;
+    double acc[2 * NV + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+    colmarch_A<RR, T>(s, x, y0, Z + s.off, Z + NT + s.off, dnode, [&](long long il, const zd& y1, const zd& y2) {
+        W[s.off + il] = y1;
+        W[NT + s.off + il] = y2;
+        acc[2 * NV] += abs2(y1) + abs2(y2);
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
+                acc[2 * l] += p.x + q.x;
+                acc[2 * l + 1] += p.y + q.y;
+            }
+    });
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
         for (int l = 0; l < nv; ++l) {
@@ -628,7 +572,32 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
     }
 }
 
-// 3D versions of k_apply_dot and k_residual on z-marching bricks (64 x 4 x TY/4 nodes).
+// R = B - A X and per-tile partials of |R|^2, |B|^2 (slots kRR, kBB), on column-marching tiles.
+template <int TY>
+__global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
+                                                      const zd* B, const double* dnode, zd* R, double* part,
+                                                      long long NT, int ntiles) {
+    constexpr int RR = TY / 4;
+    __shared__ double lds[8];
+    TILE_PROLOGUE();
+    const int y0 = tile.y0 + ty * RR;
+    double acc[2] = {0.0, 0.0};
+    colmarch_A<RR, double>(s, x, y0, X + s.off, X + NT + s.off, dnode, [&](long long il, const zd& y1, const zd& y2) {
+        const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
+        const zd r1 = b1 - y1, r2 = b2 - y2;
+        R[s.off + il] = r1;
+        R[NT + s.off + il] = r2;
+        acc[0] += abs2(r1) + abs2(r2);
+        acc[1] += abs2(b1) + abs2(b2);
+    });
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
+        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
+    }
+}
+
+// 3D versions of k_apply_dot2d and k_residual2d on z-marching bricks (64 x 4 x TY/4 nodes).
 #define BRICK_PROLOGUE()                                                     \
     TILE_PROLOGUE();                                                         \
     const int y = tile.y0 + ty;                                              \
@@ -1781,7 +1750,7 @@ struct ProbeScope {
     hipStream_t st;
     bool on;
     ProbeScope(const Dev& d, int kid, hipStream_t s, double bytes = 0.0) : p(d.probe), st(s) {
-        on = p && p->target == kid && p->n < Probe::kMax;
+        on = p && p->target == kid && (p->seen++ % p->every) == 0 && p->n < Probe::kMax;
         if (on) {
             (void)hipEventRecord(p->ev[2 * p->n], st);
             p->bytes += bytes;
@@ -1898,7 +1867,7 @@ void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode
             hipLaunchKernelGGL((k_residual3d<TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
                                d.ntiles);
         else
-            hipLaunchKernelGGL((k_residual<D(), TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+            hipLaunchKernelGGL((k_residual2d<TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
                                d.ntiles);
     });
 }
