@@ -1,5 +1,5 @@
 """The benchmark workload at full size (1024^2 triangular polycrystal, 3 amplitudes) in the launch
-configuration bench.py times (Chebyshev 5/3 inner solves, restart 4, autotuned tiles, hipGraph replay).
+configuration bench.py times (Chebyshev 5/3 inner solves, restart 4, autotuned tiles).
 The oracle cannot factor these systems in reasonable time, so it checks a property that holds at any
 size: with its own element-by-element assembly and its own nodal linearisation it forms every
 amplitude's block system Eq. (11) and verifies that the GPU's step result solves it to the requested
