@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
                     help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) / cubic (3) "
                          "extrapolation in time")
+    ap.add_argument("--dt", type=float, default=None, help="time step (default: the workload's, 1.0)")
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)
     ap.add_argument("--probe", default="apply", help="kernel timed with HIP events for the roofline ('none': off)")
@@ -100,7 +101,7 @@ def run_gpu(args, precision, probe=None):
     ets = [torch.tensor(inputs.to_planar(w.eta0), dtype=torch.float64, device="cuda") for w in wls]
     zts = [torch.zeros_like(e) for e in ets]
     s.init_zeta(ets, zts)
-    dt = wls[0].dt
+    dt = args.dt if args.dt is not None else wls[0].dt
     for _ in range(args.warmup):
         s.step(ets, zts, dt)
     if probe:
@@ -116,7 +117,7 @@ def run_gpu(args, precision, probe=None):
     sec = time.perf_counter() - t0
     J = lat.J
     dofs = sum(J * w.mesh.N for w in wls)
-    out = {"sec": sec, "iters": iters, "total_iters": total, "tile_rows": ty, "dofs": dofs, "J": J,
+    out = {"sec": sec, "iters": iters, "total_iters": total, "tile_rows": ty, "dofs": dofs, "J": J, "dt": dt,
            "relres": info["max_relres"], "instances": len(wls), "mesh": wls[0].name}
     if probe:
         n, ms_, bpl = s.probe_read()
@@ -157,7 +158,7 @@ def cpu_baseline(args):
         what = f"1 step of the Voronoi recipe at {n}^2 nodes (same h, 3 amplitudes)"
     o = Oracle(Grid(wl.mesh.dim, wl.mesh.n[: wl.mesh.dim], wl.mesh.length[: wl.mesh.dim]), k, Params.from_dB(wl.dB))
     t0 = time.perf_counter()
-    o.step(wl.eta0, wl.dt)
+    o.step(wl.eta0, args.dt if args.dt is not None else wl.dt)
     sec = time.perf_counter() - t0
     return {"value": len(k) * wl.mesh.N / sec, "unit": "amplitude-DOF-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{what}; SuperLU factor + solve per amplitude, single-threaded; {sec:.1f} s"}
@@ -187,7 +188,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": res["instances"], "first_instance": res["mesh"],
-                   "amplitude_dofs": res["dofs"], "J": res["J"], "dt": 1.0, "rtol": 1e-8,
+                   "amplitude_dofs": res["dofs"], "J": res["J"], "dt": res["dt"], "rtol": 1e-8,
                    "precision": args.precision, "inner": args.inner, "restart": args.restart,
                    "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
                    "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
