@@ -54,6 +54,8 @@ def parse():
                     help="time every n-th launch of the probed kernel (an event pair idles the stream briefly; "
                          "keep n coprime with the restart length so that every Arnoldi index is sampled)")
     ap.add_argument("--graphs", action="store_true", help="replay restart cycles as hipGraphs")
+    ap.add_argument("--per-step", action="store_true",
+                    help="one apfc_step call per step instead of one apfc_run call for the K steps")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -102,17 +104,22 @@ def run_gpu(args, precision, probe=None):
     zts = [torch.zeros_like(e) for e in ets]
     s.init_zeta(ets, zts)
     dt = args.dt if args.dt is not None else wls[0].dt
-    for _ in range(args.warmup):
-        s.step(ets, zts, dt)
+    if args.warmup > 0:
+        s.run(ets, zts, dt, args.warmup)
     if probe:
         s.probe_enable(probe, args.probe_every)
     iters, total = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = s.step(ets, zts, dt)
-        iters.append(info["max_iters"])
-        total.append(info["total_iters"])
+    if args.per_step:
+        for _ in range(args.steps):
+            info = s.step(ets, zts, dt)
+            iters.append(info["max_iters"])
+            total.append(info["total_iters"])
+    else:
+        info = s.run(ets, zts, dt, args.steps)
+        iters = info["step_max_iters"]
+        total = [info["total_iters"]]
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     J = lat.J
@@ -193,7 +200,7 @@ def main():
                    "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
                    "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
                    "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "x0_order": args.x0,
-                   "graphs": bool(args.graphs)},
+                   "graphs": bool(args.graphs), "entry": "apfc_step" if args.per_step else "apfc_run"},
         "fgmres_iters_per_step": float(np.mean(res["iters"])),
         "final_relres": res["relres"],
     }

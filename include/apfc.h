@@ -155,6 +155,17 @@ int apfc_init_zeta(apfc_ctx* ctx, apfc_state* states, void* stream);
 int apfc_step(apfc_ctx* ctx, apfc_state* states, double dt, const double* const* source,
               void* stream, apfc_stats* stats);
 
+/* nsteps >= 1 time steps with one dt: the same arithmetic as nsteps calls of apfc_step, but the state
+ * stays in the library's layout between the steps (converted from and to the caller's planar
+ * arrays once) and no statistics are copied to the host between the steps.  source as in
+ * apfc_step (the same for every step).  The caller's state is written only when every step
+ * succeeds; otherwise it is unchanged and the first failing step's code is returned.
+ * stats (may be NULL): total_iters and iters[] summed over the steps, max_iters, cycles and
+ * max_relres the largest of any step.  step_max_iters (host, [nsteps], may be NULL): the largest
+ * per-system iteration count of each step (entries after a failing step are not written). */
+int apfc_run(apfc_ctx* ctx, apfc_state* states, double dt, int nsteps, const double* const* source,
+             void* stream, apfc_stats* stats, int* step_max_iters);
+
 /* Forget the states kept for params.x0_order > 0: the next apfc_step starts a new trajectory
  * (its initial guess is the state passed in).  apfc_init_zeta and apfc_set_workspace do the
  * same.  No effect with x0_order = 0. */

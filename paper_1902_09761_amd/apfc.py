@@ -30,7 +30,7 @@ APFC_OP_A, APFC_OP_PINV = 0, 1
 
 EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_create",
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
-           "apfc_reset_history",
+           "apfc_reset_history", "apfc_run",
            "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read",
            "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
 
@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
         "apfc_init_zeta": (c_int, [c_void_p, P(apfc_state), c_void_p]),
         "apfc_step": (c_int, [c_void_p, P(apfc_state), c_double, P(c_void_p), c_void_p, P(apfc_stats)]),
         "apfc_reset_history": (c_int, [c_void_p]),
+        "apfc_run": (c_int, [c_void_p, P(apfc_state), c_double, c_int, P(c_void_p), c_void_p, P(apfc_stats),
+                             P(c_int)]),
         "apfc_energy": (c_int, [c_void_p, P(apfc_state), P(c_double), c_void_p]),
         "apfc_energy_grad": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_double), c_void_p]),
         "apfc_step_adjoint": (c_int, [c_void_p, P(apfc_state), P(apfc_state), c_double, P(c_void_p),
@@ -259,6 +261,25 @@ class Solver:
         rc = lib().apfc_step(self.ctx, self._states(etas, zetas), float(dt), src, _stream_handle(stream), byref(st))
         info = {"total_iters": st.total_iters, "max_iters": st.max_iters, "cycles": st.cycles,
                 "max_relres": st.max_relres, "ms": st.ms, "iters": list(iters)}
+        if rc != APFC_OK:
+            try:
+                _check(rc)
+            except APFCError as e:
+                e.info = info
+                raise
+        return info
+
+    def run(self, etas, zetas, dt: float, nsteps: int, source=None, stream=None) -> dict:
+        """nsteps steps in one call (apfc_run); info as step() plus step_max_iters per step."""
+        st = apfc_stats()
+        iters = (c_int * (self.count * self.J))()
+        st.iters = ctypes.cast(iters, POINTER(c_int))
+        per_step = (c_int * nsteps)()
+        src = self._ptrs(source, "source") if source is not None else None
+        rc = lib().apfc_run(self.ctx, self._states(etas, zetas), float(dt), int(nsteps), src,
+                            _stream_handle(stream), byref(st), per_step)
+        info = {"total_iters": st.total_iters, "max_iters": st.max_iters, "cycles": st.cycles,
+                "max_relres": st.max_relres, "ms": st.ms, "iters": list(iters), "step_max_iters": list(per_step)}
         if rc != APFC_OK:
             try:
                 _check(rc)

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -151,6 +152,10 @@ struct apfc_ctx {
     Krylov kr{};
     int m = 30;
     int cycle_hint = 0;   // restart cycles of the slowest system in the last solve
+    // apfc_run statistics (device, [S])
+    long long* run_it_sum = nullptr;
+    int *run_it_max = nullptr, *run_cyc_max = nullptr;
+    double* run_res_max = nullptr;
     // states passed to the last x0_order steps, for the extrapolated initial guess: a ring of
     // K = x0_order buffers, hist[newest] = x^{m-1}, hist[newest - 1] = x^{m-2}, ...; hist_n valid
     zd* hist[3] = {nullptr, nullptr, nullptr};
@@ -343,6 +348,10 @@ size_t carve(apfc_ctx& c, char* base) {
     k.iters = (int*)take(sizeof(int) * S);
     k.cycles = (int*)take(sizeof(int) * S);
     k.err = (int*)take(sizeof(int) * 4);
+    c.run_it_sum = (long long*)take(sizeof(long long) * S);
+    c.run_it_max = (int*)take(sizeof(int) * S);
+    c.run_cyc_max = (int*)take(sizeof(int) * S);
+    c.run_res_max = (double*)take(sizeof(double) * S);
     return off + 256;
 }
 
@@ -356,6 +365,25 @@ __global__ void k_reset_counters(Krylov kr, int S) {
         kr.iter_active[s] = 0;
         if (s == 0) kr.err[0] = 0;
     }
+}
+
+// Statistics of a multi-step run, summed (iterations) or maximised (cycles, residual) over the steps on
+// the device, so that the steps need no copies to the host.
+__global__ void k_run_stats(Krylov kr, int S, int reset, long long* it_sum, int* it_max, int* cyc_max,
+                            double* res_max) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (reset) {
+        it_sum[s] = 0;
+        it_max[s] = 0;
+        cyc_max[s] = 0;
+        res_max[s] = 0.0;
+        return;
+    }
+    it_sum[s] += kr.iters[s];
+    it_max[s] = max(it_max[s], kr.iters[s]);
+    cyc_max[s] = max(cyc_max[s], kr.cycles[s]);
+    res_max[s] = fmax(res_max[s], kr.relres[s]);
 }
 
 int check_mesh(const apfc_mesh& m) {
@@ -830,25 +858,12 @@ int check_states(apfc_ctx* c, const apfc_state* states, bool need_zeta) {
 
 extern "C" {
 
-int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, void* stream,
-              apfc_stats* stats) {
-    auto t0 = std::chrono::steady_clock::now();
-    if (int rc = need_ws(c); rc) return rc;
-    if (int rc = check_states(c, states, true); rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    if (int rc = refresh_dt(c, dt, st); rc) return rc;
-    std::vector<const void*> t[3];
-    for (int b = 0; b < c->count; ++b) {
-        t[0].push_back(states[b].eta);
-        t[1].push_back(states[b].zeta);
-        t[2].push_back(source ? source[b] : nullptr);
-        if (source && !source[b]) return fail(APFC_ERR_INVALID, "source[b] is NULL");
-    }
-    if (int rc = upload_ptrs(c, t, 3, st); rc) return rc;
-    Dev d = c->dev();
-    launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
+namespace {
+
+// One step of Algorithm 1 on the state held in X (zeta half, eta half): RHS, K Picard iterates with the
+// nodal linearisation, FGMRES.  *max_iters receives the largest per-system iteration count.
+int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st, int* max_iters) {
     launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
-    int iters = 0;
     const int order = c->solver.x0_order;
     if (order > 0 && c->hist_n > 0 && dt != c->hist_dt) c->hist_n = 0;
     for (int k = 0; k < c->solver.picard_iters; ++k) {
@@ -866,16 +881,97 @@ int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* s
             c->hist_n = std::min(c->hist_n + 1, K);
             c->hist_dt = dt;
         }
-        if (int rc = fgmres(c, st, &iters); rc) {
+        if (int rc = fgmres(c, st, max_iters); rc) {
             c->hist_n = 0;
-            (void)fill_stats(c, st, stats, 0.0);
             return rc;
         }
+    }
+    return APFC_OK;
+}
+
+int prepare_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, hipStream_t st) {
+    if (int rc = need_ws(c); rc) return rc;
+    if (int rc = check_states(c, states, true); rc) return rc;
+    if (int rc = refresh_dt(c, dt, st); rc) return rc;
+    std::vector<const void*> t[3];
+    for (int b = 0; b < c->count; ++b) {
+        t[0].push_back(states[b].eta);
+        t[1].push_back(states[b].zeta);
+        t[2].push_back(source ? source[b] : nullptr);
+        if (source && !source[b]) return fail(APFC_ERR_INVALID, "source[b] is NULL");
+    }
+    return upload_ptrs(c, t, 3, st);
+}
+
+}  // namespace
+
+int apfc_step(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, void* stream,
+              apfc_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = prepare_step(c, states, dt, source, st); rc) return rc;
+    Dev d = c->dev();
+    launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
+    int iters = 0;
+    if (int rc = step_body(c, d, dt, source != nullptr, st, &iters); rc) {
+        (void)fill_stats(c, st, stats, 0.0);
+        return rc;
     }
     launch_state_out(d, c->X, tab(c, 0), tab(c, 1), st);
     HIPCHK(hipGetLastError());
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return fill_stats(c, st, stats, ms);
+}
+
+int apfc_run(apfc_ctx* c, apfc_state* states, double dt, int nsteps, const double* const* source, void* stream,
+             apfc_stats* stats, int* step_max_iters) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (nsteps < 1) return fail(APFC_ERR_INVALID, "nsteps must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = prepare_step(c, states, dt, source, st); rc) return rc;
+    Dev d = c->dev();
+    const int S = c->S;
+    const dim3 sg((S + 63) / 64), sb(64);
+    hipLaunchKernelGGL(k_run_stats, sg, sb, 0, st, c->kr, S, 1, c->run_it_sum, c->run_it_max, c->run_cyc_max,
+                       c->run_res_max);
+    launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
+    int rc = APFC_OK;
+    for (int m = 0; m < nsteps && rc == APFC_OK; ++m) {
+        int iters = 0;
+        rc = step_body(c, d, dt, source != nullptr, st, &iters);
+        if (step_max_iters) step_max_iters[m] = iters;
+        if (rc == APFC_OK || rc == APFC_ERR_NOT_CONVERGED)
+            hipLaunchKernelGGL(k_run_stats, sg, sb, 0, st, c->kr, S, 0, c->run_it_sum, c->run_it_max,
+                               c->run_cyc_max, c->run_res_max);
+    }
+    if (rc == APFC_OK) launch_state_out(d, c->X, tab(c, 0), tab(c, 1), st);
+    HIPCHK(hipGetLastError());
+    if (stats) {
+        std::vector<long long> it_sum(S);
+        std::vector<int> it_max(S), cyc_max(S);
+        std::vector<double> res_max(S);
+        HIPCHK(hipMemcpyAsync(it_sum.data(), c->run_it_sum, sizeof(long long) * S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(it_max.data(), c->run_it_max, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(cyc_max.data(), c->run_cyc_max, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(res_max.data(), c->run_res_max, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        long long total = 0;
+        stats->max_iters = 0;
+        stats->cycles = 0;
+        stats->max_relres = 0.0;
+        for (int s = 0; s < S; ++s) {
+            total += it_sum[s];
+            if (stats->iters) stats->iters[s] = (int)std::min<long long>(it_sum[s], INT32_MAX);
+            stats->max_iters = std::max(stats->max_iters, it_max[s]);
+            stats->cycles = std::max(stats->cycles, cyc_max[s]);
+            stats->max_relres = std::max(stats->max_relres, res_max[s]);
+        }
+        stats->total_iters = (int)std::min<long long>(total, INT32_MAX);
+        stats->ms = rc == APFC_OK
+                        ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count()
+                        : 0.0;
+    }
+    return rc;
 }
 
 int apfc_reset_history(apfc_ctx* c) {

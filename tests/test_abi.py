@@ -111,6 +111,8 @@ def test_workspace_size_and_missing_workspace():
     L.apfc_destroy(c3)
     st = (apfc.apfc_state * 1)()
     assert L.apfc_step(c1, st, 1.0, None, None, None) == apfc.APFC_ERR_WORKSPACE
+    assert L.apfc_run(c1, st, 1.0, 0, None, None, None, None) == apfc.APFC_ERR_INVALID
+    assert L.apfc_run(c1, st, 1.0, 2, None, None, None, None) == apfc.APFC_ERR_WORKSPACE
     assert L.apfc_set_workspace(c1, ctypes.c_void_p(256), ctypes.c_size_t(16)) == apfc.APFC_ERR_WORKSPACE
     L.apfc_destroy(c1)
     L.apfc_destroy(c2)
