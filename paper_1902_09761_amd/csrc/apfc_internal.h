@@ -146,9 +146,11 @@ template <typename T>
 void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
+// vscale (may be null): v is used as vscale[sys] * v, and that scaled vector is also stored to vout
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
-                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout,
+                         const int* mask, hipStream_t st);
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,

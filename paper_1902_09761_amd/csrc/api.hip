@@ -705,12 +705,12 @@ double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
 // P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
 // Chebyshev (3D), or the paper's Jacobi-PCG.
 template <typename T>
-void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, hipStream_t st) {
+void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, hipStream_t st,
+             const double* vscale = nullptr, zd* vout = nullptr) {
     cx<T>** pc = (cx<T>**)c->pc;
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
-                               pc[0], pc[1],
-                               c->solver.mass_iters, c->solver.diff_iters, mask, st);
+                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, vscale, vout, mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB)
         launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
                                        c->solver.diff_iters, mask, st);
@@ -719,6 +719,10 @@ void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, 
                           c->solver.diff_iters, mask, st);
 }
 
+// The fused 2D Chebyshev preconditioner normalises the first basis vector of a cycle itself (reading
+// the residual), so no separate scaling pass runs.
+bool scale_in_precond(const apfc_ctx* c) { return c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2; }
+
 template <typename T>
 void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     const Krylov& kr = c->kr;
@@ -726,7 +730,10 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     cx<T>* Z = (cx<T>*)c->Z;
     cx<T>** pc = (cx<T>**)c->pc;
     const int* act = kr.iter_active;
-    precond<T>(c, d, c->V + k * vs, Z + k * vs, act, st);
+    if (k == 0 && scale_in_precond(c))   // v_0 = r / beta formed by the preconditioner's first stages
+        precond<T>(c, d, c->R, Z, act, st, kr.inv_beta, c->V);
+    else
+        precond<T>(c, d, c->V + k * vs, Z + k * vs, act, st);
     const int nv = k + 1;
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
@@ -759,7 +766,7 @@ void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
     launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
     launch_cycle_init(d, kr, false, st);
-    launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    if (!scale_in_precond(c)) launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
     launch_publish(d, kr, c->d_pub, st);
 }
 
@@ -794,7 +801,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
     launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, nullptr, st);
     launch_cycle_init(d, kr, true, st);
-    launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    if (!scale_in_precond(c)) launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
     int launched = 0;
     // Cycles before the last one of the previous solve are queued without a host round trip:
     // the iteration count changes slowly from step to step, and a cycle queued for systems that

@@ -899,7 +899,7 @@ __device__ __forceinline__ void col_sweep(const cx<T>* buf, int px, int r0, int 
 template <typename T, int STAGE, int RX, int RY, int NTH>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
                                                cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
-                                               long long NT) {
+                                               long long NT, const double* vscale, zd* vout) {
     constexpr int RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
     __shared__ cx<T> buf[RP];
@@ -914,17 +914,24 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
     auto gidx = [&](int i) { return s.off + (long long)wrapi(tile.y0 - halo + r0 + i, s.ny) * s.nx + gx; };
     auto lidx = [&](int i) { return (r0 + i) * RX + px; };
     cx<T> X[NP], R[NP], Dd[NP];
+    // v = vscale[sys] * (the vector given) when vscale is set: the first basis vector of a restart
+    // cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to vout)
+    const double vs = vscale ? vscale[tile.sys] : 1.0;
+    auto ldv = [&](long long i) {
+        const zd u = v[i];
+        return cx<T>{T(vs * u.x), T(vs * u.y)};
+    };
     // right-hand side of the inner solve
     if constexpr (STAGE == 0) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) R[i] = ld<T>(v, gidx(i));
+        for (int i = 0; i < NP; ++i) R[i] = ldv(gidx(i));
     } else {
 #pragma unroll
         for (int i = 0; i < NP; ++i) buf[lidx(i)] = STAGE == 1 ? x1[gidx(i)] : x2[gidx(i)];
         __syncthreads();
         if constexpr (STAGE == 1) {
 #pragma unroll
-            for (int i = 0; i < NP; ++i) R[i] = ld<T>(v, NT + gidx(i));
+            for (int i = 0; i < NP; ++i) R[i] = ldv(NT + gidx(i));
             const T kap = T(s.kappa);
             col_sweep<T, NP, true, true>(buf, px, r0, RX, RY, h, T(s.kv[0]), T(s.kv[1]),
                                          [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) { R[i] = R[i] - kap * gop(Ku, Tu); });
@@ -971,8 +978,10 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
         const long long g = gidx(i);
         if constexpr (STAGE == 0) {
             x1[g] = X[i];
+            if (vscale) vout[g] = vs * v[g];
         } else if constexpr (STAGE == 1) {
             x2[g] = X[i];
+            if (vscale) vout[NT + g] = vs * v[NT + g];
         } else {
             const cx<T> chi2 = X[i];
             z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
@@ -1956,36 +1965,39 @@ template void launch_precond<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, z
 
 template <typename T, int RX, int RY, int NTH>
 static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
-                        cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+                        cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout, const int* mask,
+                        hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
-    const double pts = (double)d.NT;
+    const double pts = (double)d.NT, vb = vscale ? (double)sizeof(zd) : 0.0;
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + sizeof(cx<T>)));
+        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + sizeof(cx<T>) + vb));
         hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT);
+                           diff_iters, halo, d.NT, vscale, vout);
     }
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + 2 * sizeof(cx<T>)));
+        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + 2 * sizeof(cx<T>) + vb));
         hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT);
+                           diff_iters, halo, d.NT, vscale, vout);
     }
     ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>));
     hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                       diff_iters, halo, d.NT);
+                       diff_iters, halo, d.NT, nullptr, nullptr);
 }
 
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
-                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout,
+                         const int* mask, hipStream_t st) {
     switch (shape) {
-        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
-        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
-        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mask, st); break;
+        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
+        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
+        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
     }
 }
 template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
-                                          const int*, hipStream_t);
+                                          const double*, zd*, const int*, hipStream_t);
 template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
+                                         const double*, zd*,
                                          const int*, hipStream_t);
 
 // stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D

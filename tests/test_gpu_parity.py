@@ -308,3 +308,39 @@ def test_bcc_3d_chebyshev_step_matches_oracle(precision):
                    inner_kind=apfc.APFC_INNER_CHEB, mass_iters=4, diff_iters=4, restart=6)
     got, _, _ = run_gpu(s, [eta0], 1.0, 2)
     assert rel_l2(got[0], ref) < 1e-9
+
+
+@pytest.mark.parametrize("tile_rows", [4, 8, 16, 32])
+def test_bcc_3d_ragged_bricks(tile_rows):
+    """8 x 6 x 5 hex mesh: every brick height TY/4 in {1, 2, 4, 8} leaves a ragged last brick in z
+    (and the 64 x 4 brick footprint is ragged in x and y); nz = 5 < TY/4 + 2 makes the plane march wrap
+    around the periodic z direction more than once.  Operator apply, preconditioner and two Chebyshev
+    steps against the oracle."""
+    h = 60.0 * inputs.BCC_SPACING / 128.0
+    mesh = inputs.Mesh(3, (8, 6, 5), (8 * h, 6 * h, 5 * h))
+    o = oracle_for(mesh, bcc_k(), 0.02)
+    s = solver_for([mesh], apfc.APFC_BCC3D, [0.02], rtol=1e-12, inner_kind=apfc.APFC_INNER_CHEB,
+                   mass_iters=4, diff_iters=4, restart=6)
+    s.set_tiles(tile_rows)
+    assert s.get_tiles()[0] == tile_rows
+    zin, ein = _rand_pair(6, mesh.N, 31)
+    eta_lin = inputs.single_grain(mesh, bcc_k(), phi_of(bcc_k())(0.02), math.radians(5.0), 2 * h, seed=8)
+    d, _ = o.nodal(eta_lin)
+    for op in (apfc.APFC_OP_A, apfc.APFC_OP_PINV):
+        zo = torch.zeros((6, 2, mesh.N), dtype=torch.float64, device="cuda")
+        eo = torch.zeros_like(zo)
+        s.apply(op, [to_dev(zin)], [to_dev(ein)], [zo], [eo], 0.9, [to_dev(eta_lin)])
+        gz, ge = from_dev(zo), from_dev(eo)
+        for j in range(6):
+            if op == apfc.APFC_OP_A:
+                ref = o.block_matrix(j, d, 0.9) @ np.concatenate([zin[j], ein[j]])
+            else:
+                c1, c2 = o.precond_apply(j, zin[j], ein[j], 0.9, inner="cheb", mass_iters=4, diff_iters=4)
+                ref = np.concatenate([c1, c2])
+            got = np.concatenate([gz[j], ge[j]])
+            assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), (op, j)
+    ref = eta_lin
+    for _ in range(2):
+        _, ref = o.step(ref, 1.0)
+    got, _, _ = run_gpu(s, [eta_lin], 1.0, 2)
+    assert rel_l2(got[0], ref) < 1e-9
