@@ -1,19 +1,21 @@
 """Throughput of the APFC time step on one MI355X.
 
-A step is one apfc_step: Algorithm 1 with K = 1 (nodal nonlinearity, right-hand sides, then
-restarted FGMRES with the block preconditioner on every amplitude to ||b - A x|| <= 1e-8 ||b||).
+A step is one time step of Algorithm 1 with K = 1 (nodal nonlinearity, right-hand sides, then
+restarted FGMRES with the block preconditioner on every amplitude to ||b - A x|| <= 1e-8 ||b||); the
+K timed steps run in one apfc_run call (--per-step: one apfc_step call each).
 Workloads (seeded, synthetic, resident in HBM before the timed region starts):
 
   tri1024  (default) 1024^2 triangular-lattice polycrystal, 16 periodic Voronoi grains within +-10
-           degrees, side 400 lattice spacings, 3 amplitudes, dt = 1
+           degrees, side 400 lattice spacings, 3 amplitudes, dt = 1, 100 steps
   batch64  64 independent triangular instances of seeded size n^2, n in {128,...,512}, one rotated grain
-           each, Delta B ~ U[0.01, 0.05], all in one batched context
-  bcc128   128^3 bcc lattice (6 amplitudes), spherical grain rotated 5 degrees about [001]
+           each, Delta B ~ U[0.01, 0.05], all in one batched context, 50 steps
+  bcc128   128^3 bcc lattice (6 amplitudes), spherical grain rotated 5 degrees about [001], 20 steps
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tri1024|batch64|bcc128]
-                    [--precision mixed|fp64] [--compare] [--probe KERNEL] [--no-cpu-baseline]
+                    [--precision mixed|fp64] [--no-compare] [--probe KERNEL] [--no-cpu-baseline]
 
-Prints one JSON line; value = (sum over instances of J * N) * K / seconds of the K timed steps.
+Prints one JSON line; value = (sum over instances of J * N) * K / seconds of the K timed steps.  The
+other precision runs the same steps afterwards (unless --no-compare) for the eta and energy differences.
 """
 import argparse
 import hashlib
@@ -35,12 +37,14 @@ TRAFFIC_MD = os.path.join(ROOT, "profiles", "apply_dot_tri1024_mixed_hbm_counter
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's run length, 100 / 50 / 20)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tri1024", choices=["tri1024", "batch64", "bcc128"])
     ap.add_argument("--n", type=int, default=None, help="override the mesh side (tri1024 / bcc128)")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
-    ap.add_argument("--compare", action="store_true", help="also time the other precision on the same workload")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip the run in the other precision (FP64 vs mixed: eta and energy differences)")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
     ap.add_argument("--restart", type=int, default=4)
     ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
@@ -173,6 +177,8 @@ def cpu_baseline(args):
 
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = {"tri1024": 100, "batch64": 50, "bcc128": 20}[args.workload]
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -131,7 +131,11 @@ void launch_state_out(const Dev& d, const zd* X, double* const* eta_tab, double*
 void launch_planar_in(const Dev& d, double* const* tab, zd* half, hipStream_t st);
 void launch_planar_out(const Dev& d, const zd* half, double* const* tab, hipStream_t st);
 void launch_fill_zero(zd* p, long long n, hipStream_t st);
-void launch_extrapolate(const Dev& d, zd* X, const zd* const* h, zd* oldest, int order, hipStream_t st);
+// k_rhs_base + k_nonlinear in one pass (K = 1)
+void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_tab, double* dnode, zd* B,
+                          hipStream_t st);
+void launch_extrapolate(const Dev& d, const zd* X, const zd* const* h, zd* X0, zd* keep, int order,
+                        hipStream_t st);
 void launch_widen(const zf* in, zd* out, long long n, hipStream_t st);
 
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st);

@@ -870,22 +870,38 @@ namespace {
 // One step of Algorithm 1 on the state held in X (zeta half, eta half): RHS, K Picard iterates with the
 // nodal linearisation, FGMRES.  *max_iters receives the largest per-system iteration count.
 int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st, int* max_iters) {
-    launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
+    const int K = c->solver.picard_iters;
+    if (K == 1)
+        launch_rhs_nonlinear(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->dnode, c->B, st);
+    else
+        launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
     const int order = c->solver.x0_order;
     if (order > 0 && c->hist_n > 0 && dt != c->hist_dt) c->hist_n = 0;
-    for (int k = 0; k < c->solver.picard_iters; ++k) {
+    for (int k = 0; k < K; ++k) {
         // all amplitudes linearised at the previous iterate (Jacobi splitting)
-        launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
+        if (K > 1) launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
         if (k == 0 && order > 0) {
-            // initial guess extrapolated from the kept states; the state passed in replaces the
-            // oldest one
-            const int K = order, use = std::min(order, c->hist_n);
+            // initial guess extrapolated from the kept states; the state passed in becomes the newest
+            // kept state and the oldest one is dropped
+            const int Q = order, use = std::min(order, c->hist_n);
             const zd* h[3] = {nullptr, nullptr, nullptr};
-            for (int q = 0; q < use; ++q) h[q] = c->hist[(c->hist_newest - q + K) % K];
-            const int oldest = (c->hist_newest + 1) % K;
-            launch_extrapolate(d, c->X, h, c->hist[oldest], use, st);
+            for (int q = 0; q < use; ++q) h[q] = c->hist[(c->hist_newest - q + Q) % Q];
+            const int oldest = (c->hist_newest + 1) % Q;
+            if (!c->use_graphs) {
+                // the guess goes to the scratch buffer W, which then becomes X; the state's buffer is
+                // kept as it is as the newest state, and the dropped state's buffer becomes W
+                launch_extrapolate(d, c->X, h, c->W, nullptr, use, st);
+                zd* state = c->X;
+                c->X = c->W;
+                c->W = c->hist[oldest];
+                c->hist[oldest] = state;
+                invalidate_graphs(*c);
+            } else {
+                // captured cycles hold X's address: copy the state, extrapolate in place
+                launch_extrapolate(d, c->X, h, c->X, c->hist[oldest], use, st);
+            }
             c->hist_newest = oldest;
-            c->hist_n = std::min(c->hist_n + 1, K);
+            c->hist_n = std::min(c->hist_n + 1, Q);
             c->hist_dt = dt;
         }
         if (int rc = fgmres(c, st, max_iters); rc) {

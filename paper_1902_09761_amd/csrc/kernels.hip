@@ -375,6 +375,54 @@ __device__ __forceinline__ void bulk_h(const Terms& T, const Sys& s, const zd* e
     }
 }
 
+// bulk_h with the amplitudes in registers: JM >= T.J compile-time slots (eta zero beyond T.J), the
+// amplitude of a resonant factor picked by unrolled selects instead of a run-time array index, so nothing
+// goes through scratch memory.  Same operations in the same order as bulk_h.
+template <int JM>
+__device__ __forceinline__ zd pick(const zd (&e)[JM], int k) {
+    zd r = e[0];
+#pragma unroll
+    for (int q = 1; q < JM; ++q)
+        if (k == q) r = e[q];
+    return r;
+}
+
+template <int JM>
+__device__ __forceinline__ void bulk_h_reg(const Terms& T, const Sys& s, const zd (&eta)[JM], double& d,
+                                           zd (&h)[JM]) {
+    double A = 0.0;
+#pragma unroll
+    for (int l = 0; l < JM; ++l) A += abs2(eta[l]);
+    A *= 2.0;
+    d = 2.0 * s.a1 / s.a0 + 4.0 * s.a2 / s.a0 * A;
+    const double c4 = -4.0 * s.a2 / s.a0;
+#pragma unroll
+    for (int l = 0; l < JM; ++l) h[l] = (c4 * abs2(eta[l])) * eta[l];
+    for (int t = 0; t < T.n; ++t) {
+        const double c = term_coef(T, t, s);
+        const int ord = T.order[t];
+        zd f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const zd v = pick(eta, q < ord ? T.idx[t][q] : 0);
+            f[q] = (q < ord && T.cj[t][q]) ? cconj(v) : v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ord) break;
+            zd p{c, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < ord && r != q) p = cmul(p, f[r]);
+            const zd add = T.cj[t][q] ? p : cconj(p);
+            const int l = T.idx[t][q];
+#pragma unroll
+            for (int m = 0; m < JM; ++m)
+                if (m == l) h[m] = h[m] + add;
+        }
+    }
+}
+
 __device__ __forceinline__ double bulk_f(const Terms& T, const Sys& s, const zd* eta) {
     const int J = T.J;
     double A = 0.0, S4 = 0.0;
@@ -425,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_base(const Sys* sys, const Tile*
 }
 
 // d (per instance node) and B = [0 ; BB - kappa_j w h_j(eta_it)] for every amplitude of the instance.
-template <int DIM, int TY>
+template <int DIM, int TY, int JM>
 __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
                                                      const zd* eta_half, const zd* BB, double* dnode, zd* B,
                                                      long long NT) {
@@ -434,17 +482,61 @@ __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile
     if (s.j != 0) return;
     FOR_ROWS(TY) {
         const long long i = ((long long)pz * s.ny + y) * s.nx + x;
-        zd eta[kMaxJ], h[kMaxJ];
-        for (int l = 0; l < T.J; ++l) eta[l] = eta_half[s.off + l * s.N + i];
+        zd eta[JM], h[JM];
+#pragma unroll
+        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[s.off + l * s.N + i] : zd{0.0, 0.0};
         double d;
-        bulk_h(T, s, eta, d, h);
+        bulk_h_reg<JM>(T, s, eta, d, h);
         dnode[s.doff + i] = d;
-        for (int l = 0; l < T.J; ++l) {
+#pragma unroll
+        for (int l = 0; l < JM; ++l) {
+            if (l >= T.J) break;
             const double kap = sys[tile.sys + l].kappa;
             const long long o = s.off + l * s.N + i;
             B[o] = zd{0.0, 0.0};
             B[NT + o] = BB[o] - (kap * s.w) * h[l];
         }
+    }
+}
+
+// k_rhs_base and k_nonlinear in one pass for a step with one linearisation (K = 1): every tile of
+// amplitude j evaluates the nodal nonlinearity from all amplitudes of its instance and forms
+// M eta_j/dt (+ M s_j) at the node, writing B_j (and d, from amplitude 0's tiles) without going through
+// BB.  The same arithmetic as the two kernels.
+template <int DIM, int TY, int JM>
+__global__ __launch_bounds__(kBlock) void k_rhs_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
+                                                         const zd* eta_half, double* const* src_tab, double* dnode,
+                                                         zd* B, long long NT) {
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    const long long off0 = s.off - (long long)s.j * s.N;   // amplitude 0 of the instance
+    const double* src = src_tab ? src_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    FOR_ROWS(TY) {
+        Nbr<DIM> n;
+        make_nbr<DIM>(s, x, y, pz, n);
+        const long long i = nb_index<DIM>(n, 1, 1, 1);
+        zd eta[JM], h[JM];
+#pragma unroll
+        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[off0 + l * s.N + i] : zd{0.0, 0.0};
+        double d;
+        bulk_h_reg<JM>(T, s, eta, d, h);
+        if (s.j == 0) dnode[s.doff + i] = d;
+        zd Mu, Ku, Tu;
+        stencil<DIM, false, false, double>([&](int a, int b, int c) { return eta_half[s.off + nb_index<DIM>(n, a, b, c)]; },
+                                           s.h, s.kv[0], s.kv[1], s.kv[2], Mu, Ku, Tu);
+        zd bb = s.inv_dt * Mu;
+        if (src) {
+            zd Ms;
+            stencil<DIM, false, false, double>(
+                [&](int a, int b, int c) {
+                    const long long q = nb_index<DIM>(n, a, b, c);
+                    return zd{src[q], src[s.N + q]};
+                },
+                s.h, 0.0, 0.0, 0.0, Ms, Ku, Tu);
+            bb = bb + Ms;
+        }
+        B[s.off + i] = zd{0.0, 0.0};
+        B[NT + s.off + i] = bb - (s.kappa * s.w) * pick(h, s.j);
     }
 }
 
@@ -483,30 +575,30 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* ti
 
 // 2D column march: a thread walks rows y0-1 .. y0+RR of column x (periodic); the x pass (mass,
 // stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept for the next
-// two rows, so each input row is loaded once per field (3 loads instead of 9).  zz, ze point at the
-// zeta and eta parts of u for the system; emit(il, y1, y2) receives A_j u at node il = (x, y) for
-// y = y0 .. y0+RR-1 inside the mesh.
-template <int RR, typename T, typename EMIT>
-__device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const cx<T>* zz, const cx<T>* ze,
-                                           const double* dnode, const EMIT& emit) {
+// two rows, so each input row is loaded once per field (3 loads instead of 9).  load(f, i) returns node i
+// of the system's zeta (f = 0) or eta (f = 1) part of u; emit(il, y1, y2) receives A_j u at node
+// il = (x, y) for y = y0 .. y0+RR-1 inside the mesh.
+template <int RR, typename LOAD, typename EMIT>
+__device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LOAD& load, const double* dnode,
+                                           const EMIT& emit) {
     const int xc = x < s.nx ? x : s.nx - 1;                  // clamp for loads of ragged tiles
     const int xm = xc == 0 ? s.nx - 1 : xc - 1, xp = xc == s.nx - 1 ? 0 : xc + 1;
     const double h = s.h, m0 = h / 6.0, m1 = 4.0 * h / 6.0, ih = 1.0 / h;
     const double kx = s.kv[0], ky = s.kv[1];
     zd mz[3], kz[3], dz[3], me[3], ke[3], de[3], ce[3];
+    // first row y0 - 1, periodic; y0 itself may lie past the mesh (rows of a tile taller than the mesh)
+    int row = y0 == 0 ? s.ny - 1 : (y0 - 1) % s.ny;
 #pragma unroll
-    for (int a = 0; a < RR + 2; ++a) {
-        int row = y0 - 1 + a;
-        row = row < 0 ? row + s.ny : (row >= s.ny ? row - s.ny : row);
+    for (int a = 0; a < RR + 2; ++a, row = row + 1 == s.ny ? 0 : row + 1) {
         const long long rb = (long long)row * s.nx;
         {
-            const zd l = ld<double>(zz, rb + xm), c = ld<double>(zz, rb + xc), r = ld<double>(zz, rb + xp);
+            const zd l = load(0, rb + xm), c = load(0, rb + xc), r = load(0, rb + xp);
             mz[2] = m0 * (l + r) + m1 * c;
             kz[2] = ih * ((c + c) - (l + r));
             dz[2] = 0.5 * (r - l);
         }
         {
-            const zd l = ld<double>(ze, rb + xm), c = ld<double>(ze, rb + xc), r = ld<double>(ze, rb + xp);
+            const zd l = load(1, rb + xm), c = load(1, rb + xc), r = load(1, rb + xp);
             me[2] = m0 * (l + r) + m1 * c;
             ke[2] = ih * ((c + c) - (l + r));
             de[2] = 0.5 * (r - l);
@@ -550,7 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
     double acc[2 * NV + 1];
 #pragma unroll
     for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    colmarch_A<RR, T>(s, x, y0, Z + s.off, Z + NT + s.off, dnode, [&](long long il, const zd& y1, const zd& y2) {
+    const cx<T>* zz = Z + s.off;
+    const cx<T>* ze = Z + NT + s.off;
+    auto load = [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); };
+    colmarch_A<RR>(s, x, y0, load, dnode, [&](long long il, const zd& y1, const zd& y2) {
         W[s.off + il] = y1;
         W[NT + s.off + il] = y2;
         acc[2 * NV] += abs2(y1) + abs2(y2);
@@ -582,7 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Til
     TILE_PROLOGUE();
     const int y0 = tile.y0 + ty * RR;
     double acc[2] = {0.0, 0.0};
-    colmarch_A<RR, double>(s, x, y0, X + s.off, X + NT + s.off, dnode, [&](long long il, const zd& y1, const zd& y2) {
+    const zd* xz = X + s.off;
+    const zd* xe = X + NT + s.off;
+    auto load = [&](int f, long long i) { return (f == 0 ? xz : xe)[i]; };
+    colmarch_A<RR>(s, x, y0, load, dnode, [&](long long il, const zd& y1, const zd& y2) {
         const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
         const zd r1 = b1 - y1, r2 = b2 - y2;
         R[s.off + il] = r1;
@@ -1826,28 +1924,32 @@ __global__ __launch_bounds__(kBlock) void k_widen(const zf* in, zd* out, long lo
 }
 // Initial guess from the kept states h_1 (newest) .. h_K: the polynomial through x and the last
 // `order` kept states, evaluated one step ahead (order 0: x; 1: 2x - h1; 2: 3x - 3h1 + h2;
-// 3: 4x - 6h1 + 4h2 - h3).  The state x then replaces the oldest kept state, `oldest` (which is
-// h_order when order = K; each element is read before it is written).
-__global__ __launch_bounds__(kBlock) void k_extrapolate(zd* X, const zd* h1, const zd* h2, const zd* h3, zd* oldest,
-                                                       long long n, int order) {
+// 3: 4x - 6h1 + 4h2 - h3), written to X0.  With keep != null the state x is also copied there (the
+// oldest kept state's buffer, possibly h_order itself: each element is read before it is written); the
+// guess may then overwrite X in place.  With keep = null, X0 is a buffer of its own and X is only read
+// (the caller keeps X's buffer as the newest state).
+__global__ __launch_bounds__(kBlock) void k_extrapolate(const zd* X, const zd* h1, const zd* h2, const zd* h3,
+                                                       zd* X0, zd* keep, long long n, int order) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
         const zd x = X[i];
+        zd g = x;
         if (order == 1) {
-            X[i] = x + (x - h1[i]);
+            g = x + (x - h1[i]);
         } else if (order == 2) {
-            X[i] = h2[i] + 3.0 * (x - h1[i]);
+            g = h2[i] + 3.0 * (x - h1[i]);
         } else if (order == 3) {
-            X[i] = 4.0 * (x + h2[i]) - (6.0 * h1[i] + h3[i]);
+            g = 4.0 * (x + h2[i]) - (6.0 * h1[i] + h3[i]);
         }
-        oldest[i] = x;
+        if (keep) keep[i] = x;
+        X0[i] = g;
     }
 }
-void launch_extrapolate(const Dev& d, zd* X, const zd* const* h, zd* oldest, int order, hipStream_t st) {
+void launch_extrapolate(const Dev& d, const zd* X, const zd* const* h, zd* X0, zd* keep, int order, hipStream_t st) {
     ProbeScope ps(d, KID_OTHER, st);
     const long long n = 2 * d.NT;
     long long blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h[0], h[1], h[2], oldest, n,
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h[0], h[1], h[2], X0, keep, n,
                        order);
 }
 
@@ -1862,10 +1964,28 @@ void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* B
         hipLaunchKernelGGL((k_rhs_base<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, Xeta, src_tab, BB);
     });
 }
+// amplitude slots of the register-resident nonlinearity: 3 (triangular), 6 (bcc), else 8
+template <typename F>
+static void dispatch_jm(int J, F&& f) {
+    if (J == 3) f(std::integral_constant<int, 3>{});
+    else if (J == 6) f(std::integral_constant<int, 6>{});
+    else f(std::integral_constant<int, kMaxJ>{});
+}
 void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
-        hipLaunchKernelGGL((k_nonlinear<D(), TY()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half, BB, dnode, B,
-                           d.NT);
+        dispatch_jm(d.J, [&](auto JM) {
+            hipLaunchKernelGGL((k_nonlinear<D(), TY(), JM()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half, BB,
+                               dnode, B, d.NT);
+        });
+    });
+}
+void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_tab, double* dnode, zd* B,
+                          hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        dispatch_jm(d.J, [&](auto JM) {
+            hipLaunchKernelGGL((k_rhs_nonlinear<D(), TY(), JM()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half,
+                               src_tab, dnode, B, d.NT);
+        });
     });
 }
 void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, zd* R, double* part,

@@ -55,7 +55,7 @@ def test_autograd_checkpointed_gradient_matches_oracle():
 
 def test_differentiation_workload_finite_differences():
     """256^2 two grains (+-4 degrees), 50 FP64 steps, checkpoint every 10; loss = |eta(T) - target|^2 + E(eta(T))
-    with the target from a run at Delta B = 0.03.  Central differences (h = 1e-5) along Delta B and 3
+    with the target from a run at Delta B = 0.03.  Central differences (h = 1e-6) along Delta B and 3
     seeded directions in eta0 agree with the adjoint gradient to 1e-6."""
     from paper_1902_09761_amd import autograd as ag
     n, dt, steps, dB = 256, 1.0, 50, 0.02
@@ -79,7 +79,7 @@ def test_differentiation_workload_finite_differences():
     L = _loss(ag.run(eta0, dBt, cache, dt, steps, 10), tgt, dBt, cache, w)
     L.backward()
     g = eta0.grad.detach()
-    eps = 1e-5
+    eps = 1e-6
     fd = (loss_value(eta0.detach(), dB + eps) - loss_value(eta0.detach(), dB - eps)) / (2 * eps)
     print("dL/ddB adjoint", float(dBt.grad), "fd", fd)
     assert abs(fd - float(dBt.grad)) <= 1e-6 * abs(fd)

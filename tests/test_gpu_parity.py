@@ -344,3 +344,21 @@ def test_bcc_3d_ragged_bricks(tile_rows):
         _, ref = o.step(ref, 1.0)
     got, _, _ = run_gpu(s, [eta_lin], 1.0, 2)
     assert rel_l2(got[0], ref) < 1e-9
+
+
+@pytest.mark.parametrize("tile_rows", [8, 32])
+@pytest.mark.parametrize("inner", [apfc.APFC_INNER_CHEB, apfc.APFC_INNER_PCG])
+def test_tiles_taller_than_the_mesh(tile_rows, inner):
+    """40 x 6 nodes with tiles of 8 or 32 rows: the column march starts past the last row and wraps the
+    periodic y direction more than once; the fused preconditioner regions wrap as well."""
+    mesh = inputs.Mesh(2, (40, 6, 1), (40 * H_TRI, 6 * H_TRI, 1.0))
+    eta0 = inputs.single_grain(mesh, tri_k(), phi_of(tri_k())(0.02), math.radians(7.0), 3 * H_TRI, seed=13)
+    o = oracle_for(mesh, tri_k(), 0.02)
+    ref = eta0
+    for _ in range(3):
+        _, ref = o.step(ref, 1.0)
+    kw = {"mass_iters": 4, "diff_iters": 4} if inner == apfc.APFC_INNER_CHEB else {}
+    s = solver_for([mesh], apfc.APFC_TRI2D, [0.02], rtol=1e-12, inner_kind=inner, restart=5, **kw)
+    s.set_tiles(tile_rows)
+    got, _, _ = run_gpu(s, [eta0], 1.0, 3)
+    assert rel_l2(got[0], ref) < 1e-9
