@@ -185,7 +185,10 @@ __device__ __forceinline__ cx<R> gop(cx<R> Ku, cx<R> Tu) {
 // 3D z-marching.  The x and y passes of the separable stencil at one (x, y) column of one plane are
 // needed by the three output planes z-1, z, z+1; a thread that walks consecutive planes of its
 // column takes them once per plane and keeps the last three in registers, so each input plane is
-// loaded once per field (9 loads instead of 27 per node).  The arithmetic is that of stencil().
+// used once per field (9 values instead of 27 per node).  The arithmetic is that of stencil().
+// zmarch loads the 9 values of a plane from global memory (the operator apply and residual, whose
+// basis-vector streams dominate); zmarch_lds stages the planes of the workgroup in LDS (the Chebyshev
+// iterations, whose stencil loads dominate).
 // ------------------------------------------------------------------------------------------
 template <typename R>
 struct Plane {
@@ -251,6 +254,74 @@ __device__ __forceinline__ void zmarch(const Sys& s, int xc, int yc, int z0, R m
             P[f][1] = P[f][2];
         }
         zz = zz + 1 == s.nz ? 0 : zz + 1;
+    }
+}
+
+// 3D plane march with the planes of the workgroup's 64 x 4 columns plus a one-node halo (66 x 6) staged in
+// LDS: the workgroup loads a plane with two coalesced loads per thread and field, the next plane while
+// the current one is in use, and every thread takes its x/y pass from LDS (9 LDS reads instead of 9
+// global loads).  buf: [2][NF][66 * 6] values in the storage type S.
+constexpr int kPX = 66, kPY = 6, kPP = kPX * kPY;
+
+template <bool WK, bool WT, typename R, typename S>
+__device__ __forceinline__ Plane<R> plane_pass_lds(const cx<S>* b, int lane, int ty, R m0, R m1, R ih) {
+    const R half = R(0.5);
+    cx<R> mx[3], kx[3], dx[3];
+    Plane<R> p{};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const cx<S>* row = b + (ty + q) * kPX + lane;
+        const cx<R> l{R(row[0].x), R(row[0].y)}, c{R(row[1].x), R(row[1].y)}, r{R(row[2].x), R(row[2].y)};
+        mx[q] = m0 * (l + r) + m1 * c;
+        if (WK) kx[q] = ih * ((c + c) - (l + r));
+        if (WT) dx[q] = half * (r - l);
+        if (q == 1) p.c = c;
+    }
+    p.m = m0 * (mx[0] + mx[2]) + m1 * mx[1];
+    if (WK) p.k = (m0 * (kx[0] + kx[2]) + m1 * kx[1]) + ih * ((mx[1] + mx[1]) - (mx[0] + mx[2]));
+    if (WT) {
+        p.dx = m0 * (dx[0] + dx[2]) + m1 * dx[1];
+        p.dy = half * (mx[2] - mx[0]);
+    }
+    return p;
+}
+
+template <int RR, int NF, bool WK, bool WT, typename R, typename S, typename LOADG, typename EMIT>
+__device__ __forceinline__ void zmarch_lds(const Sys& s, const Tile& tile, int lane, int ty, cx<S> (*buf)[NF][kPP],
+                                           R m0, R m1, R ih, const LOADG& loadg, const EMIT& emit) {
+    const int e0 = (int)threadIdx.x, e1 = (int)threadIdx.x + kBlock;
+    auto goff = [&](int e) {
+        int gx = (tile.x0 - 1 + e % kPX) % s.nx, gy = (tile.y0 - 1 + e / kPX) % s.ny;
+        gx = gx < 0 ? gx + s.nx : gx;
+        gy = gy < 0 ? gy + s.ny : gy;
+        return (long long)gy * s.nx + gx;
+    };
+    const long long o0 = goff(e0), o1 = e1 < kPP ? goff(e1) : 0;
+    const long long plane = (long long)s.nx * s.ny;
+    auto fetch = [&](int b, long long base) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            buf[b][f][e0] = loadg(f, base + o0);
+            if (e1 < kPP) buf[b][f][e1] = loadg(f, base + o1);
+        }
+    };
+    Plane<R> P[NF][3];
+    int zz = tile.z == 0 ? s.nz - 1 : tile.z - 1;
+    fetch(0, zz * plane);
+#pragma unroll
+    for (int a = 0; a < RR + 2; ++a) {
+        __syncthreads();
+        const int zn = zz + 1 == s.nz ? 0 : zz + 1;
+        if (a + 1 < RR + 2) fetch((a + 1) & 1, zn * plane);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P[f][2] = plane_pass_lds<WK, WT, R>(buf[a & 1][f], lane, ty, m0, m1, ih);
+        if (a >= 2) emit(tile.z + a - 2, P);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            P[f][0] = P[f][1];
+            P[f][1] = P[f][2];
+        }
+        zz = zn;
     }
 }
 
@@ -1178,11 +1249,11 @@ __global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile
     constexpr bool WG = STAGE == 1 || STAGE == 3;
     const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
     const int y = tile.y0 + ty;
-    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
     const T k0 = T(s.kv[0]), k1 = T(s.kv[1]), k2 = T(s.kv[2]);
-    zmarch<TY / 4, 1, WG, WG, T>(
-        s, xc, yc, tile.z, m0, m1, ih, [&](int, long long i) { return ld<T>(src, s.off + i); },
+    __shared__ cx<T> buf[2][1][kPP];
+    zmarch_lds<TY / 4, 1, WG, WG, T, T>(
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return src[s.off + i]; },
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
             const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
@@ -1211,10 +1282,10 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile
     const T c1 = T(c1d), c2 = T(c2d / (OP == 0 ? s.diagM : s.diagL));
     const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
     const int y = tile.y0 + ty;
-    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
-    zmarch<TY / 4, 1, OP == 1, false, T>(
-        s, xc, yc, tile.z, m0, m1, ih, [&](int, long long i) { return ld<T>(din, s.off + i); },
+    __shared__ cx<T> buf[2][1][kPP];
+    zmarch_lds<TY / 4, 1, OP == 1, false, T, T>(
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return din[s.off + i]; },
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
             const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
