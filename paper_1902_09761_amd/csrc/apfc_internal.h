@@ -175,8 +175,6 @@ void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* 
                     zd* X, const int* mask, hipStream_t st);
 
 void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st);
-void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st);
-void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st);
 void launch_gs_reduce(const Dev& d, const Krylov& kr, int k, int phase, const double* part, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
 void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st);

@@ -1486,16 +1486,6 @@ __device__ int reorth_decide(const Krylov& kr, int s, int k) {
     return need;
 }
 
-__global__ void k_reorth_flag(Krylov kr, int S, int k) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    if (!kr.iter_active[s]) {
-        kr.reorth[s] = 0;
-        return;
-    }
-    (void)reorth_decide(kr, s, k);
-}
-
 // Column k of the Hessenberg matrix from the two projections, Givens rotations, residual estimate,
 // convergence / breakdown / restart decision for system s.
 __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
@@ -1571,12 +1561,6 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
         kr.kcount[s] = k + 1;
         kr.iter_active[s] = 0;
     }
-}
-
-__global__ void k_arnoldi(Krylov kr, int S, int k) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S || !kr.iter_active[s]) return;
-    arnoldi_update(kr, s, k);
 }
 
 // One workgroup per system: sum the 2(k+1)+1 partials of a Gram-Schmidt pass in a fixed order, then
@@ -2325,11 +2309,6 @@ void launch_gs_reduce(const Dev& d, const Krylov& kr, int k, int phase, const do
         hipLaunchKernelGGL(k_gs_reduce<2>, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, k, part, (long long)d.nchunks);
 }
 
-void launch_reorth_flag(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
-    ProbeScope ps(d, KID_SMALL, st);
-    hipLaunchKernelGGL(k_reorth_flag, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, k);
-}
-
 void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
                        const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st) {
     ProbeScope ps(d, KID_PROJ_FINAL, st, (double)(nv + 2) * 2.0 * d.NT * sizeof(zd));
@@ -2353,10 +2332,6 @@ template void launch_xupdate<float>(const Dev&, const zf*, long long, const int*
 void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);
     hipLaunchKernelGGL(k_cycle_init, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, first ? 1 : 0);
-}
-void launch_arnoldi(const Dev& d, const Krylov& kr, int k, hipStream_t st) {
-    ProbeScope ps(d, KID_SMALL, st);
-    hipLaunchKernelGGL(k_arnoldi, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, k);
 }
 void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st) {
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, kr, d.S, pub);
