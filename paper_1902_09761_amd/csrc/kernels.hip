@@ -570,44 +570,52 @@ __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile
     }
 }
 
-// k_rhs_base and k_nonlinear in one pass for a step with one linearisation (K = 1): every tile of
-// amplitude j evaluates the nodal nonlinearity from all amplitudes of its instance and forms
-// M eta_j/dt (+ M s_j) at the node, writing B_j (and d, from amplitude 0's tiles) without going through
-// BB.  The same arithmetic as the two kernels.
+// k_rhs_base and k_nonlinear in one pass for a step with one linearisation (K = 1): on the tiles of
+// amplitude 0, the nodal nonlinearity of the instance is evaluated once per node and M eta_j/dt
+// (+ M s_j) of every amplitude is formed there and used at once, instead of going through BB.  The same
+// arithmetic as the two kernels.
 template <int DIM, int TY, int JM>
 __global__ __launch_bounds__(kBlock) void k_rhs_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
                                                          const zd* eta_half, double* const* src_tab, double* dnode,
                                                          zd* B, long long NT) {
     const int* mask = nullptr;
     TILE_PROLOGUE();
-    const long long off0 = s.off - (long long)s.j * s.N;   // amplitude 0 of the instance
-    const double* src = src_tab ? src_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    if (s.j != 0) return;
+    const double* src0 = src_tab ? src_tab[s.inst] : nullptr;
     FOR_ROWS(TY) {
         Nbr<DIM> n;
         make_nbr<DIM>(s, x, y, pz, n);
         const long long i = nb_index<DIM>(n, 1, 1, 1);
         zd eta[JM], h[JM];
 #pragma unroll
-        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[off0 + l * s.N + i] : zd{0.0, 0.0};
+        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[s.off + l * s.N + i] : zd{0.0, 0.0};
         double d;
         bulk_h_reg<JM>(T, s, eta, d, h);
-        if (s.j == 0) dnode[s.doff + i] = d;
-        zd Mu, Ku, Tu;
-        stencil<DIM, false, false, double>([&](int a, int b, int c) { return eta_half[s.off + nb_index<DIM>(n, a, b, c)]; },
-                                           s.h, s.kv[0], s.kv[1], s.kv[2], Mu, Ku, Tu);
-        zd bb = s.inv_dt * Mu;
-        if (src) {
-            zd Ms;
+        dnode[s.doff + i] = d;
+#pragma unroll
+        for (int l = 0; l < JM; ++l) {
+            if (l >= T.J) break;
+            const Sys& sl = sys[tile.sys + l];
+            zd Mu, Ku, Tu;
             stencil<DIM, false, false, double>(
-                [&](int a, int b, int c) {
-                    const long long q = nb_index<DIM>(n, a, b, c);
-                    return zd{src[q], src[s.N + q]};
-                },
-                s.h, 0.0, 0.0, 0.0, Ms, Ku, Tu);
-            bb = bb + Ms;
+                [&](int a, int b, int c) { return eta_half[sl.off + nb_index<DIM>(n, a, b, c)]; }, sl.h, sl.kv[0],
+                sl.kv[1], sl.kv[2], Mu, Ku, Tu);
+            zd bb = sl.inv_dt * Mu;
+            if (src0) {
+                const double* src = src0 + (long long)l * 2 * s.N;
+                zd Ms;
+                stencil<DIM, false, false, double>(
+                    [&](int a, int b, int c) {
+                        const long long q = nb_index<DIM>(n, a, b, c);
+                        return zd{src[q], src[s.N + q]};
+                    },
+                    sl.h, 0.0, 0.0, 0.0, Ms, Ku, Tu);
+                bb = bb + Ms;
+            }
+            const long long o = sl.off + i;
+            B[o] = zd{0.0, 0.0};
+            B[NT + o] = bb - (sl.kappa * s.w) * h[l];
         }
-        B[s.off + i] = zd{0.0, 0.0};
-        B[NT + s.off + i] = bb - (s.kappa * s.w) * pick(h, s.j);
     }
 }
 
@@ -1273,9 +1281,13 @@ __global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile
         });
 }
 
-template <int TY, typename T, int OP, bool LAST>
+// FINAL (the last iteration of step 3): also step 4 of the preconditioner, z_zeta = x1 - (x2 - chi2 /
+// sqrt(dt)) / sqrt(kappa) with chi2 the new iterate (xv = the eta part of z, zz = its zeta part).
+template <int TY, typename T, int OP, bool LAST, bool FINAL = false>
 __global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
-                                                     const cx<T>* din, cx<T>* dout, cx<T>* r, cx<T>* xv) {
+                                                     const cx<T>* din, cx<T>* dout, cx<T>* r, cx<T>* xv,
+                                                     const cx<T>* x1 = nullptr, const cx<T>* x2 = nullptr,
+                                                     cx<T>* zz = nullptr) {
     TILE_PROLOGUE();
     double c1d, c2d;
     cheb_coef(OP == 0 ? s.thM : s.thL, OP == 0 ? s.deM : s.deL, j, c1d, c2d);
@@ -1294,7 +1306,42 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile
             const cx<T> q = OP == 0 ? Mu : cM * Mu + cK * Ku;
             const cx<T> rv = ld<T>(r, i) - q;
             const cx<T> dv = c1 * P[0][1].c + c2 * rv;
-            xv[i] = ld<T>(xv, i) + dv;
+            const cx<T> xn = ld<T>(xv, i) + dv;
+            xv[i] = xn;
+            if constexpr (!LAST) {
+                r[i] = rv;
+                dout[i] = dv;
+            }
+            if constexpr (FINAL) zz[i] = ld<T>(x1, i) - T(s.isq_kap) * (ld<T>(x2, i) - T(s.isq_dt) * xn);
+        });
+}
+
+// Step 1's initialisation and first Chebyshev iteration in one plane march (3D): r0 = beta1 (the zeta part
+// of v), d0 = x0 = r0/(theta D) formed from v as the planes are staged, then r1 = r0 - M d0,
+// d1 = c1 d0 + c2 D^{-1} r1, x1 = x0 + d1.  Same arithmetic as k_cb_init (stage 0) + k_cb_iter3d (j = 1).
+template <int TY, typename T, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                      const zd* v, cx<T>* dout, cx<T>* r, cx<T>* xv) {
+    TILE_PROLOGUE();
+    const T scale = T(1.0 / (s.thM * s.diagM));
+    double c1d, c2d;
+    cheb_coef(s.thM, s.deM, 1, c1d, c2d);
+    const T c1 = T(c1d), c2 = T(c2d / s.diagM);
+    const int y = tile.y0 + ty;
+    const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
+    __shared__ cx<T> buf[2][1][kPP];
+    zmarch_lds<TY / 4, 1, false, false, T, T>(
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih,
+        [&](int, long long i) { return scale * ld<T>(v, s.off + i); },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
+            cx<T> Mu, Ku, Tu;
+            zcombine<false, false, T>(P[0][0], P[0][1], P[0][2], m0, m1, ih, T(0), T(0), T(0), Mu, Ku, Tu);
+            const cx<T> d0 = P[0][1].c;
+            const cx<T> rv = ld<T>(v, i) - Mu;
+            const cx<T> dv = c1 * d0 + c2 * rv;
+            xv[i] = d0 + dv;
             if constexpr (!LAST) {
                 r[i] = rv;
                 dout[i] = dv;
@@ -2209,11 +2256,62 @@ static void cb_iterations(const Dev& d, int its, cx<T>* d0, cx<T>* d1, cx<T>* r,
     }
 }
 
+// 3D Chebyshev iterations j0 .. its-1 of one inner solve; with x1 and x2 set, the last one also does
+// step 4 of the preconditioner (k_cb_iter3d FINAL).
+template <int TYv, typename T, int OP>
+static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1, cx<T>* r, cx<T>* xv,
+                            const cx<T>* x1, const cx<T>* x2, cx<T>* zz, const int* mask, hipStream_t st) {
+    cx<T>* D[2] = {d0, d1};
+    for (int j = j0; j < its; ++j) {
+        const bool last = j == its - 1;
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (last ? (x1 ? 6.0 : 3.0) : 6.0));
+        if (last && x1)
+            hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, true, true>), TILE_GRID, d.sys, d.tiles, mask, j,
+                               D[(j - 1) & 1], D[j & 1], r, xv, x1, x2, zz);
+        else if (last)
+            hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j, D[(j - 1) & 1],
+                               D[j & 1], r, xv, nullptr, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, false>), TILE_GRID, d.sys, d.tiles, mask, j,
+                               D[(j - 1) & 1], D[j & 1], r, xv, nullptr, nullptr, nullptr);
+    }
+}
+
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
                                  cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
+        if constexpr (DIM == 3) {
+            // step 1: initialisation fused with the first iteration
+            if (mass_iters >= 2) {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + (mass_iters == 2 ? 1.0 : 3.0) * sizeof(cx<T>)));
+                if (mass_iters == 2)
+                    hipLaunchKernelGGL((k_cb_first3d<TYv, T, true>), TILE_GRID, d.sys, d.tiles, mask, v, d1, r, x1);
+                else
+                    hipLaunchKernelGGL((k_cb_first3d<TYv, T, false>), TILE_GRID, d.sys, d.tiles, mask, v, d1, r, x1);
+            } else {
+                cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+            }
+            // d1 holds d_1: iterations j >= 2 read D[(j - 1) & 1] = d1 first
+            cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
+            {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 4.0 * sizeof(cx<T>)));
+                cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
+            }
+            cb_iterations3d<TYv, T, 1>(d, 1, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
+            {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>));
+                cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, d0, z + d.NT, st);
+            }
+            // steps 3 and 4: the last iteration also forms z_zeta
+            cb_iterations3d<TYv, T, 1>(d, 1, diff_iters, d0, d1, r, z + d.NT, x1, x2, z, mask, st);
+            if (diff_iters < 2) {
+                ProbeScope ps(d, KID_PC_FINAL, st);
+                hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);
+            }
+            return;
+        }
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 3.0 * sizeof(cx<T>)));
             cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
