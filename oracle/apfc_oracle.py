@@ -323,14 +323,19 @@ def kron_matrices(grid: Grid, kvecs: np.ndarray):
 # ---------------------------------------------------------------------------------------
 
 class Oracle:
-    def __init__(self, grid: Grid, kvecs: np.ndarray, params: Params):
+    def __init__(self, grid: Grid, kvecs: np.ndarray, params: Params, assembly: str = "element"):
+        """assembly = "element" (element loop, the default) or "kron" (the same matrices from 1D
+        stencils, pinned equal to the element loop; for meshes too large for the element loop)."""
         self.grid = grid
         self.k = np.asarray(kvecs, float)
         self.J = len(self.k)
         self.params = params
         self.kappa = kappas(self.k, params)
         self.bulk = BulkEnergy(self.k, params)
-        self.M, self.K, self.T = assemble(grid, self.k)
+        if assembly == "kron":
+            self.M, self.K, self.T = kron_matrices(grid, self.k)
+        else:
+            self.M, self.K, self.T = assemble(grid, self.k)
         self.G = [(-self.K + 1j * Tj).tocsr() for Tj in self.T]
         self._Mlu = None
 
@@ -347,6 +352,14 @@ class Oracle:
         kap = self.kappa[j]
         B = (self.M / dt + kap * w * sp.diags(d)).astype(np.complex128)
         return sp.bmat([[self.M.astype(np.complex128), -self.G[j]], [kap * self.G[j], B]], format="csc")
+
+    def apply_block(self, j: int, d: np.ndarray, dt: float, zeta_j, eta_j):
+        """A_j [zeta_j; eta_j] block by block (Eq. (11)), without forming the 2N x 2N matrix:
+        (M zeta - G eta, kappa G zeta + M eta/dt + kappa w d eta)."""
+        kap, w = self.kappa[j], self.grid.w
+        y1 = self.M @ zeta_j - self.G[j] @ eta_j
+        y2 = kap * (self.G[j] @ zeta_j) + self.M @ eta_j / dt + (kap * w) * d * eta_j
+        return y1, y2
 
     def rhs(self, j: int, eta_prev_j, h_j, dt: float, source_j=None):
         """b_j = [0 ; M eta_j^{m-1}/dt - kappa_j w h_j (+ M s_j)] (R1, R8)."""

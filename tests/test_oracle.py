@@ -56,6 +56,26 @@ def test_element_assembly_matches_kronecker(dim, n):
         assert abs(a - b).max() < 1e-14
 
 
+@pytest.mark.parametrize("dim,n", [(2, (6, 5)), (3, (4, 5, 4))])
+def test_block_apply_and_kron_oracle(dim, n):
+    """Oracle.apply_block equals the assembled block matrix times the vector, and an oracle built from
+    the Kronecker matrices gives the same block operator as the element loop."""
+    L = tuple(2.3 * x for x in n)
+    g = Grid(dim, n, L)
+    k = tri_k() if dim == 2 else bcc_k()
+    p = Params.from_dB(0.02)
+    o, ok = Oracle(g, k, p), Oracle(g, k, p, assembly="kron")
+    rng = np.random.default_rng(5)
+    d = 0.02 + 0.1 * rng.random(g.N)
+    z = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    e = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    for j in range(len(k)):
+        ref = o.block_matrix(j, d, 0.8) @ np.concatenate([z, e])
+        for oo in (o, ok):
+            y1, y2 = oo.apply_block(j, d, 0.8, z, e)
+            assert np.max(np.abs(np.concatenate([y1, y2]) - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
 def test_element_matrices_exact_integrals():
     """Hand-computed 1D integrals: int psi0^2 = h/3, int psi0 psi1 = h/6, int psi0'^2 = 1/h,
     int psi0' psi0 = -1/2; 2D mass entries are products of these."""
