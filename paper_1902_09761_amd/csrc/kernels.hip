@@ -1079,7 +1079,11 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
                                                long long NT, const double* vscale, zd* vout) {
     constexpr int RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
-    __shared__ cx<T> buf[RP];
+    // FP32: two region buffers used in turn, so each iteration needs one barrier (its writes go to the
+    // buffer the previous iteration did not read); FP64 regions are too large to double
+    constexpr int NB = sizeof(T) == 4 ? 2 : 1;
+    __shared__ cx<T> bufs[NB][RP];
+    cx<T>* buf = bufs[0];
     const CTile tile = tiles[blockIdx.x];
     if (mask && !mask[tile.sys]) return;
     const Sys s = sys[tile.sys];
@@ -1131,13 +1135,14 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
         X[i] = Dd[i];
     }
     for (int k = 1; k < its; ++k) {
-        __syncthreads();
+        cx<T>* b = bufs[NB == 2 ? (k & 1) : 0];
+        if constexpr (NB == 1) __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NP; ++i) buf[lidx(i)] = Dd[i];
+        for (int i = 0; i < NP; ++i) b[lidx(i)] = Dd[i];
         __syncthreads();
         const T rn = T(1) / (T(2) * sig - rho);
         const T c1 = rn * rho, c2 = T(2) * rn / de * iD;
-        col_sweep<T, NP, !isM, false>(buf, px, r0, RX, RY, h, T(0), T(0), [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) {
+        col_sweep<T, NP, !isM, false>(b, px, r0, RX, RY, h, T(0), T(0), [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) {
             const cx<T> q = isM ? Mu : cM * Mu + cK * Ku;
             R[i] = R[i] - q;
             Dd[i] = c1 * Dd[i] + c2 * R[i];
