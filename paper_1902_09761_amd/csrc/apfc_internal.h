@@ -118,6 +118,7 @@ struct Krylov {
     int* iters;         // [S]
     int* cycles;        // [S]
     int* err;           // [1]
+    int* tick_c;        // [S] workgroups of the system done in the current second-pass launch
     int m;
     int nv1;            // 2*(m+1)
     double rtol;
@@ -162,8 +163,10 @@ void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1,
 
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
+// second Gram-Schmidt pass on the systems flagged for it; the last workgroup of each such system also
+// reduces the pass (phase 2 of the Gram-Schmidt reduction)
 void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 double* part, const int* mask, hipStream_t st);
+                 double* part, const int* mask, const Krylov& kr, int k, hipStream_t st);
 template <typename T>
 void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const zd* V, long long vstride, int nv,
                       double* part, const int* mask, hipStream_t st);
@@ -175,7 +178,8 @@ void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* 
                     zd* X, const int* mask, hipStream_t st);
 
 void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st);
-void launch_gs_reduce(const Dev& d, const Krylov& kr, int k, int phase, const double* part, hipStream_t st);
+// phase 1 of the Gram-Schmidt reduction (phase 2 runs inside k_mdot)
+void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
 void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st);
 

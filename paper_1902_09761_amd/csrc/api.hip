@@ -348,6 +348,7 @@ size_t carve(apfc_ctx& c, char* base) {
     k.iters = (int*)take(sizeof(int) * S);
     k.cycles = (int*)take(sizeof(int) * S);
     k.err = (int*)take(sizeof(int) * 4);
+    k.tick_c = (int*)take(sizeof(int) * S);
     c.run_it_sum = (long long*)take(sizeof(long long) * S);
     c.run_it_max = (int*)take(sizeof(int) * S);
     c.run_cyc_max = (int*)take(sizeof(int) * S);
@@ -647,6 +648,8 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
     c->ws_bytes = bytes;
     c->hist_n = 0;
     carve(*c, c->ws);
+    // the tickets of the fused second-pass reduction start at zero; every launch leaves them at zero
+    HIPCHK(hipMemset(c->kr.tick_c, 0, sizeof(int) * c->S));
     return upload_tables(*c);
 }
 
@@ -738,9 +741,8 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
     // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
-    launch_gs_reduce(d, kr, k, 1, c->apart, st);
-    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, st);
-    launch_gs_reduce(d, kr, k, 2, c->cpart, st);
+    launch_gs_reduce1(d, kr, k, c->apart, st);
+    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, kr, k, st);
     launch_proj_final(d, c->V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), c->V + (k + 1) * vs, act, st);
 }
 

@@ -93,6 +93,29 @@ __device__ __forceinline__ void sum_partials(const double* part, long long P, co
     __syncthreads();
 }
 
+// The workgroups of one system write their partials, then count themselves on the system's ticket; the
+// last one to arrive (device-wide) sees every partial and runs the per-system reduction in the fixed
+// order a kernel of its own would, and re-arms the ticket.  No workgroup waits for another.  The
+// device-scope release fence this needs writes back the L2, so it is used only where few workgroups
+// take part (the second Gram-Schmidt pass, which runs only for systems that need it).
+__device__ __forceinline__ bool last_of_system(int* ticket, int si, int n, int* flag_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                      // this workgroup's partials before its ticket
+        const int t = atomicAdd(&ticket[si], 1);
+        const int last = t == n - 1;
+        if (last) ticket[si] = 0;
+        *flag_lds = last;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last) __threadfence();                // the other workgroups' partials after their tickets
+    return last;
+}
+
+template <int PHASE>
+__device__ void gs_reduce_sys(const Sys* sys, const Krylov& kr, int k, const double* part, long long P, int si);
+
 // ------------------------------------------------------------------------------------------
 // geometry: periodic neighbours of node (x, y, z)
 // ------------------------------------------------------------------------------------------
@@ -1377,7 +1400,8 @@ __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long
 template <int NV>
 __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const zd* V,
                                                 long long vstride, int nv, const zd* w, const double* coef,
-                                                int coef_ld, double* part, int nchunks, long long NT) {
+                                                int coef_ld, double* part, int nchunks, long long NT, Krylov kr,
+                                                int kit) {
     constexpr int EPT = kChunk / kBlock;
     __shared__ double lds[4 * (2 * NV + 1)];
     __shared__ zd cf[NV];
@@ -1416,6 +1440,8 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
         }
         part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
     }
+    __shared__ int flag;
+    if (last_of_system(kr.tick_c, ch.sys, s.cend - s.cbeg, &flag)) gs_reduce_sys<2>(sys, kr, kit, part, nchunks, ch.sys);
 }
 
 // out = (w - sum_l hcoef_l V_l) * hinv
@@ -1618,21 +1644,17 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
 // One workgroup per system: sum the 2(k+1)+1 partials of a Gram-Schmidt pass in a fixed order, then
 // (thread 0) PHASE 1: decide on the second pass and, if it is skipped, finish the Arnoldi step;
 // PHASE 2: finish the Arnoldi step with both passes.
+// Per-system reduction of a Gram-Schmidt pass (one whole workgroup): sum the 2(k+1)+1 partials in a
+// fixed order, one wave per value, then (phase 1) decide the second pass or (phase 2, or phase 1
+// without a second pass) update the Hessenberg column.
 template <int PHASE>
-__global__ __launch_bounds__(kBlock) void k_gs_reduce(const Sys* sys, Krylov kr, int k, const double* part,
-                                                     long long P) {
-    const int si = blockIdx.x;
-    if (PHASE == 1 && !kr.iter_active[si]) {
-        if (threadIdx.x == 0) kr.reorth[si] = 0;
-        return;
-    }
-    if (PHASE == 2 && !kr.reorth[si]) return;
+__device__ void gs_reduce_sys(const Sys* sys, const Krylov& kr, int k, const double* part, long long P, int si) {
     const Sys s = sys[si];
     const int beg = PHASE == 1 ? s.tbeg : s.cbeg, end = PHASE == 1 ? s.tend : s.cend;
     const int nvals = 2 * (k + 1) + 1;
     double* out = (PHASE == 1 ? kr.red1 : kr.red2) + (long long)si * (kr.nv1 + 1);
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int v = wv; v < nvals; v += 4) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (int)blockDim.x >> 6;
+    for (int v = wv; v < nvals; v += nw) {
         double a = 0.0;
         for (int t = beg + lane; t < end; t += 64) a += part[v * P + t];
         a = wave_sum(a);
@@ -1643,6 +1665,18 @@ __global__ __launch_bounds__(kBlock) void k_gs_reduce(const Sys* sys, Krylov kr,
     if (threadIdx.x == 0) {
         if (PHASE == 2 || !reorth_decide(kr, si, k)) arnoldi_update(kr, si, k);
     }
+}
+
+// Phase 1 as a kernel: one workgroup of kRedBlock threads per system.
+constexpr int kRedBlock = 1024;
+__global__ __launch_bounds__(kRedBlock) void k_gs_reduce1(const Sys* sys, Krylov kr, int k, const double* part,
+                                                        long long P) {
+    const int si = blockIdx.x;
+    if (!kr.iter_active[si]) {
+        if (threadIdx.x == 0) kr.reorth[si] = 0;
+        return;
+    }
+    gs_reduce_sys<1>(sys, kr, k, part, P, si);
 }
 
 // Summary flags for the host, written to mapped host memory: any system still solving, the
@@ -2365,12 +2399,12 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
 }
 
 void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 double* part, const int* mask, hipStream_t st) {
+                 double* part, const int* mask, const Krylov& kr, int k, hipStream_t st) {
     // reads w and nv basis vectors (full vectors of 2 NT complex doubles)
     ProbeScope ps(d, KID_MDOT, st, (double)(nv + 1) * 2.0 * d.NT * sizeof(zd));
     auto go = [&](auto nvc) {
         hipLaunchKernelGGL((k_mdot<decltype(nvc)::value>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
-                           coef, coef_ld, part, d.nchunks, d.NT);
+                           coef, coef_ld, part, d.nchunks, d.NT, kr, k);
     };
     if (nv <= 4) go(std::integral_constant<int, 4>{});
     else if (nv <= 8) go(std::integral_constant<int, 8>{});
@@ -2404,12 +2438,9 @@ template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*
 template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zd*, long long, int, double*,
                                       const int*, hipStream_t);
 
-void launch_gs_reduce(const Dev& d, const Krylov& kr, int k, int phase, const double* part, hipStream_t st) {
+void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st) {
     ProbeScope ps(d, KID_REDUCE, st);
-    if (phase == 1)
-        hipLaunchKernelGGL(k_gs_reduce<1>, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, k, part, (long long)d.ntiles);
-    else
-        hipLaunchKernelGGL(k_gs_reduce<2>, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, k, part, (long long)d.nchunks);
+    hipLaunchKernelGGL(k_gs_reduce1, dim3(d.S), dim3(kRedBlock), 0, st, d.sys, kr, k, part, (long long)d.ntiles);
 }
 
 void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,

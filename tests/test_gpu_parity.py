@@ -362,3 +362,22 @@ def test_tiles_taller_than_the_mesh(tile_rows, inner):
     s.set_tiles(tile_rows)
     got, _, _ = run_gpu(s, [eta0], 1.0, 3)
     assert rel_l2(got[0], ref) < 1e-9
+
+
+@pytest.mark.parametrize("precision", [apfc.APFC_FP64, apfc.APFC_MIXED])
+def test_second_gram_schmidt_pass(precision):
+    """rtol 5e-14 sets the second-pass threshold to (100 eps / rtol)^2 = 0.19 (re-orthogonalise
+    whenever the first pass removed more than 81% of |w|^2), so the second pass and its fused reduction
+    run in many iterations; 4 steps of the 64^2 grain (mixed precision at rtol 1e-12: 3 steps) against
+    the oracle."""
+    wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
+    o = oracle_for(wl.mesh, tri_k(), wl.dB)
+    steps = 4 if precision == apfc.APFC_FP64 else 3
+    ref = wl.eta0
+    for _ in range(steps):
+        _, ref = o.step(ref, wl.dt)
+    rtol = 5e-14 if precision == apfc.APFC_FP64 else 1e-12
+    s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB], rtol=rtol, precision=precision,
+                   inner_kind=apfc.APFC_INNER_CHEB, mass_iters=5, diff_iters=3, restart=8, max_iters=2000)
+    got, _, infos = run_gpu(s, [wl.eta0], wl.dt, steps)
+    assert rel_l2(got[0], ref) < 1e-10
