@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--per-step", action="store_true",
                     help="one apfc_step call per step instead of one apfc_run call for the K steps")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiles", default=None,
+                    help="ROWS[,REGION]: fixed tile rows (and fused-preconditioner region) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 256 MiB device-to-device (reference for HBM counters)")
@@ -101,7 +103,10 @@ def run_gpu(args, precision, probe=None):
     ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
     s = apfc.Solver(ms, lat, ps)
     s.set_graphs(args.graphs)
-    if not args.no_autotune:
+    if args.tiles:
+        tr = [int(v) for v in args.tiles.split(",")]
+        s.set_tiles(tr[0], tr[1] if len(tr) > 1 else 0)
+    elif not args.no_autotune:
         s.autotune()
     ty = s.get_tiles()
     ets = [torch.tensor(inputs.to_planar(w.eta0), dtype=torch.float64, device="cuda") for w in wls]
@@ -140,16 +145,17 @@ def run_gpu(args, precision, probe=None):
     return out
 
 
-def traffic_from_profile():
+def traffic_from_profile(tile_rows):
     """HBM bytes per k_apply_dot launch from the committed counter summary, if it was taken with the
-    current kernel source (null otherwise)."""
+    current kernel source and the same tile rows (null otherwise)."""
     if not os.path.exists(TRAFFIC_MD):
         return None, None
     text = open(TRAFFIC_MD).read()
     m1 = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
     m2 = re.search(r"kernels_hip_sha256:\s*([0-9a-f]+)", text)
+    m3 = re.search(r"tile_rows:\s*([0-9]+)", text)
     sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
-    if not (m1 and m2) or m2.group(1) != sha:
+    if not (m1 and m2 and m3) or m2.group(1) != sha or int(m3.group(1)) != tile_rows:
         return None, os.path.relpath(TRAFFIC_MD, ROOT)
     return float(m1.group(1)), os.path.relpath(TRAFFIC_MD, ROOT)
 
@@ -214,8 +220,9 @@ def main():
     if pr and pr["launches"] > 0:
         avg_ms = pr["ms"] / pr["launches"]
         ach = pr["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-        traffic, src = traffic_from_profile() if (pr["kernel"] == "apply" and args.workload == "tri1024"
-                                                 and args.precision == "mixed") else (None, None)
+        traffic, src = (traffic_from_profile(res["tile_rows"][0])
+                        if (pr["kernel"] == "apply" and args.workload == "tri1024" and args.precision == "mixed")
+                        else (None, None))
         line["roofline"] = {"bound": "hbm", "kernel": "k_apply_dot" if pr["kernel"] == "apply" else pr["kernel"],
                             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                             "traffic": traffic, "traffic_source": src, "avg_launch_us": 1e3 * avg_ms,

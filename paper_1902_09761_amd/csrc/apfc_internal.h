@@ -14,6 +14,7 @@ constexpr int kChunk = 2048;     // elements of a full vector per Krylov workgro
 constexpr int kMaxJ = 8;
 constexpr int kMaxTerms = 24;
 constexpr int kMaxRestart = 32;
+constexpr int kMaxCheb = 64;     // Chebyshev iterations per inner solve
 
 // Complex value stored as two reals (re, im), 2*sizeof(R)-aligned for vector loads.
 template <typename R>
@@ -39,6 +40,11 @@ struct Sys {
     // Chebyshev parameters (centre theta, half width delta) of the Jacobi-scaled spectra of M and
     // L = M/sqrt(dt) + sqrt(kappa) K on the periodic uniform mesh
     double thM, deM, thL, deL;
+    // Chebyshev scalars of the two inner operators (0: M, 1: L), folded with the Jacobi diagonal D:
+    // cb[op][0][0] = 1/(theta D) (d_0 = cb r_0), and for j >= 1 cb[op][j] = {rho_j rho_{j-1}, 2 rho_j/(delta D)}
+    // with rho_0 = delta/theta, rho_j = 1/(2 theta/delta - rho_{j-1}).  Indexed dynamically, so kernels
+    // read it through the Sys pointer, not from a local copy.
+    double cb[2][kMaxCheb][2];
 };
 
 struct Tile { int sys, x0, y0, z; };

@@ -245,6 +245,22 @@ void cheb_bounds(const Sys& y, double& thM, double& deM, double& thL, double& de
     deL = 0.5 * (mxL - mnL);
 }
 
+void cheb_table(Sys& y) {
+    const double th[2] = {y.thM, y.thL}, de[2] = {y.deM, y.deL}, dg[2] = {y.diagM, y.diagL};
+    for (int op = 0; op < 2; ++op) {
+        const double sig = th[op] / de[op];
+        double rho = 1.0 / sig;
+        y.cb[op][0][0] = 1.0 / (th[op] * dg[op]);
+        y.cb[op][0][1] = 0.0;
+        for (int j = 1; j < kMaxCheb; ++j) {
+            const double rn = 1.0 / (2.0 * sig - rho);
+            y.cb[op][j][0] = rn * rho;
+            y.cb[op][j][1] = 2.0 * rn / (de[op] * dg[op]);
+            rho = rn;
+        }
+    }
+}
+
 void set_dt_scalars(apfc_ctx& c, double dt) {
     for (auto& y : c.sys) {
         y.inv_dt = 1.0 / dt;
@@ -253,6 +269,7 @@ void set_dt_scalars(apfc_ctx& c, double dt) {
         y.isq_kap = 1.0 / std::sqrt(y.kappa);
         y.diagL = y.diagM * y.isq_dt + y.sq_kap * y.diagK;
         cheb_bounds(y, y.thM, y.deM, y.thL, y.deL);
+        cheb_table(y);
     }
     c.dt = dt;
 }
@@ -407,7 +424,7 @@ int check_params(const apfc_params& p) {
     if (p.restart < 1 || p.restart > kMaxRestart) return fail(APFC_ERR_INVALID, "params.restart must be in [1,32]");
     if (p.max_iters < 1) return fail(APFC_ERR_INVALID, "params.max_iters must be >= 1");
     if (p.precision != APFC_FP64 && p.precision != APFC_MIXED) return fail(APFC_ERR_INVALID, "params.precision");
-    if (p.mass_iters < 1 || p.mass_iters > 64 || p.diff_iters < 1 || p.diff_iters > 64)
+    if (p.mass_iters < 1 || p.mass_iters > kMaxCheb || p.diff_iters < 1 || p.diff_iters > kMaxCheb)
         return fail(APFC_ERR_INVALID, "params: inner iterations must be in [1,64]");
     if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB)
         return fail(APFC_ERR_INVALID, "params.inner_kind");

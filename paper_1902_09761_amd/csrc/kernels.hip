@@ -1065,35 +1065,41 @@ __device__ __forceinline__ int wrapi(int g, int n) {
     return g < 0 ? g + n : g;
 }
 
-// Stencils at NP consecutive rows r0..r0+NP-1 of column px of an LDS region (RX x RY, clamped at
-// the region border), streamed row by row: the x pass of each of the NP+2 rows involved is
-// evaluated once, and f(i, Mu, Ku, Tu) is called for row r0+i as soon as its three rows are known,
-// so only three rows of x-pass values are live at a time.
-template <typename T, int NP, bool WK, bool WT, typename F>
-__device__ __forceinline__ void col_sweep(const cx<T>* buf, int px, int r0, int RX, int RY, T h, T k0, T k1,
-                                          F&& f) {
-    const T m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h, half = T(0.5);
+// The operators of the inner solves in split form.  With P = [1 4 1], Q = [-1 2 -1] = 6 delta - P and
+// E = [-1 0 1], the bilinear element stencils are M = (h/6)^2 P(x)P,
+// K = (1/6)(Q(x)P + P(x)Q) = (delta(x)P + P(x)delta) - P(x)P/3 and T_j = (h/6)(k0 E(x)P + k1 P(x)E).
+// At a node with rows A, B, C (y - 1, y, y + 1), x passes p = P u and e = E u of those rows and centre
+// values uA, uB, uC:
+//   (cM M + cK K) u = a (pA + pC) + b pB + c (uA + uC) + d uB,
+//   a = cM (h/6)^2 - cK/3,  b = 4 a + cK,  c = cK,  d = 4 cK   (M alone: a = (h/6)^2, b = 4 a, c = d = 0),
+//   T_j u = (h/6) (k0 (eA + 4 eB + eC) + k1 (pC - pA)).
+// split_sweep streams rows r0 - 1 .. r0 + NP of column px of an LDS region (clamped at the region
+// border) and calls f(i, pA, pB, pC, uA, uB, uC, eA, eB, eC) for row r0 + i (e only with WE).
+template <typename T, int NP, bool WE, typename F>
+__device__ __forceinline__ void split_sweep(const cx<T>* buf, int px, int r0, int RX, int RY, F&& f) {
     const int xm = px > 0 ? px - 1 : px, xp = px < RX - 1 ? px + 1 : px;
     const cx<T> zero{T(0), T(0)};
-    cx<T> mA = zero, mB = zero, kA = zero, kB = zero, dA = zero, dB = zero;
+    cx<T> pA = zero, pB = zero, uA = zero, uB = zero, eA = zero, eB = zero;
 #pragma unroll
     for (int a = 0; a < NP + 2; ++a) {
         int row = r0 - 1 + a;
         row = row < 0 ? 0 : (row > RY - 1 ? RY - 1 : row);
         const cx<T> l = buf[row * RX + xm], c = buf[row * RX + px], r = buf[row * RX + xp];
-        const cx<T> mC = m0 * (l + r) + m1 * c;
-        const cx<T> kC = WK ? ih * ((c + c) - (l + r)) : zero;
-        const cx<T> dC = WT ? half * (r - l) : zero;
-        if (a >= 2) {
-            const cx<T> Mu = m0 * (mA + mC) + m1 * mB;
-            const cx<T> Ku = WK ? m0 * (kA + kC) + m1 * kB + ih * ((mB + mB) - (mA + mC)) : zero;
-            const cx<T> Tu = WT ? T(2) * (k0 * (m0 * (dA + dC) + m1 * dB) + k1 * half * (mC - mA)) : zero;
-            f(a - 2, Mu, Ku, Tu);
-        }
-        mA = mB; mB = mC;
-        kA = kB; kB = kC;
-        dA = dB; dB = dC;
+        const cx<T> pC = T(4) * c + (l + r);
+        const cx<T> eC = WE ? r - l : zero;
+        if (a >= 2) f(a - 2, pA, pB, pC, uA, uB, c, eA, eB, eC);
+        pA = pB; pB = pC;
+        uA = uB; uB = c;
+        eA = eB; eB = eC;
     }
+}
+
+struct SplitCoef {
+    double a, b, c, d;
+};
+__host__ __device__ inline SplitCoef split_coef(double h, double cM, double cK) {
+    const double m = (h / 6.0) * (h / 6.0), a = cM * m - cK / 3.0;
+    return {a, 4.0 * a + cK, cK, 4.0 * cK};
 }
 
 template <typename T, int STAGE, int RX, int RY, int NTH>
@@ -1111,7 +1117,6 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
     if (mask && !mask[tile.sys]) return;
     const Sys s = sys[tile.sys];
     const int IX = RX - 2 * halo, IY = RY - 2 * halo;
-    const T h = T(s.h);
     // thread -> region column px and NP consecutive rows r0 .. r0 + NP - 1
     const int px = threadIdx.x % RX, r0 = (threadIdx.x / RX) * NP;
     const long long gx = wrapi(tile.x0 - halo + px, s.nx);
@@ -1136,25 +1141,34 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
         if constexpr (STAGE == 1) {
 #pragma unroll
             for (int i = 0; i < NP; ++i) R[i] = ldv(NT + gidx(i));
-            const T kap = T(s.kappa);
-            col_sweep<T, NP, true, true>(buf, px, r0, RX, RY, h, T(s.kv[0]), T(s.kv[1]),
-                                         [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) { R[i] = R[i] - kap * gop(Ku, Tu); });
+            // r = beta2 - kappa G x1 with G = -K + i T_j: r += kappa K x1 - i kappa T_j x1
+            const T k3 = T(s.kappa / 3.0), k4 = T(4.0 * s.kappa), kap = T(s.kappa);
+            const T g0 = T(s.kappa * s.h / 6.0 * s.kv[0]), g1 = T(s.kappa * s.h / 6.0 * s.kv[1]);
+            split_sweep<T, NP, true>(buf, px, r0, RX, RY,
+                                     [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC,
+                                         cx<T> eA, cx<T> eB, cx<T> eC) {
+                                         const cx<T> kk = kap * (uA + uC) + k4 * uB - k3 * ((pA + pC) + pB);
+                                         const cx<T> tt = g0 * (T(4) * eB + (eA + eC)) + g1 * (pC - pA);
+                                         R[i] = R[i] + cx<T>{kk.x + tt.y, kk.y - tt.x};
+                                     });
         } else {
-            col_sweep<T, NP, false, false>(buf, px, r0, RX, RY, h, T(0), T(0),
-                                           [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) { R[i] = Mu; });
+            const SplitCoef m = split_coef(s.h, 1.0, 0.0);
+            const T ma = T(m.a), mb = T(m.b);
+            split_sweep<T, NP, false>(buf, px, r0, RX, RY,
+                                      [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T>, cx<T>, cx<T>, cx<T>, cx<T>,
+                                          cx<T>) { R[i] = ma * (pA + pC) + mb * pB; });
         }
     }
     // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
     constexpr bool isM = STAGE == 0;
     const int its = isM ? sM : sL;
-    const T th = T(isM ? s.thM : s.thL), de = T(isM ? s.deM : s.deL);
-    const T iD = T(1.0 / (isM ? s.diagM : s.diagL));
-    const T cM = isM ? T(1) : T(s.isq_dt), cK = isM ? T(0) : T(s.sq_kap);
-    const T sig = th / de;
-    T rho = T(1) / sig;
+    const double(*cb)[2] = sys[tile.sys].cb[isM ? 0 : 1];
+    const SplitCoef oc = split_coef(s.h, isM ? 1.0 : s.isq_dt, isM ? 0.0 : s.sq_kap);
+    const T oa = T(oc.a), ob = T(oc.b), occ = T(oc.c), od = T(oc.d);
+    const T d0 = T(cb[0][0]);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        Dd[i] = (iD / th) * R[i];
+        Dd[i] = d0 * R[i];
         X[i] = Dd[i];
     }
     for (int k = 1; k < its; ++k) {
@@ -1163,15 +1177,16 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
 #pragma unroll
         for (int i = 0; i < NP; ++i) b[lidx(i)] = Dd[i];
         __syncthreads();
-        const T rn = T(1) / (T(2) * sig - rho);
-        const T c1 = rn * rho, c2 = T(2) * rn / de * iD;
-        col_sweep<T, NP, !isM, false>(b, px, r0, RX, RY, h, T(0), T(0), [&](int i, cx<T> Mu, cx<T> Ku, cx<T> Tu) {
-            const cx<T> q = isM ? Mu : cM * Mu + cK * Ku;
-            R[i] = R[i] - q;
+        const T c1 = T(cb[k][0]), c2 = T(cb[k][1]);
+        split_sweep<T, NP, false>(b, px, r0, RX, RY, [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB,
+                                                         cx<T> uC, cx<T>, cx<T>, cx<T>) {
+            // r -= OP d, as a chain of fused multiply-adds (the mass operator has no centre terms)
+            cx<T> q = R[i] - oa * (pA + pC) - ob * pB;
+            if constexpr (!isM) q = q - occ * (uA + uC) - od * uB;
+            R[i] = q;
             Dd[i] = c1 * Dd[i] + c2 * R[i];
             X[i] = X[i] + Dd[i];
         });
-        rho = rn;
     }
     // interior output (no wrap: each mesh node is written by exactly one tile)
     const int ix = px - halo;
@@ -1198,19 +1213,8 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
 // ------------------------------------------------------------------------------------------
 // Block preconditioner with Chebyshev-Jacobi inner solves, one launch per inner iteration (any
 // dimension; used in 3D, where a halo of several layers of a 27-point stencil does not fit LDS).
-// Same recurrence as k_cheb2d; the scalars rho_j follow from (theta, delta) of each system.
+// Same recurrence as k_cheb2d, with the scalars of iteration j from the system's table (Sys::cb).
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void cheb_coef(double th, double de, int j, double& c1, double& c2) {
-    // rho_0 = delta/theta, rho_j = 1/(2 theta/delta - rho_{j-1}); c1 = rho_j rho_{j-1}, c2 = 2 rho_j/delta
-    const double sig = th / de;
-    double rho = 1.0 / sig, rn = rho;
-    for (int i = 1; i <= j; ++i) {
-        rn = 1.0 / (2.0 * sig - rho);
-        if (i < j) rho = rn;
-    }
-    c1 = rn * rho;
-    c2 = 2.0 * rn / de;
-}
 
 // r0 of the inner solve (STAGE 0: beta1; 1: beta2 - kappa G x1; 2: M x2; 3: G src for the accurate
 // mass solve M zeta = G eta), d0 = r0/(theta D), x = d0
@@ -1220,7 +1224,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* 
     TILE_PROLOGUE();
     constexpr bool isM = STAGE == 0 || STAGE == 3;
     constexpr bool WG = STAGE == 1 || STAGE == 3;
-    const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
+    const T scale = T(sys[tile.sys].cb[isM ? 0 : 1][0][0]);
     FOR_ROWS(TY) {
         Nbr<DIM> n;
         make_nbr<DIM>(s, x, y, pz, n);
@@ -1252,9 +1256,7 @@ template <int DIM, int TY, typename T, int OP, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* tiles, const int* mask, int j,
                                                    const cx<T>* din, cx<T>* dout, cx<T>* r, cx<T>* xv) {
     TILE_PROLOGUE();
-    double c1d, c2d;
-    cheb_coef(OP == 0 ? s.thM : s.thL, OP == 0 ? s.deM : s.deL, j, c1d, c2d);
-    const T c1 = T(c1d), c2 = T(c2d / (OP == 0 ? s.diagM : s.diagL));
+    const T c1 = T(sys[tile.sys].cb[OP][j][0]), c2 = T(sys[tile.sys].cb[OP][j][1]);
     const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
     FOR_ROWS(TY) {
         Nbr<DIM> n;
@@ -1283,7 +1285,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile
     TILE_PROLOGUE();
     constexpr bool isM = STAGE == 3;
     constexpr bool WG = STAGE == 1 || STAGE == 3;
-    const T scale = T(1.0 / ((isM ? s.thM : s.thL) * (isM ? s.diagM : s.diagL)));
+    const T scale = T(sys[tile.sys].cb[isM ? 0 : 1][0][0]);
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
     const T k0 = T(s.kv[0]), k1 = T(s.kv[1]), k2 = T(s.kv[2]);
@@ -1317,9 +1319,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile
                                                      const cx<T>* x1 = nullptr, const cx<T>* x2 = nullptr,
                                                      cx<T>* zz = nullptr) {
     TILE_PROLOGUE();
-    double c1d, c2d;
-    cheb_coef(OP == 0 ? s.thM : s.thL, OP == 0 ? s.deM : s.deL, j, c1d, c2d);
-    const T c1 = T(c1d), c2 = T(c2d / (OP == 0 ? s.diagM : s.diagL));
+    const T c1 = T(sys[tile.sys].cb[OP][j][0]), c2 = T(sys[tile.sys].cb[OP][j][1]);
     const T cM = OP == 0 ? T(1) : T(s.isq_dt), cK = OP == 0 ? T(0) : T(s.sq_kap);
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
@@ -1351,10 +1351,8 @@ template <int TY, typename T, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Tile* tiles, const int* mask,
                                                       const zd* v, cx<T>* dout, cx<T>* r, cx<T>* xv) {
     TILE_PROLOGUE();
-    const T scale = T(1.0 / (s.thM * s.diagM));
-    double c1d, c2d;
-    cheb_coef(s.thM, s.deM, 1, c1d, c2d);
-    const T c1 = T(c1d), c2 = T(c2d / s.diagM);
+    const T scale = T(sys[tile.sys].cb[0][0][0]);
+    const T c1 = T(sys[tile.sys].cb[0][1][0]), c2 = T(sys[tile.sys].cb[0][1][1]);
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
     __shared__ cx<T> buf[2][1][kPP];
