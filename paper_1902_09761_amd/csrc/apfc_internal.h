@@ -144,6 +144,7 @@ void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_t
 void launch_extrapolate(const Dev& d, const zd* X, const zd* const* h, zd* X0, zd* keep, int order,
                         hipStream_t st);
 void launch_widen(const zf* in, zd* out, long long n, hipStream_t st);
+void launch_narrow(const zd* in, zf* out, long long n, hipStream_t st);
 
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st);
 void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st);
@@ -154,31 +155,35 @@ template <typename T>
 void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st);
 
 template <typename T>
-void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
+void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
-// vscale (may be null): v is used as vscale[sys] * v, and that scaled vector is also stored to vout
+// vscale (may be null): the input is vscale[sys] * rv (FP64) instead of v, and that scaled vector is also
+// stored to vout in precision T
 template <typename T>
-void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
-                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout,
-                         const int* mask, hipStream_t st);
+void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
+                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                         const zd* rv, cx<T>* vout, const int* mask, hipStream_t st);
 
 template <typename T>
-void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
+void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
                                  cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
 // second Gram-Schmidt pass on the systems flagged for it; the last workgroup of each such system also
 // reduces the pass (phase 2 of the Gram-Schmidt reduction)
-void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
+template <typename VT>
+void launch_mdot(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
                  double* part, const int* mask, const Krylov& kr, int k, hipStream_t st);
 template <typename T>
-void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const zd* V, long long vstride, int nv,
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
                       double* part, const int* mask, hipStream_t st);
-void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
-                       const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st);
-void launch_scale(const Dev& d, const zd* r, const double* inv_beta, zd* v0, const int* mask, hipStream_t st);
+template <typename VT>
+void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
+                       const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st);
+template <typename VT>
+void launch_scale(const Dev& d, const zd* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st);
 template <typename T>
 void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
                     zd* X, const int* mask, hipStream_t st);

@@ -724,13 +724,16 @@ double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
 
 // P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
 // Chebyshev (3D), or the paper's Jacobi-PCG.
+// With vscale set (fused 2D Chebyshev only), the input is vscale[sys] * rv instead of v and is also
+// stored to vout.
 template <typename T>
-void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, hipStream_t st,
-             const double* vscale = nullptr, zd* vout = nullptr) {
+void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mask, hipStream_t st,
+             const double* vscale = nullptr, const zd* rv = nullptr, cx<T>* vout = nullptr) {
     cx<T>** pc = (cx<T>**)c->pc;
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
-                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, vscale, vout, mask, st);
+                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, vscale, rv, vout, mask,
+                               st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB)
         launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
                                        c->solver.diff_iters, mask, st);
@@ -743,24 +746,38 @@ void precond(apfc_ctx* c, const Dev& d, const zd* v, cx<T>* z, const int* mask, 
 // the residual), so no separate scaling pass runs.
 bool scale_in_precond(const apfc_ctx* c) { return c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2; }
 
+// The Krylov basis V is stored in the preconditioner's precision T: FP32 in mixed precision (inner
+// products and projections still accumulate in FP64), FP64 otherwise.
+template <typename T>
+cx<T>* basis(apfc_ctx* c) { return (cx<T>*)c->V; }
+
+// v_0 = r / beta where the preconditioner does not form it
+void scale_start(apfc_ctx* c, const Dev& d, hipStream_t st) {
+    if (scale_in_precond(c)) return;
+    if (c->mixed)
+        launch_scale<zf>(d, c->R, c->kr.inv_beta, basis<float>(c), c->kr.iter_active, st);
+    else
+        launch_scale<zd>(d, c->R, c->kr.inv_beta, basis<double>(c), c->kr.iter_active, st);
+}
+
 template <typename T>
 void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     const Krylov& kr = c->kr;
     const long long vs = c->vstride();
     cx<T>* Z = (cx<T>*)c->Z;
-    cx<T>** pc = (cx<T>**)c->pc;
+    cx<T>* V = basis<T>(c);
     const int* act = kr.iter_active;
     if (k == 0 && scale_in_precond(c))   // v_0 = r / beta formed by the preconditioner's first stages
-        precond<T>(c, d, c->R, Z, act, st, kr.inv_beta, c->V);
+        precond<T>(c, d, nullptr, Z, act, st, kr.inv_beta, c->R, V);
     else
-        precond<T>(c, d, c->V + k * vs, Z + k * vs, act, st);
+        precond<T>(c, d, V + k * vs, Z + k * vs, act, st);
     const int nv = k + 1;
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
-    launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, c->V, vs, nv, c->apart, act, st);
+    launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, V, vs, nv, c->apart, act, st);
     // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
     launch_gs_reduce1(d, kr, k, c->apart, st);
-    launch_mdot(d, c->V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, kr, k, st);
-    launch_proj_final(d, c->V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), c->V + (k + 1) * vs, act, st);
+    launch_mdot<cx<T>>(d, V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, kr, k, st);
+    launch_proj_final<cx<T>>(d, V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
 }
 
 void run_iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
@@ -785,7 +802,7 @@ void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
     launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
     launch_cycle_init(d, kr, false, st);
-    if (!scale_in_precond(c)) launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    scale_start(c, d, st);
     launch_publish(d, kr, c->d_pub, st);
 }
 
@@ -820,7 +837,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
     launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, nullptr, st);
     launch_cycle_init(d, kr, true, st);
-    if (!scale_in_precond(c)) launch_scale(d, c->R, kr.inv_beta, c->V, kr.iter_active, st);
+    scale_start(c, d, st);
     int launched = 0;
     // Cycles before the last one of the previous solve are queued without a host round trip:
     // the iteration count changes slowly from step to step, and a cycle queued for systems that
@@ -1169,13 +1186,13 @@ int apfc_apply(apfc_ctx* c, int which, const apfc_state* lin, const apfc_state* 
         launch_apply<double>(d, c->W, c->dnode, c->R, nullptr, st);
         launch_state_out(d, c->R, tab(c, 2), tab(c, 3), st);
     } else {
-        launch_state_in(d, tab(c, 0), tab(c, 1), c->V, st);
-        const long long vs = c->vstride();
-        (void)vs;
         if (c->mixed) {
-            precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
+            launch_state_in(d, tab(c, 0), tab(c, 1), c->W, st);
+            launch_narrow(c->W, basis<float>(c), 2 * c->NT, st);
+            precond<float>(c, d, basis<float>(c), (zf*)c->Z, nullptr, st);
             launch_widen((const zf*)c->Z, c->R, 2 * c->NT, st);
         } else {
+            launch_state_in(d, tab(c, 0), tab(c, 1), c->V, st);
             precond<double>(c, d, c->V, c->R, nullptr, st);
         }
         launch_state_out(d, c->R, tab(c, 2), tab(c, 3), st);
@@ -1310,11 +1327,13 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
             d.probe = nullptr;
             auto body = [&]() {
                 if (c->mixed) {
-                    precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
-                    launch_apply_dot<float>(d, (const zf*)c->Z, c->dnode, c->W, c->V, vs, 2, c->apart, nullptr, st);
+                    precond<float>(c, d, basis<float>(c), (zf*)c->Z, nullptr, st);
+                    launch_apply_dot<float>(d, (const zf*)c->Z, c->dnode, c->W, basis<float>(c), vs, 2, c->apart,
+                                            nullptr, st);
                 } else {
                     precond<double>(c, d, c->V, (zd*)c->Z, nullptr, st);
-                    launch_apply_dot<double>(d, (const zd*)c->Z, c->dnode, c->W, c->V, vs, 2, c->apart, nullptr, st);
+                    launch_apply_dot<double>(d, (const zd*)c->Z, c->dnode, c->W, c->V, vs, 2, c->apart, nullptr,
+                                             st);
                 }
                 launch_reduce(d, c->apart, 0, 5, false, c->kr.red1, c->kr.nv1 + 1, nullptr, st);
                 launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
@@ -1351,7 +1370,7 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
                 d.probe = nullptr;
                 auto body = [&]() {
                     if (c->mixed)
-                        precond<float>(c, d, c->V, (zf*)c->Z, nullptr, st);
+                        precond<float>(c, d, basis<float>(c), (zf*)c->Z, nullptr, st);
                     else
                         precond<double>(c, d, c->V, (zd*)c->Z, nullptr, st);
                 };

@@ -734,7 +734,7 @@ __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LO
 // tiles (TY/4 rows per thread); 3D: k_apply_dot3d below.
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                       const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V,
                                                        long long vstride, int nv, double* part, long long NT,
                                                        int ntiles) {
     constexpr int RR = TY / 4;
@@ -754,7 +754,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
 #pragma unroll
         for (int l = 0; l < NV; ++l)
             if (l < nv) {
-                const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
+                const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
+                         q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                 acc[2 * l] += p.x + q.x;
                 acc[2 * l + 1] += p.y + q.y;
             }
@@ -806,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Til
 
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const zd* V,
+                                                       const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V,
                                                        long long vstride, int nv, double* part, long long NT,
                                                        int ntiles) {
     __shared__ double lds[4 * (2 * NV + 1)];
@@ -829,7 +830,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
 #pragma unroll
             for (int l = 0; l < NV; ++l)
                 if (l < nv) {
-                    const zd p = cdot(V[l * vstride + s.off + il], y1), q = cdot(V[l * vstride + NT + s.off + il], y2);
+                    const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
+                         q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                     acc[2 * l] += p.x + q.x;
                     acc[2 * l + 1] += p.y + q.y;
                 }
@@ -886,7 +888,7 @@ __device__ __forceinline__ double op_diag(const Sys& s) { return OP == 0 ? s.dia
 // step 1 init: r = beta1 (zeta part of v), p0 = r / D_M
 template <int DIM, int TY, typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_init_copy(const Sys* sys, const Tile* tiles, const int* mask,
-                                                        const zd* v, cx<T>* r, cx<T>* p0, double* part,
+                                                        const cx<T>* v, cx<T>* r, cx<T>* p0, double* part,
                                                         int ntiles) {
     __shared__ double lds[4];
     TILE_PROLOGUE();
@@ -906,7 +908,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_copy(const Sys* sys, const T
 // step 2 init: r = beta2 - kappa G x1 (x1 ~ M^{-1} beta1), p0 = r / D_L
 template <int DIM, int TY, typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_init_g(const Sys* sys, const Tile* tiles, const int* mask,
-                                                     const zd* v, const cx<T>* x1, cx<T>* r, cx<T>* p0,
+                                                     const cx<T>* v, const cx<T>* x1, cx<T>* r, cx<T>* p0,
                                                      double* part, int ntiles, long long NT) {
     __shared__ double lds[4];
     TILE_PROLOGUE();
@@ -1103,9 +1105,9 @@ __host__ __device__ inline SplitCoef split_coef(double h, double cM, double cK) 
 }
 
 template <typename T, int STAGE, int RX, int RY, int NTH>
-__global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const zd* v,
+__global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v,
                                                cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
-                                               long long NT, const double* vscale, zd* vout) {
+                                               long long NT, const double* vscale, const zd* rv, cx<T>* vout) {
     constexpr int RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
     // FP32: two region buffers used in turn, so each iteration needs one barrier (its writes go to the
@@ -1123,11 +1125,13 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
     auto gidx = [&](int i) { return s.off + (long long)wrapi(tile.y0 - halo + r0 + i, s.ny) * s.nx + gx; };
     auto lidx = [&](int i) { return (r0 + i) * RX + px; };
     cx<T> X[NP], R[NP], Dd[NP];
-    // v = vscale[sys] * (the vector given) when vscale is set: the first basis vector of a restart
-    // cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to vout)
+    // The input is v, or, when vscale is set, vscale[sys] * rv (FP64): the first basis vector of a
+    // restart cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it, in
+    // the basis precision T, to vout)
     const double vs = vscale ? vscale[tile.sys] : 1.0;
     auto ldv = [&](long long i) {
-        const zd u = v[i];
+        if (!vscale) return v[i];
+        const zd u = rv[i];
         return cx<T>{T(vs * u.x), T(vs * u.y)};
     };
     // right-hand side of the inner solve
@@ -1198,10 +1202,10 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
         const long long g = gidx(i);
         if constexpr (STAGE == 0) {
             x1[g] = X[i];
-            if (vscale) vout[g] = vs * v[g];
+            if (vscale) stv(vout, g, vs * rv[g]);
         } else if constexpr (STAGE == 1) {
             x2[g] = X[i];
-            if (vscale) vout[NT + g] = vs * v[NT + g];
+            if (vscale) stv(vout, NT + g, vs * rv[NT + g]);
         } else {
             const cx<T> chi2 = X[i];
             z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
@@ -1219,7 +1223,7 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
 // r0 of the inner solve (STAGE 0: beta1; 1: beta2 - kappa G x1; 2: M x2; 3: G src for the accurate
 // mass solve M zeta = G eta), d0 = r0/(theta D), x = d0
 template <int DIM, int TY, typename T, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* tiles, const int* mask, const zd* v,
+__global__ __launch_bounds__(kBlock) void k_cb_init(const Sys* sys, const Tile* tiles, const int* mask, const cx<T>* v,
                                                    const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
     TILE_PROLOGUE();
     constexpr bool isM = STAGE == 0 || STAGE == 3;
@@ -1279,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* 
 // 3D versions of k_cb_init (STAGE 1..3, the stages with a stencil) and k_cb_iter on z-marching
 // bricks; same arithmetic per node.
 template <int TY, typename T, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile* tiles, const int* mask, const zd* v,
+__global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile* tiles, const int* mask, const cx<T>* v,
                                                      const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
     static_assert(STAGE >= 1 && STAGE <= 3, "stage 0 has no stencil");
     TILE_PROLOGUE();
@@ -1349,7 +1353,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter3d(const Sys* sys, const Tile
 // d1 = c1 d0 + c2 D^{-1} r1, x1 = x0 + d1.  Same arithmetic as k_cb_init (stage 0) + k_cb_iter3d (j = 1).
 template <int TY, typename T, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                      const zd* v, cx<T>* dout, cx<T>* r, cx<T>* xv) {
+                                                      const cx<T>* v, cx<T>* dout, cx<T>* r, cx<T>* xv) {
     TILE_PROLOGUE();
     const T scale = T(sys[tile.sys].cb[0][0][0]);
     const T c1 = T(sys[tile.sys].cb[0][1][0]), c2 = T(sys[tile.sys].cb[0][1][1]);
@@ -1395,8 +1399,8 @@ __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long
 // Partials of V_i^H w' (i < nv) and |w'|^2 with w' = w - sum_l coef_l V_l (the second, re-
 // orthogonalising Gram-Schmidt pass).  Each thread walks its elements one at a time and keeps the
 // nv basis values of the element in registers, so V is read once.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const zd* V,
+template <int NV, typename VT>
+__global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const VT* V,
                                                 long long vstride, int nv, const zd* w, const double* coef,
                                                 int coef_ld, double* part, int nchunks, long long NT, Krylov kr,
                                                 int kit) {
@@ -1418,7 +1422,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
         const long long gi = elem_index(s, NT, e);
         zd vv[NV];
 #pragma unroll
-        for (int l = 0; l < NV; ++l) vv[l] = l < nv ? V[l * vstride + gi] : zd{0.0, 0.0};
+        for (int l = 0; l < NV; ++l) vv[l] = l < nv ? ld<double>(V, l * vstride + gi) : zd{0.0, 0.0};
         zd wv = w[gi];
 #pragma unroll
         for (int l = 0; l < NV; ++l) wv = wv - cmul(cf[l], vv[l]);
@@ -1442,10 +1446,11 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
     if (last_of_system(kr.tick_c, ch.sys, s.cend - s.cbeg, &flag)) gs_reduce_sys<2>(sys, kr, kit, part, nchunks, ch.sys);
 }
 
-// out = (w - sum_l hcoef_l V_l) * hinv
+// out = (w - sum_l hcoef_l V_l) * hinv, formed in FP64 and stored in the basis precision
+template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chunk* chunks, const int* mask,
-                                                      const zd* V, long long vstride, int nv, const zd* w,
-                                                      const double* hcoef, int hld, const double* hinv, zd* out,
+                                                      const VT* V, long long vstride, int nv, const zd* w,
+                                                      const double* hcoef, int hld, const double* hinv, VT* out,
                                                       long long NT) {
     __shared__ zd cf[kMaxRestart + 1];
     CHUNK_PROLOGUE();
@@ -1456,18 +1461,19 @@ __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chu
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
         zd wv = w[gi];
-        for (int l = 0; l < nv; ++l) wv = wv - cmul(cf[l], V[l * vstride + gi]);
-        out[gi] = sc * wv;
+        for (int l = 0; l < nv; ++l) wv = wv - cmul(cf[l], ld<double>(V, l * vstride + gi));
+        stv(out, gi, sc * wv);
     }
 }
 
+template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_scale(const Sys* sys, const Chunk* chunks, const int* mask, const zd* r,
-                                                 const double* inv_beta, zd* v0, long long NT) {
+                                                 const double* inv_beta, VT* v0, long long NT) {
     CHUNK_PROLOGUE();
     const double sc = inv_beta[ch.sys];
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
-        v0[gi] = sc * r[gi];
+        stv(v0, gi, sc * r[gi]);
     }
 }
 
@@ -2061,6 +2067,10 @@ __global__ __launch_bounds__(kBlock) void k_widen(const zf* in, zd* out, long lo
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
         out[i] = zd{(double)in[i].x, (double)in[i].y};
 }
+__global__ __launch_bounds__(kBlock) void k_narrow(const zd* in, zf* out, long long n) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = zf{(float)in[i].x, (float)in[i].y};
+}
 // Initial guess from the kept states h_1 (newest) .. h_K: the polynomial through x and the last
 // `order` kept states, evaluated one step ahead (order 0: x; 1: 2x - h1; 2: 3x - 3h1 + h2;
 // 3: 4x - 6h1 + 4h2 - h3), written to X0.  With keep != null the state x is also copied there (the
@@ -2097,6 +2107,12 @@ void launch_widen(const zf* in, zd* out, long long n, hipStream_t st) {
     long long blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks), dim3(kBlock), 0, st, in, out, n);
+}
+void launch_narrow(const zd* in, zf* out, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)blocks), dim3(kBlock), 0, st, in, out, n);
 }
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
@@ -2187,7 +2203,7 @@ static void cg_iterations(const Dev& d, cx<T>* xv, cx<T>* r, cx<T>* p0, cx<T>* p
 }
 
 template <typename T>
-void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
+void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
@@ -2219,49 +2235,50 @@ void launch_precond(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, c
 }
 template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, zd*, double*, int, int,
                                      const int*, hipStream_t);
-template void launch_precond<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
+template void launch_precond<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
                                     const int*, hipStream_t);
 
 template <typename T, int RX, int RY, int NTH>
-static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z, cx<T>* x1,
-                        cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout, const int* mask,
-                        hipStream_t st) {
+static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
+                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, const zd* rv,
+                        cx<T>* vout, const int* mask, hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
-    const double pts = (double)d.NT, vb = vscale ? (double)sizeof(zd) : 0.0;
+    // input half read (FP64 residual or basis vector) and, with vscale, the basis vector written
+    const double pts = (double)d.NT, vin = vscale ? (double)sizeof(zd) : (double)sizeof(cx<T>),
+                 vb = vscale ? (double)sizeof(cx<T>) : 0.0;
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + sizeof(cx<T>) + vb));
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb));
         hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT, vscale, vout);
+                           diff_iters, halo, d.NT, vscale, rv, vout);
     }
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (sizeof(zd) + 2 * sizeof(cx<T>) + vb));
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb));
         hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT, vscale, vout);
+                           diff_iters, halo, d.NT, vscale, rv, vout);
     }
     ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>));
     hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                       diff_iters, halo, d.NT, nullptr, nullptr);
+                       diff_iters, halo, d.NT, nullptr, nullptr, nullptr);
 }
 
 template <typename T>
-void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const zd* v, cx<T>* z,
-                         cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, zd* vout,
-                         const int* mask, hipStream_t st) {
+void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
+                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                         const zd* rv, cx<T>* vout, const int* mask, hipStream_t st) {
     switch (shape) {
-        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
-        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
-        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, vout, mask, st); break;
+        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
+        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
+        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
     }
 }
 template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
-                                          const double*, zd*, const int*, hipStream_t);
-template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zd*, zf*, zf*, zf*, int, int,
-                                         const double*, zd*,
-                                         const int*, hipStream_t);
+                                          const double*, const zd*, zd*, const int*, hipStream_t);
+template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
+                                         const double*, const zd*, zf*, const int*, hipStream_t);
 
 // stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D
 template <int DIM, int TY, typename T, int STAGE>
-static void cb_init_launch(const Dev& d, const int* mask, const zd* v, const cx<T>* src, cx<T>* r, cx<T>* dd,
+static void cb_init_launch(const Dev& d, const int* mask, const cx<T>* v, const cx<T>* src, cx<T>* r, cx<T>* dd,
                            cx<T>* xv, hipStream_t st) {
     if constexpr (DIM == 3 && STAGE != 0)
         hipLaunchKernelGGL((k_cb_init3d<TY, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv, d.NT);
@@ -2315,7 +2332,7 @@ static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1,
 }
 
 template <typename T>
-void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
+void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
                                  cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
@@ -2370,7 +2387,7 @@ void launch_precond_cheb_unfused(const Dev& d, const zd* v, cx<T>* z, cx<T>* x1,
 }
 template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, int, int,
                                                   const int*, hipStream_t);
-template void launch_precond_cheb_unfused<float>(const Dev&, const zd*, zf*, zf*, zf*, zf*, zf*, zf*, int, int,
+template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, int, int,
                                                  const int*, hipStream_t);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
@@ -2396,12 +2413,13 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
                        out, ld);
 }
 
-void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
+template <typename VT>
+void launch_mdot(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
                  double* part, const int* mask, const Krylov& kr, int k, hipStream_t st) {
-    // reads w and nv basis vectors (full vectors of 2 NT complex doubles)
-    ProbeScope ps(d, KID_MDOT, st, (double)(nv + 1) * 2.0 * d.NT * sizeof(zd));
+    // reads w and nv basis vectors (full vectors of 2 NT complex values)
+    ProbeScope ps(d, KID_MDOT, st, 2.0 * d.NT * (sizeof(zd) + nv * sizeof(VT)));
     auto go = [&](auto nvc) {
-        hipLaunchKernelGGL((k_mdot<decltype(nvc)::value>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
+        hipLaunchKernelGGL((k_mdot<decltype(nvc)::value, VT>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
                            coef, coef_ld, part, d.nchunks, d.NT, kr, k);
     };
     if (nv <= 4) go(std::integral_constant<int, 4>{});
@@ -2409,13 +2427,17 @@ void launch_mdot(const Dev& d, const zd* V, long long vstride, int nv, const zd*
     else if (nv <= 16) go(std::integral_constant<int, 16>{});
     else go(std::integral_constant<int, 32>{});
 }
+template void launch_mdot<zd>(const Dev&, const zd*, long long, int, const zd*, const double*, int, double*,
+                              const int*, const Krylov&, int, hipStream_t);
+template void launch_mdot<zf>(const Dev&, const zf*, long long, int, const zd*, const double*, int, double*,
+                              const int*, const Krylov&, int, hipStream_t);
 
 template <typename T>
-void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const zd* V, long long vstride, int nv,
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
                       double* part, const int* mask, hipStream_t st) {
-    // reads z, d, nv basis vectors; writes w
+    // reads z, d, nv basis vectors (stored like z); writes w
     ProbeScope ps(d, KID_APPLY, st,
-                  (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) * (1 + nv) + 8.0 / d.J));
+                  (double)d.NT * (2.0 * sizeof(cx<T>) * (1 + nv) + 2.0 * sizeof(zd) + 8.0 / d.J));
     dispatch(d, [&](auto D, auto TY) {
         auto go = [&](auto nvc) {
             if constexpr (D() == 2)
@@ -2433,7 +2455,7 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
 }
 template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*, const zd*, long long, int, double*,
                                        const int*, hipStream_t);
-template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zd*, long long, int, double*,
+template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zf*, long long, int, double*,
                                       const int*, hipStream_t);
 
 void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st) {
@@ -2441,15 +2463,23 @@ void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part
     hipLaunchKernelGGL(k_gs_reduce1, dim3(d.S), dim3(kRedBlock), 0, st, d.sys, kr, k, part, (long long)d.ntiles);
 }
 
-void launch_proj_final(const Dev& d, const zd* V, long long vstride, int nv, const zd* w, const double* hcoef,
-                       const double* hinv, int hstride, zd* out, const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_PROJ_FINAL, st, (double)(nv + 2) * 2.0 * d.NT * sizeof(zd));
-    hipLaunchKernelGGL(k_proj_final, CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, hcoef, hstride, hinv, out,
+template <typename VT>
+void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
+                       const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st) {
+    ProbeScope ps(d, KID_PROJ_FINAL, st, 2.0 * d.NT * (sizeof(zd) + (nv + 1) * sizeof(VT)));
+    hipLaunchKernelGGL(k_proj_final<VT>, CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, hcoef, hstride, hinv, out,
                        d.NT);
 }
-void launch_scale(const Dev& d, const zd* r, const double* inv_beta, zd* v0, const int* mask, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale, CHUNK_GRID, d.sys, d.chunks, mask, r, inv_beta, v0, d.NT);
+template <typename VT>
+void launch_scale(const Dev& d, const zd* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale<VT>, CHUNK_GRID, d.sys, d.chunks, mask, r, inv_beta, v0, d.NT);
 }
+template void launch_proj_final<zd>(const Dev&, const zd*, long long, int, const zd*, const double*, const double*,
+                                    int, zd*, const int*, hipStream_t);
+template void launch_proj_final<zf>(const Dev&, const zf*, long long, int, const zd*, const double*, const double*,
+                                    int, zf*, const int*, hipStream_t);
+template void launch_scale<zd>(const Dev&, const zd*, const double*, zd*, const int*, hipStream_t);
+template void launch_scale<zf>(const Dev&, const zd*, const double*, zf*, const int*, hipStream_t);
 template <typename T>
 void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
                     zd* X, const int* mask, hipStream_t st) {
