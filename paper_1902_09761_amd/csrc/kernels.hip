@@ -679,8 +679,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* ti
 // stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept for the next
 // two rows, so each input row is loaded once per field (3 loads instead of 9).  load(f, i) returns node i
 // of the system's zeta (f = 0) or eta (f = 1) part of u; emit(il, y1, y2) receives A_j u at node
-// il = (x, y) for y = y0 .. y0+RR-1 inside the mesh.
-template <int RR, typename LOAD, typename EMIT>
+// il = (x, y) for y = y0 .. y0+RR-1 inside the mesh.  CHECK = false: the caller knows that every row and
+// column of the march lies inside the mesh, so the march has no branch and the compiler can issue the
+// loads of later rows while earlier rows are computed.
+template <int RR, bool CHECK, typename LOAD, typename EMIT>
 __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LOAD& load, const double* dnode,
                                            const EMIT& emit) {
     const int xc = x < s.nx ? x : s.nx - 1;                  // clamp for loads of ragged tiles
@@ -708,7 +710,7 @@ __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LO
         }
         if (a >= 2) {
             const int y = y0 + a - 2;
-            if (x < s.nx && y < s.ny) {
+            if (!CHECK || (x < s.nx && y < s.ny)) {
                 auto Msum = [&](const zd* u) { return m0 * (u[0] + u[2]) + m1 * u[1]; };
                 const zd Mz = Msum(mz), Me = Msum(me);
                 const zd Kz = Msum(kz) + ih * ((mz[1] + mz[1]) - (mz[0] + mz[2]));
@@ -732,9 +734,11 @@ __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LO
 // W = A Z at every node and, fused, the first Gram-Schmidt pass: per-tile partials of V_i^H w
 // (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).  2D: column-marching
 // tiles (TY/4 rows per thread); 3D: k_apply_dot3d below.
+// NV >= nv basis vectors; with NV <= 4 the launch uses NV = nv exactly, so the basis loads carry no test.
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V,
+                                                       const cx<T>* __restrict__ Z, const double* __restrict__ dnode,
+                                                       zd* __restrict__ W, const cx<T>* __restrict__ V,
                                                        long long vstride, int nv, double* part, long long NT,
                                                        int ntiles) {
     constexpr int RR = TY / 4;
@@ -747,19 +751,23 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
     const cx<T>* zz = Z + s.off;
     const cx<T>* ze = Z + NT + s.off;
     auto load = [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); };
-    colmarch_A<RR>(s, x, y0, load, dnode, [&](long long il, const zd& y1, const zd& y2) {
+    auto emit = [&](long long il, const zd& y1, const zd& y2) {
         W[s.off + il] = y1;
         W[NT + s.off + il] = y2;
         acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
         for (int l = 0; l < NV; ++l)
-            if (l < nv) {
+            if (NV <= 4 || l < nv) {
                 const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
                          q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                 acc[2 * l] += p.x + q.x;
                 acc[2 * l + 1] += p.y + q.y;
             }
-    });
+    };
+    if (tile.x0 + 64 <= s.nx && y0 + RR <= s.ny)
+        colmarch_A<RR, false>(s, x, y0, load, dnode, emit);
+    else
+        colmarch_A<RR, true>(s, x, y0, load, dnode, emit);
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
         for (int l = 0; l < nv; ++l) {
@@ -772,9 +780,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
 
 // R = B - A X and per-tile partials of |R|^2, |B|^2 (slots kRR, kBB), on column-marching tiles.
 template <int TY>
-__global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
-                                                      const zd* B, const double* dnode, zd* R, double* part,
-                                                      long long NT, int ntiles) {
+__global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                      const zd* __restrict__ X, const zd* __restrict__ B,
+                                                      const double* __restrict__ dnode, zd* __restrict__ R,
+                                                      double* part, long long NT, int ntiles) {
     constexpr int RR = TY / 4;
     __shared__ double lds[8];
     TILE_PROLOGUE();
@@ -783,14 +792,18 @@ __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Til
     const zd* xz = X + s.off;
     const zd* xe = X + NT + s.off;
     auto load = [&](int f, long long i) { return (f == 0 ? xz : xe)[i]; };
-    colmarch_A<RR>(s, x, y0, load, dnode, [&](long long il, const zd& y1, const zd& y2) {
+    auto emit = [&](long long il, const zd& y1, const zd& y2) {
         const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
         const zd r1 = b1 - y1, r2 = b2 - y2;
         R[s.off + il] = r1;
         R[NT + s.off + il] = r2;
         acc[0] += abs2(r1) + abs2(r2);
         acc[1] += abs2(b1) + abs2(b2);
-    });
+    };
+    if (tile.x0 + 64 <= s.nx && y0 + RR <= s.ny)
+        colmarch_A<RR, false>(s, x, y0, load, dnode, emit);
+    else
+        colmarch_A<RR, true>(s, x, y0, load, dnode, emit);
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {
         part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
@@ -829,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
             acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
             for (int l = 0; l < NV; ++l)
-                if (l < nv) {
+                if (NV <= 4 || l < nv) {
                     const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
                          q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                     acc[2 * l] += p.x + q.x;
@@ -2447,7 +2460,10 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
                 hipLaunchKernelGGL((k_apply_dot3d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
                                    dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
         };
-        if (nv <= 4) go(std::integral_constant<int, 4>{});
+        if (nv == 1) go(std::integral_constant<int, 1>{});
+        else if (nv == 2) go(std::integral_constant<int, 2>{});
+        else if (nv == 3) go(std::integral_constant<int, 3>{});
+        else if (nv == 4) go(std::integral_constant<int, 4>{});
         else if (nv <= 8) go(std::integral_constant<int, 8>{});
         else if (nv <= 16) go(std::integral_constant<int, 16>{});
         else go(std::integral_constant<int, 32>{});
