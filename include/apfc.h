@@ -233,8 +233,9 @@ int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* byte
 int apfc_autotune(apfc_ctx* ctx, void* stream, int* chosen_tile_rows);
 
 /* Set the tiling by hand instead of apfc_autotune: tile_rows in {4, 8, 16, 32} (rows of the 64-wide
- * stencil tiles) and precond_region in {0, 1, 2} (LDS region of the fused 2D Chebyshev
- * preconditioner: 128x32 nodes / 512 threads, 64x32 / 256, 64x64 / 512).  Needs the workspace. */
+ * stencil tiles) and precond_region in 0..4 (LDS region of the fused 2D Chebyshev preconditioner:
+ * 128x32 nodes / 512 threads, 64x32 / 256, 64x64 / 512, 128x36 / 512, 128x40 / 512; the taller regions
+ * give fewer tiles, which can fill the chip in fewer rounds).  Needs the workspace. */
 int apfc_set_tiles(apfc_ctx* ctx, int tile_rows, int precond_region);
 int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
 

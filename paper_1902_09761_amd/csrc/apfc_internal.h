@@ -51,8 +51,9 @@ struct Tile { int sys, x0, y0, z; };
 // Interior tile of the fused Chebyshev preconditioner kernels (region = interior + halo).
 struct CTile { int sys, x0, y0, z; };
 // LDS region shapes (width, height, threads) of the fused preconditioner kernels.
-constexpr int kChebShapes = 3;
-constexpr int kChebShape[kChebShapes][3] = {{128, 32, 512}, {64, 32, 256}, {64, 64, 512}};
+constexpr int kChebShapes = 5;
+constexpr int kChebShape[kChebShapes][3] = {{128, 32, 512}, {64, 32, 256}, {64, 64, 512}, {128, 36, 512},
+                                            {128, 40, 512}};
 struct Chunk { int sys; int e0; };     // element offset inside the system's 2N-element full vector
 
 // Resonant products of the bulk energy with distinct amplitude indices: term value

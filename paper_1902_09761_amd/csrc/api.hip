@@ -1244,7 +1244,7 @@ int apfc_set_tiles(apfc_ctx* c, int tile_rows, int precond_region) {
     if (int rc = need_ws(c); rc) return rc;
     if (tile_rows != 4 && tile_rows != 8 && tile_rows != 16 && tile_rows != 32)
         return fail(APFC_ERR_INVALID, "tile_rows must be 4, 8, 16 or 32");
-    if (precond_region < 0 || precond_region >= kChebShapes) return fail(APFC_ERR_INVALID, "precond_region must be 0, 1 or 2");
+    if (precond_region < 0 || precond_region >= kChebShapes) return fail(APFC_ERR_INVALID, "precond_region must be in 0..4");
     c->TY = tile_rows;
     build_tiles(*c, c->TY, c->tiles);
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2) {

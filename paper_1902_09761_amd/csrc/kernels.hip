@@ -2281,6 +2281,8 @@ void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctil
     switch (shape) {
         case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
         case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
+        case 3: cheb_stages<T, 128, 36, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
+        case 4: cheb_stages<T, 128, 40, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
         default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
     }
 }

@@ -247,7 +247,8 @@ def test_operator_A_matches_oracle():
                                                  (apfc.APFC_INNER_PCG, apfc.APFC_MIXED, 2e-5),
                                                  (apfc.APFC_INNER_CHEB, apfc.APFC_FP64, 1e-12),
                                                  (apfc.APFC_INNER_CHEB, apfc.APFC_MIXED, 2e-5)])
-@pytest.mark.parametrize("n,tiles", [((40, 28), (16, 0)), ((256, 192), (8, 1)), ((256, 192), (32, 2)), ((96, 80), (4, 1))])
+@pytest.mark.parametrize("n,tiles", [((40, 28), (16, 0)), ((256, 192), (8, 1)), ((256, 192), (32, 2)), ((96, 80), (4, 1)),
+                                     ((256, 192), (16, 3)), ((96, 80), (8, 4))])
 def test_preconditioner_matches_oracle(inner, precision, tol, n, tiles):
     """P^{-1} by its four steps on the GPU vs the oracle's four steps with the same inner solver
     (Jacobi-PCG 3/5 or Chebyshev 4/4), element by element."""
