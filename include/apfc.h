@@ -224,7 +224,9 @@ int apfc_rotation(apfc_ctx* ctx, const apfc_state* states, double* const* omega,
  * `name` inside apfc_step is bracketed by HIP events on the launch stream (an event pair adds
  * a few microseconds of stream idle, hence the sampling); apfc_probe_read returns the number of
  * recorded launches, their summed duration and their mean algorithmic bytes since the last
- * reset.  name = NULL disables the probe. */
+ * reset, each launch's bytes counting only the systems it worked on (converged systems of a
+ * batch are skipped and move nothing); launches in which every system was masked (a cycle queued
+ * past convergence) are left out of all three.  name = NULL disables the probe. */
 int apfc_probe_enable(apfc_ctx* ctx, const char* name, int every);
 int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* bytes_per_launch);
 

@@ -83,9 +83,10 @@ struct Probe {
     int n = 0;
     int every = 1;            // record every `every`-th launch of the target
     long long seen = 0;       // launches of the target since the probe was enabled
-    double bytes = 0.0;       // algorithmic HBM bytes of the recorded launches
     static constexpr int kMax = 8192;
     hipEvent_t ev[2 * kMax];
+    double bytes[kMax];         // algorithmic HBM bytes of recorded launch i with every system active
+    double* d_frac = nullptr;   // device [kMax]: share of the nodes whose systems launch i worked on
     bool created = false;
 };
 

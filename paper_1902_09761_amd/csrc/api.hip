@@ -674,8 +674,10 @@ int apfc_destroy(apfc_ctx* c) {
     if (!c) return APFC_OK;
     invalidate_graphs(*c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->probe.created)
+    if (c->probe.created) {
         for (auto& e : c->probe.ev) (void)hipEventDestroy(e);
+        (void)hipFree(c->probe.d_frac);
+    }
     if (c->h_tab) (void)hipHostFree(c->h_tab);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     if (c->h_pub) (void)hipHostFree(c->h_pub);
@@ -825,6 +827,16 @@ int capture_graphs(apfc_ctx* c) {
     return APFC_OK;
 }
 
+// Host wait for the end of a restart cycle.  The convergence check sits on the critical path of every
+// time step, and a blocking wait adds the wake-up latency of the waiting thread (tens of microseconds)
+// to each step, so the host polls the stream instead.
+hipError_t poll_sync(hipStream_t st) {
+    for (;;) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
 // Restarted FGMRES on every system: B and the initial guess X must be set, dnode current.
 int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     Dev d = c->dev();
@@ -850,7 +862,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
             run_cycle(c, d, st);
         launched += c->m;
         if (cyc + 1 < hint) continue;
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(poll_sync(st));
         // k_publish wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
         const volatile int* pub = c->h_pub;
         if (pub[1]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
@@ -1275,30 +1287,36 @@ int apfc_probe_enable(apfc_ctx* c, const char* name, int every) {
     if (name && kid == KID_NONE) return fail(APFC_ERR_INVALID, std::string("unknown kernel name: ") + name);
     if (!c->probe.created && kid != KID_NONE) {
         for (auto& e : c->probe.ev) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipMalloc(&c->probe.d_frac, sizeof(double) * Probe::kMax));
         c->probe.created = true;
     }
     c->probe.target = kid;
     c->probe.every = every;
     c->probe.seen = 0;
     c->probe.n = 0;
-    c->probe.bytes = 0.0;
     return APFC_OK;
 }
 
 int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_per_launch) {
     if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
-    double tot = 0.0;
-    for (int i = 0; i < c->probe.n; ++i) {
+    double tot = 0.0, bytes = 0.0;
+    const int n = c->probe.n;
+    int used = 0;
+    std::vector<double> frac(n);
+    if (n > 0) HIPCHK(hipMemcpy(frac.data(), c->probe.d_frac, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
         HIPCHK(hipEventSynchronize(c->probe.ev[2 * i + 1]));
+        if (frac[i] <= 0.0) continue;   // every system masked: an empty launch, not a sample of the kernel
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->probe.ev[2 * i], c->probe.ev[2 * i + 1]));
         tot += ms;
+        bytes += c->probe.bytes[i] * frac[i];
+        ++used;
     }
-    if (launches) *launches = c->probe.n;
+    if (launches) *launches = used;
     if (total_ms) *total_ms = tot;
-    if (bytes_per_launch) *bytes_per_launch = c->probe.n > 0 ? c->probe.bytes / c->probe.n : 0.0;
+    if (bytes_per_launch) *bytes_per_launch = used > 0 ? bytes / used : 0.0;
     c->probe.n = 0;
-    c->probe.bytes = 0.0;
     return APFC_OK;
 }
 

@@ -11,6 +11,7 @@
 // per workgroup, summed in a fixed order.
 #include "apfc_internal.h"
 
+#include <hip/hip_ext.h>
 #include <type_traits>
 #include <utility>
 
@@ -1471,6 +1472,26 @@ __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chu
         cf[l] = zd{hcoef[ch.sys * hld + 2 * l], hcoef[ch.sys * hld + 2 * l + 1]};
     __syncthreads();
     const double sc = hinv[ch.sys];
+    constexpr int EPT = kChunk / kBlock;
+    if (ch.e0 + kChunk <= twoN) {
+        // full chunk: basis vector by basis vector over the thread's EPT elements, so EPT loads are in
+        // flight at a time instead of one
+        long long gi[EPT];
+        zd wv[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            gi[u] = elem_index(s, NT, (long long)ch.e0 + threadIdx.x + (long long)u * kBlock);
+            wv[u] = w[gi[u]];
+        }
+        for (int l = 0; l < nv; ++l) {
+            const zd c = cf[l];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) wv[u] = wv[u] - cmul(c, ld<double>(V, l * vstride + gi[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) stv(out, gi[u], sc * wv[u]);
+        return;
+    }
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
         zd wv = w[gi];
@@ -1500,6 +1521,25 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const Sys* sys, const Chunk*
     if (kc <= 0) return;
     for (int l = threadIdx.x; l < kc; l += kBlock) cf[l] = zd{y[ch.sys * ldy + 2 * l], y[ch.sys * ldy + 2 * l + 1]};
     __syncthreads();
+    constexpr int EPT = kChunk / kBlock;
+    if (ch.e0 + kChunk <= twoN) {
+        // full chunk: EPT loads in flight per basis vector (as in k_proj_final)
+        long long gi[EPT];
+        zd xv[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            gi[u] = elem_index(s, NT, (long long)ch.e0 + threadIdx.x + (long long)u * kBlock);
+            xv[u] = X[gi[u]];
+        }
+        for (int l = 0; l < kc; ++l) {
+            const zd c = cf[l];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) xv[u] = xv[u] + cmul(c, ld<double>(Z, l * zstride + gi[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) X[gi[u]] = xv[u];
+        return;
+    }
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
         zd xv = X[gi];
@@ -2010,20 +2050,50 @@ int kernel_id(const char* name) {
     return KID_NONE;
 }
 
+// Share of the batch's nodes that belong to the systems a masked launch works on (1 without a mask):
+// converged systems are skipped by the kernels and move no bytes.
+__global__ __launch_bounds__(kBlock) void k_active_frac(const Sys* sys, int S, const int* mask, double* out) {
+    __shared__ double lds[2 * (kBlock / 64)];
+    double acc[2] = {0.0, 0.0};
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+        const double n = (double)sys[s].N;
+        acc[0] += (!mask || mask[s]) ? n : 0.0;
+        acc[1] += n;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) *out = acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
+}
+
+// HIP events around a sampled launch of the probed kernel; after the closing event (outside the timed
+// window) k_active_frac records which share of the batch the launch worked on.  A launcher that starts
+// its kernel through launch() with ext = true has the two events stamped by the kernel's own dispatch
+// (hipExtLaunchKernel), so no event sits between them and the kernel.
 struct ProbeScope {
     Probe* p;
     hipStream_t st;
-    bool on;
-    ProbeScope(const Dev& d, int kid, hipStream_t s, double bytes = 0.0) : p(d.probe), st(s) {
+    const Sys* sys;
+    int S;
+    const int* mask;
+    bool on, ext;
+    ProbeScope(const Dev& d, int kid, hipStream_t s, double bytes = 0.0, const int* m = nullptr, bool e = false)
+        : p(d.probe), st(s), sys(d.sys), S(d.S), mask(m), ext(e) {
         on = p && p->target == kid && (p->seen++ % p->every) == 0 && p->n < Probe::kMax;
         if (on) {
-            (void)hipEventRecord(p->ev[2 * p->n], st);
-            p->bytes += bytes;
+            if (!ext) (void)hipEventRecord(p->ev[2 * p->n], st);
+            p->bytes[p->n] = bytes;
         }
+    }
+    template <typename K, typename... A>
+    void launch(K kernel, dim3 grid, dim3 block, A... args) {
+        if (on && ext)
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, st, p->ev[2 * p->n], p->ev[2 * p->n + 1], 0, args...);
+        else
+            hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
     }
     ~ProbeScope() {
         if (on) {
-            (void)hipEventRecord(p->ev[2 * p->n + 1], st);
+            if (!ext) (void)hipEventRecord(p->ev[2 * p->n + 1], st);
+            hipLaunchKernelGGL(k_active_frac, dim3(1), dim3(kBlock), 0, st, sys, S, mask, p->d_frac + p->n);
             p->n += 1;
         }
     }
@@ -2090,18 +2160,15 @@ __global__ __launch_bounds__(kBlock) void k_narrow(const zd* in, zf* out, long l
 // oldest kept state's buffer, possibly h_order itself: each element is read before it is written); the
 // guess may then overwrite X in place.  With keep = null, X0 is a buffer of its own and X is only read
 // (the caller keeps X's buffer as the newest state).
+template <int ORDER>
 __global__ __launch_bounds__(kBlock) void k_extrapolate(const zd* X, const zd* h1, const zd* h2, const zd* h3,
-                                                       zd* X0, zd* keep, long long n, int order) {
+                                                       zd* X0, zd* keep, long long n) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
         const zd x = X[i];
         zd g = x;
-        if (order == 1) {
-            g = x + (x - h1[i]);
-        } else if (order == 2) {
-            g = h2[i] + 3.0 * (x - h1[i]);
-        } else if (order == 3) {
-            g = 4.0 * (x + h2[i]) - (6.0 * h1[i] + h3[i]);
-        }
+        if constexpr (ORDER == 1) g = x + (x - h1[i]);
+        else if constexpr (ORDER == 2) g = h2[i] + 3.0 * (x - h1[i]);
+        else if constexpr (ORDER == 3) g = 4.0 * (x + h2[i]) - (6.0 * h1[i] + h3[i]);
         if (keep) keep[i] = x;
         X0[i] = g;
     }
@@ -2111,8 +2178,16 @@ void launch_extrapolate(const Dev& d, const zd* X, const zd* const* h, zd* X0, z
     const long long n = 2 * d.NT;
     long long blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h[0], h[1], h[2], X0, keep, n,
-                       order);
+    auto go = [&](auto oc) {
+        hipLaunchKernelGGL((k_extrapolate<decltype(oc)::value>), dim3((unsigned)blocks), dim3(kBlock), 0, st, X, h[0],
+                           h[1], h[2], X0, keep, n);
+    };
+    switch (order) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        default: go(std::integral_constant<int, 0>{}); break;
+    }
 }
 
 void launch_widen(const zf* in, zd* out, long long n, hipStream_t st) {
@@ -2171,7 +2246,7 @@ void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode
 template <typename T>
 void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st) {
     // reads z (2 half vectors) and d (per instance), writes w (2 FP64 half vectors)
-    ProbeScope ps(d, KID_APPLY, st, (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) + 8.0 / d.J));
+    ProbeScope ps(d, KID_APPLY, st, (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) + 8.0 / d.J), mask);
     dispatch(d, [&](auto D, auto TY) {
         hipLaunchKernelGGL((k_apply<D(), TY(), T>), TILE_GRID, d.sys, d.tiles, mask, Z, dnode, W, d.NT);
     });
@@ -2260,16 +2335,16 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
     const double pts = (double)d.NT, vin = vscale ? (double)sizeof(zd) : (double)sizeof(cx<T>),
                  vb = vscale ? (double)sizeof(cx<T>) : 0.0;
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb));
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
         hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                            diff_iters, halo, d.NT, vscale, rv, vout);
     }
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb));
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb), mask);
         hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                            diff_iters, halo, d.NT, vscale, rv, vout);
     }
-    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>));
+    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask);
     hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
                        diff_iters, halo, d.NT, nullptr, nullptr, nullptr);
 }
@@ -2306,7 +2381,7 @@ static void cb_iterations(const Dev& d, int its, cx<T>* d0, cx<T>* d1, cx<T>* r,
                           hipStream_t st) {
     cx<T>* D[2] = {d0, d1};
     for (int j = 1; j < its; ++j) {
-        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (j == its - 1 ? 3.0 : 6.0));
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (j == its - 1 ? 3.0 : 6.0), mask);
         if constexpr (DIM == 3) {
             if (j == its - 1)
                 hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, true>), TILE_GRID, d.sys, d.tiles, mask, j,
@@ -2333,7 +2408,7 @@ static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1,
     cx<T>* D[2] = {d0, d1};
     for (int j = j0; j < its; ++j) {
         const bool last = j == its - 1;
-        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (last ? (x1 ? 6.0 : 3.0) : 6.0));
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * (last ? (x1 ? 6.0 : 3.0) : 6.0), mask);
         if (last && x1)
             hipLaunchKernelGGL((k_cb_iter3d<TYv, T, OP, true, true>), TILE_GRID, d.sys, d.tiles, mask, j,
                                D[(j - 1) & 1], D[j & 1], r, xv, x1, x2, zz);
@@ -2354,7 +2429,7 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
         if constexpr (DIM == 3) {
             // step 1: initialisation fused with the first iteration
             if (mass_iters >= 2) {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + (mass_iters == 2 ? 1.0 : 3.0) * sizeof(cx<T>)));
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (mass_iters == 2 ? 2.0 : 4.0) * sizeof(cx<T>), mask);
                 if (mass_iters == 2)
                     hipLaunchKernelGGL((k_cb_first3d<TYv, T, true>), TILE_GRID, d.sys, d.tiles, mask, v, d1, r, x1);
                 else
@@ -2365,12 +2440,12 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             // d1 holds d_1: iterations j >= 2 read D[(j - 1) & 1] = d1 first
             cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 4.0 * sizeof(cx<T>)));
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
                 cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
             }
             cb_iterations3d<TYv, T, 1>(d, 1, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>));
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
                 cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, d0, z + d.NT, st);
             }
             // steps 3 and 4: the last iteration also forms z_zeta
@@ -2382,17 +2457,17 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             return;
         }
         {
-            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 3.0 * sizeof(cx<T>)));
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
             cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
         }
         cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         {
-            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (sizeof(zd) + 4.0 * sizeof(cx<T>)));
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
             cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
         }
         cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, x2, mask, st);
         {
-            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>));
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
             cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, d0, z + d.NT, st);
         }
         cb_iterations<DIM, TYv, T, 1>(d, diff_iters, d0, d1, r, z + d.NT, mask, st);
@@ -2432,7 +2507,7 @@ template <typename VT>
 void launch_mdot(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
                  double* part, const int* mask, const Krylov& kr, int k, hipStream_t st) {
     // reads w and nv basis vectors (full vectors of 2 NT complex values)
-    ProbeScope ps(d, KID_MDOT, st, 2.0 * d.NT * (sizeof(zd) + nv * sizeof(VT)));
+    ProbeScope ps(d, KID_MDOT, st, 2.0 * d.NT * (sizeof(zd) + nv * sizeof(VT)), mask);
     auto go = [&](auto nvc) {
         hipLaunchKernelGGL((k_mdot<decltype(nvc)::value, VT>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
                            coef, coef_ld, part, d.nchunks, d.NT, kr, k);
@@ -2452,15 +2527,15 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
                       double* part, const int* mask, hipStream_t st) {
     // reads z, d, nv basis vectors (stored like z); writes w
     ProbeScope ps(d, KID_APPLY, st,
-                  (double)d.NT * (2.0 * sizeof(cx<T>) * (1 + nv) + 2.0 * sizeof(zd) + 8.0 / d.J));
+                  (double)d.NT * (2.0 * sizeof(cx<T>) * (1 + nv) + 2.0 * sizeof(zd) + 8.0 / d.J), mask, true);
     dispatch(d, [&](auto D, auto TY) {
         auto go = [&](auto nvc) {
             if constexpr (D() == 2)
-                hipLaunchKernelGGL((k_apply_dot2d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
-                                   dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+                ps.launch(k_apply_dot2d<TY(), T, decltype(nvc)::value>, dim3(d.ntiles), dim3(kBlock), d.sys, d.tiles,
+                          mask, Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
             else
-                hipLaunchKernelGGL((k_apply_dot3d<TY(), T, decltype(nvc)::value>), TILE_GRID, d.sys, d.tiles, mask, Z,
-                                   dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
+                ps.launch(k_apply_dot3d<TY(), T, decltype(nvc)::value>, dim3(d.ntiles), dim3(kBlock), d.sys, d.tiles,
+                          mask, Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
         };
         if (nv == 1) go(std::integral_constant<int, 1>{});
         else if (nv == 2) go(std::integral_constant<int, 2>{});
@@ -2484,7 +2559,7 @@ void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part
 template <typename VT>
 void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
                        const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_PROJ_FINAL, st, 2.0 * d.NT * (sizeof(zd) + (nv + 1) * sizeof(VT)));
+    ProbeScope ps(d, KID_PROJ_FINAL, st, 2.0 * d.NT * (sizeof(zd) + (nv + 1) * sizeof(VT)), mask);
     hipLaunchKernelGGL(k_proj_final<VT>, CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, hcoef, hstride, hinv, out,
                        d.NT);
 }
