@@ -735,7 +735,7 @@ __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LO
 // W = A Z at every node and, fused, the first Gram-Schmidt pass: per-tile partials of V_i^H w
 // (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).  2D: column-marching
 // tiles (TY/4 rows per thread); 3D: k_apply_dot3d below.
-// NV >= nv basis vectors; with NV <= 4 the launch uses NV = nv exactly, so the basis loads carry no test.
+// NV >= nv basis vectors; with NV <= 8 the launch uses NV = nv exactly, so the basis loads carry no test.
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
                                                        const cx<T>* __restrict__ Z, const double* __restrict__ dnode,
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
         acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
         for (int l = 0; l < NV; ++l)
-            if (NV <= 4 || l < nv) {
+            if (NV <= 8 || l < nv) {
                 const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
                          q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                 acc[2 * l] += p.x + q.x;
@@ -771,10 +771,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
         colmarch_A<RR, true>(s, x, y0, load, dnode, emit);
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
-        for (int l = 0; l < nv; ++l) {
-            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
-            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
-        }
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
+                part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
+            }
         part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
     }
 }
@@ -843,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
             acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
             for (int l = 0; l < NV; ++l)
-                if (NV <= 4 || l < nv) {
+                if (NV <= 8 || l < nv) {
                     const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
                          q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
                     acc[2 * l] += p.x + q.x;
@@ -852,10 +854,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
         });
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
-        for (int l = 0; l < nv; ++l) {
-            part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
-            part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
-        }
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
+                part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
+            }
         part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
     }
 }
@@ -1450,10 +1454,12 @@ __global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* ch
     }
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
-        for (int l = 0; l < nv; ++l) {
-            part[(2 * l) * (long long)nchunks + blockIdx.x] = acc[2 * l];
-            part[(2 * l + 1) * (long long)nchunks + blockIdx.x] = acc[2 * l + 1];
-        }
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+            if (l < nv) {
+                part[(2 * l) * (long long)nchunks + blockIdx.x] = acc[2 * l];
+                part[(2 * l + 1) * (long long)nchunks + blockIdx.x] = acc[2 * l + 1];
+            }
         part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
     }
     __shared__ int flag;
@@ -2537,12 +2543,18 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
                 ps.launch(k_apply_dot3d<TY(), T, decltype(nvc)::value>, dim3(d.ntiles), dim3(kBlock), d.sys, d.tiles,
                           mask, Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
         };
-        if (nv == 1) go(std::integral_constant<int, 1>{});
-        else if (nv == 2) go(std::integral_constant<int, 2>{});
-        else if (nv == 3) go(std::integral_constant<int, 3>{});
-        else if (nv == 4) go(std::integral_constant<int, 4>{});
-        else if (nv <= 8) go(std::integral_constant<int, 8>{});
-        else if (nv <= 16) go(std::integral_constant<int, 16>{});
+        switch (nv) {
+            case 1: go(std::integral_constant<int, 1>{}); return;
+            case 2: go(std::integral_constant<int, 2>{}); return;
+            case 3: go(std::integral_constant<int, 3>{}); return;
+            case 4: go(std::integral_constant<int, 4>{}); return;
+            case 5: go(std::integral_constant<int, 5>{}); return;
+            case 6: go(std::integral_constant<int, 6>{}); return;
+            case 7: go(std::integral_constant<int, 7>{}); return;
+            case 8: go(std::integral_constant<int, 8>{}); return;
+            default: break;
+        }
+        if (nv <= 16) go(std::integral_constant<int, 16>{});
         else go(std::integral_constant<int, 32>{});
     });
 }
