@@ -594,9 +594,10 @@ __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile
     }
 }
 
-// k_rhs_base and k_nonlinear in one pass for a step with one linearisation (K = 1): on the tiles of
-// amplitude 0, the nodal nonlinearity of the instance is evaluated once per node and M eta_j/dt
-// (+ M s_j) of every amplitude is formed there and used at once, instead of going through BB.  The same
+// k_rhs_base and k_nonlinear in one pass for a step with one linearisation (K = 1): the nodal
+// nonlinearity of the instance is evaluated once per node and M eta_j/dt (+ M s_j) of every amplitude is
+// formed there and used at once, instead of going through BB.  The J tiles of an instance that cover the
+// same nodes share the rows (amplitude j's tile takes the row steps rr with rr % J == j).  The same
 // arithmetic as the two kernels.
 template <int DIM, int TY, int JM>
 __global__ __launch_bounds__(kBlock) void k_rhs_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
@@ -604,41 +605,43 @@ __global__ __launch_bounds__(kBlock) void k_rhs_nonlinear(const Sys* sys, const 
                                                          zd* B, long long NT) {
     const int* mask = nullptr;
     TILE_PROLOGUE();
-    if (s.j != 0) return;
+    const int s0 = tile.sys - s.j;   // amplitude 0 of the instance
+    const Sys b = sys[s0];
     const double* src0 = src_tab ? src_tab[s.inst] : nullptr;
     FOR_ROWS(TY) {
+        if (rr_ % T.J != s.j) continue;
         Nbr<DIM> n;
         make_nbr<DIM>(s, x, y, pz, n);
         const long long i = nb_index<DIM>(n, 1, 1, 1);
         zd eta[JM], h[JM];
 #pragma unroll
-        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[s.off + l * s.N + i] : zd{0.0, 0.0};
+        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[b.off + l * b.N + i] : zd{0.0, 0.0};
         double d;
-        bulk_h_reg<JM>(T, s, eta, d, h);
+        bulk_h_reg<JM>(T, b, eta, d, h);
         dnode[s.doff + i] = d;
 #pragma unroll
         for (int l = 0; l < JM; ++l) {
             if (l >= T.J) break;
-            const Sys& sl = sys[tile.sys + l];
+            const Sys& sl = sys[s0 + l];
             zd Mu, Ku, Tu;
             stencil<DIM, false, false, double>(
-                [&](int a, int b, int c) { return eta_half[sl.off + nb_index<DIM>(n, a, b, c)]; }, sl.h, sl.kv[0],
+                [&](int a, int bb, int c) { return eta_half[sl.off + nb_index<DIM>(n, a, bb, c)]; }, sl.h, sl.kv[0],
                 sl.kv[1], sl.kv[2], Mu, Ku, Tu);
-            zd bb = sl.inv_dt * Mu;
+            zd rhs = sl.inv_dt * Mu;
             if (src0) {
                 const double* src = src0 + (long long)l * 2 * s.N;
                 zd Ms;
                 stencil<DIM, false, false, double>(
-                    [&](int a, int b, int c) {
-                        const long long q = nb_index<DIM>(n, a, b, c);
+                    [&](int a, int bb, int c) {
+                        const long long q = nb_index<DIM>(n, a, bb, c);
                         return zd{src[q], src[s.N + q]};
                     },
                     sl.h, 0.0, 0.0, 0.0, Ms, Ku, Tu);
-                bb = bb + Ms;
+                rhs = rhs + Ms;
             }
             const long long o = sl.off + i;
             B[o] = zd{0.0, 0.0};
-            B[NT + o] = bb - (sl.kappa * s.w) * h[l];
+            B[NT + o] = rhs - (sl.kappa * s.w) * h[l];
         }
     }
 }
