@@ -1614,16 +1614,14 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
 // After the first pass: re-orthogonalise only if |w'|^2 = |w|^2 - |h1|^2 fell below
 // reorth_theta |w|^2.  One classical Gram-Schmidt pass leaves the new basis vector orthogonal to
 // about eps |w| / |w'|, so theta is chosen from rtol (api.hip); otherwise the second pass is
-// skipped and its results set to h2 = 0, |w'|^2 = |w|^2 - |h1|^2.
-__device__ int reorth_decide(const Krylov& kr, int s, int k) {
-    const double* h1 = kr.red1 + (long long)s * (kr.nv1 + 1);
+// skipped and its results set to h2 = 0, |w'|^2 = |w|^2 - |h1|^2.  h1, h2: the passes' sums in LDS.
+__device__ int reorth_decide(const Krylov& kr, int s, int k, const double* h1, double* h2) {
     double hn = 0.0;
     for (int i = 0; i <= k; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
     const double wn2 = h1[2 * (k + 1)];
     const int need = (kr.always_reorth || wn2 - hn < kr.reorth_theta * wn2) ? 1 : 0;
     kr.reorth[s] = need;
     if (!need) {
-        double* h2 = kr.red2 + (long long)s * (kr.nv1 + 1);
         for (int i = 0; i <= k; ++i) h2[2 * i] = h2[2 * i + 1] = 0.0;
         h2[2 * (k + 1)] = wn2 - hn;
     }
@@ -1631,14 +1629,15 @@ __device__ int reorth_decide(const Krylov& kr, int s, int k) {
 }
 
 // Column k of the Hessenberg matrix from the two projections, Givens rotations, residual estimate,
-// convergence / breakdown / restart decision for system s.
-__device__ void arnoldi_update(const Krylov& kr, int s, int k) {
-    const int m = kr.m, nv1 = kr.nv1;
-    const double* h1 = kr.red1 + (long long)s * (nv1 + 1);
-    const double* h2 = kr.red2 + (long long)s * (nv1 + 1);
-    double* col = kr.H + ((long long)s * m + k) * 2 * (m + 1);
+// convergence / breakdown / restart decision for system s.  Reads only LDS (h1, h2; rot = the previous
+// rotations cs[0..k), sn[0..2k) and g[2k], g[2k+1]; col: scratch for the column) and the two scalars
+// given, so the single thread that runs it waits on no memory load.
+__device__ void arnoldi_update(const Krylov& kr, int s, int k, const double* h1, const double* h2, const double* rot,
+                               double* col, int iters, double target) {
+    const int m = kr.m;
+    double* colg = kr.H + ((long long)s * m + k) * 2 * (m + 1);
     double* hs = kr.hsum + (long long)s * 2 * (m + 1);
-    double h2n = 0.0;
+    double h2n = 0.0, cnorm = 0.0;
     for (int i = 0; i <= k; ++i) {
         const double re = h1[2 * i] + h2[2 * i], im = h1[2 * i + 1] + h2[2 * i + 1];
         hs[2 * i] = re;
@@ -1646,15 +1645,14 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
         col[2 * i] = re;
         col[2 * i + 1] = im;
         h2n += h2[2 * i] * h2[2 * i] + h2[2 * i + 1] * h2[2 * i + 1];
+        cnorm += re * re + im * im;
     }
     const double wn2 = h2[2 * (k + 1)];
     const double hn = sqrt(fmax(wn2 - h2n, 0.0));
-    double cnorm = hn * hn;
-    for (int i = 0; i <= k; ++i) cnorm += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
-    cnorm = sqrt(cnorm);
+    cnorm = sqrt(cnorm + hn * hn);
     // previous rotations: [c s; -conj(s) c]
-    double* cs = kr.cs + (long long)s * m;
-    double* sn = kr.sn + (long long)s * 2 * m;
+    const double* cs = rot;
+    const double* sn = rot + k;
     for (int i = 0; i < k; ++i) {
         const double ar = col[2 * i], ai = col[2 * i + 1], br = col[2 * i + 2], bi = col[2 * i + 3];
         const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
@@ -1679,19 +1677,21 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
         rr = ar * nu / aa;
         ri = ai * nu / aa;
     }
-    cs[k] = c;
-    sn[2 * k] = sr;
-    sn[2 * k + 1] = si;
     col[2 * k] = rr;
     col[2 * k + 1] = ri;
+    for (int i = 0; i < 2 * (k + 1); ++i) colg[i] = col[i];
+    kr.cs[(long long)s * m + k] = c;
+    kr.sn[(long long)s * 2 * m + 2 * k] = sr;
+    kr.sn[(long long)s * 2 * m + 2 * k + 1] = si;
     double* g = kr.g + (long long)s * 2 * (m + 1);
-    const double gr = g[2 * k], gi = g[2 * k + 1];
+    const double gr = rot[3 * k], gi = rot[3 * k + 1];
     g[2 * k] = c * gr;
     g[2 * k + 1] = c * gi;
-    g[2 * k + 2] = -(sr * gr + si * gi);
-    g[2 * k + 3] = -(sr * gi - si * gr);
-    const double res = sqrt(g[2 * k + 2] * g[2 * k + 2] + g[2 * k + 3] * g[2 * k + 3]);
-    kr.iters[s] += 1;
+    const double gnr = -(sr * gr + si * gi), gni = -(sr * gi - si * gr);
+    g[2 * k + 2] = gnr;
+    g[2 * k + 3] = gni;
+    const double res = sqrt(gnr * gnr + gni * gni);
+    kr.iters[s] = iters + 1;
     kr.hinv[s] = hn > 0.0 ? 1.0 / hn : 0.0;
     if (!isfinite(res) || !isfinite(hn)) {
         kr.err[0] = 1;
@@ -1701,35 +1701,60 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k) {
         return;
     }
     const bool breakdown = hn <= 1e-14 * cnorm;
-    if (res <= kr.target[s] || breakdown || k + 1 == m) {
+    if (res <= target || breakdown || k + 1 == m) {
         kr.kcount[s] = k + 1;
         kr.iter_active[s] = 0;
     }
 }
 
-// One workgroup per system: sum the 2(k+1)+1 partials of a Gram-Schmidt pass in a fixed order, then
-// (thread 0) PHASE 1: decide on the second pass and, if it is skipped, finish the Arnoldi step;
-// PHASE 2: finish the Arnoldi step with both passes.
 // Per-system reduction of a Gram-Schmidt pass (one whole workgroup): sum the 2(k+1)+1 partials in a
-// fixed order, one wave per value, then (phase 1) decide the second pass or (phase 2, or phase 1
-// without a second pass) update the Hessenberg column.
+// fixed order, one wave per value, while the other threads stage the previous rotations in LDS; then
+// (phase 1) decide the second pass or (phase 2, or phase 1 without a second pass) update the
+// Hessenberg column.
 template <int PHASE>
 __device__ void gs_reduce_sys(const Sys* sys, const Krylov& kr, int k, const double* part, long long P, int si) {
+    constexpr int NH = 2 * (kMaxRestart + 1) + 1;
+    __shared__ double hh[2][NH], rot[3 * kMaxRestart + 2], col[2 * (kMaxRestart + 1)];
     const Sys s = sys[si];
+    const int m = kr.m;
     const int beg = PHASE == 1 ? s.tbeg : s.cbeg, end = PHASE == 1 ? s.tend : s.cend;
     const int nvals = 2 * (k + 1) + 1;
     double* out = (PHASE == 1 ? kr.red1 : kr.red2) + (long long)si * (kr.nv1 + 1);
+    int iters = 0;
+    double target = 0.0;
+    if (threadIdx.x == 0) {
+        iters = kr.iters[si];
+        target = kr.target[si];
+    }
+    // staging: the first-pass sums (phase 2), the rotations and g
+    const int nst = (PHASE == 2 ? nvals : 0) + 3 * k + 2;
+    for (int t = threadIdx.x; t < nst; t += blockDim.x) {
+        int u = t;
+        if (PHASE == 2) {
+            if (u < nvals) {
+                hh[0][u] = kr.red1[(long long)si * (kr.nv1 + 1) + u];
+                continue;
+            }
+            u -= nvals;
+        }
+        if (u < k) rot[u] = kr.cs[(long long)si * m + u];
+        else if (u < 3 * k) rot[u] = kr.sn[(long long)si * 2 * m + (u - k)];
+        else rot[u] = kr.g[(long long)si * 2 * (m + 1) + 2 * k + (u - 3 * k)];
+    }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (int)blockDim.x >> 6;
     for (int v = wv; v < nvals; v += nw) {
         double a = 0.0;
         for (int t = beg + lane; t < end; t += 64) a += part[v * P + t];
         a = wave_sum(a);
-        if (lane == 0) out[v] = a;
+        if (lane == 0) {
+            out[v] = a;
+            hh[PHASE - 1][v] = a;
+        }
     }
-    __threadfence_block();
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (PHASE == 2 || !reorth_decide(kr, si, k)) arnoldi_update(kr, si, k);
+        if (PHASE == 2 || !reorth_decide(kr, si, k, hh[0], hh[1]))
+            arnoldi_update(kr, si, k, hh[0], hh[1], rot, col, iters, target);
     }
 }
 
