@@ -127,6 +127,7 @@ struct Krylov {
     int* cycles;        // [S]
     int* err;           // [1]
     int* tick_c;        // [S] workgroups of the system done in the current second-pass launch
+    int* tick_p;        // [1] workgroups done in the current cycle-start launch
     int m;
     int nv1;            // 2*(m+1)
     double rtol;
@@ -190,11 +191,14 @@ template <typename T>
 void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
                     zd* X, const int* mask, hipStream_t st);
 
-void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st);
+// Start of a restart cycle from the residual partials of launch_residual: per-system reduction of
+// |r|^2 and |b|^2, beta, target and the cycle's state (first: the solve's start); with pub set, the
+// last workgroup also writes the host summary (any system still solving, non-finite flag, largest
+// iteration count) to pub.
+void launch_cycle_start(const Dev& d, const Krylov& kr, const double* part, bool first, int* pub, hipStream_t st);
 // phase 1 of the Gram-Schmidt reduction (phase 2 runs inside k_mdot)
 void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
-void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,
                        int iters, hipStream_t st);

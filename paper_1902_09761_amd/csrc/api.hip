@@ -166,7 +166,7 @@ struct apfc_ctx {
     double** h_tab = nullptr;
     std::vector<const void*> tab_shadow;   // pointer tables currently in d_tab
     int* h_flags = nullptr;
-    int* h_pub = nullptr;                  // mapped host flags written by k_publish
+    int* h_pub = nullptr;                  // mapped host flags written by k_cycle_start
     int* d_pub = nullptr;
     double* h_dbl = nullptr;
 
@@ -366,6 +366,7 @@ size_t carve(apfc_ctx& c, char* base) {
     k.cycles = (int*)take(sizeof(int) * S);
     k.err = (int*)take(sizeof(int) * 4);
     k.tick_c = (int*)take(sizeof(int) * S);
+    k.tick_p = (int*)take(sizeof(int));
     c.run_it_sum = (long long*)take(sizeof(long long) * S);
     c.run_it_max = (int*)take(sizeof(int) * S);
     c.run_cyc_max = (int*)take(sizeof(int) * S);
@@ -667,6 +668,7 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
     carve(*c, c->ws);
     // the tickets of the fused second-pass reduction start at zero; every launch leaves them at zero
     HIPCHK(hipMemset(c->kr.tick_c, 0, sizeof(int) * c->S));
+    HIPCHK(hipMemset(c->kr.tick_p, 0, sizeof(int)));
     return upload_tables(*c);
 }
 
@@ -802,10 +804,8 @@ void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
     else
         launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
-    launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, kr.solve_active, st);
-    launch_cycle_init(d, kr, false, st);
+    launch_cycle_start(d, kr, c->tpart, false, c->d_pub, st);
     scale_start(c, d, st);
-    launch_publish(d, kr, c->d_pub, st);
 }
 
 int capture_graphs(apfc_ctx* c) {
@@ -847,8 +847,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
         if (int rc = capture_graphs(c); rc) return rc;
     hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, kr, c->S);
     launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
-    launch_reduce(d, c->tpart, kRR, 2, false, kr.redr, 2, nullptr, st);
-    launch_cycle_init(d, kr, true, st);
+    launch_cycle_start(d, kr, c->tpart, true, nullptr, st);
     scale_start(c, d, st);
     int launched = 0;
     // Cycles before the last one of the previous solve are queued without a host round trip:
@@ -863,7 +862,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
         launched += c->m;
         if (cyc + 1 < hint) continue;
         HIPCHK(poll_sync(st));
-        // k_publish wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
+        // k_cycle_start wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
         const volatile int* pub = c->h_pub;
         if (pub[1]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
         if (!pub[0]) {

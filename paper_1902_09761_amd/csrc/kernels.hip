@@ -1576,11 +1576,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Sys* sys, const int* ma
 // ------------------------------------------------------------------------------------------
 // small per-system FGMRES bookkeeping (one thread per system)
 // ------------------------------------------------------------------------------------------
-__global__ void k_cycle_init(Krylov kr, int S, int first) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    if (!first && !kr.solve_active[s]) return;
-    const double rr = kr.redr[2 * s], bb = kr.redr[2 * s + 1];
+__device__ void cycle_init_sys(const Krylov& kr, int s, int first, double rr, double bb) {
     const double beta = sqrt(rr);
     if (!isfinite(beta) || !isfinite(bb)) {
         kr.err[0] = 1;
@@ -1594,7 +1590,8 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
         // a zero right-hand side is solved relative to the initial residual
         kr.target[s] = kr.rtol * (bn > 0.0 ? bn : beta);
     }
-    kr.relres[s] = kr.bnorm[s] > 0.0 ? beta / kr.bnorm[s] : beta;
+    const double bnorm = kr.bnorm[s];
+    kr.relres[s] = bnorm > 0.0 ? beta / bnorm : beta;
     kr.kcount[s] = 0;
     if (beta <= kr.target[s]) {
         kr.solve_active[s] = 0;
@@ -1609,6 +1606,53 @@ __global__ void k_cycle_init(Krylov kr, int S, int first) {
     g[0] = beta;
     g[1] = 0.0;
     for (int i = 1; i <= kr.m; ++i) g[2 * i] = g[2 * i + 1] = 0.0;
+}
+
+// One workgroup per system: |r|^2 and |b|^2 from the residual partials (slots kRR, kBB, one wave
+// each, fixed order), then the cycle's start (beta, target on the first cycle, the state); systems that
+// stopped solving are skipped after the first cycle.  With pub, every workgroup takes a ticket and the
+// last one writes the host summary.
+__global__ __launch_bounds__(kBlock) void k_cycle_start(const Sys* sys, Krylov kr, int S, int first,
+                                                        const double* part, long long P, int* pub) {
+    __shared__ double red[2];
+    __shared__ int flag;
+    const int si = blockIdx.x;
+    if (first || kr.solve_active[si]) {
+        const Sys s = sys[si];
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (wv < 2) {
+            double a = 0.0;
+            for (int t = s.tbeg + lane; t < s.tend; t += 64) a += part[(kRR + wv) * P + t];
+            a = wave_sum(a);
+            if (lane == 0) {
+                red[wv] = a;
+                kr.redr[2 * si + wv] = a;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) cycle_init_sys(kr, si, first, red[0], red[1]);
+    }
+    if (!pub) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                      // this workgroup's state before its ticket
+        const int t = atomicAdd(kr.tick_p, 1);
+        flag = t == S - 1;
+        if (flag) *kr.tick_p = 0;
+    }
+    __syncthreads();
+    if (!flag) return;
+    __threadfence();                          // the other workgroups' state after their tickets
+    if (threadIdx.x == 0) {
+        int any = 0, mx = 0;
+        for (int q = 0; q < S; ++q) {
+            any |= kr.solve_active[q];
+            mx = kr.iters[q] > mx ? kr.iters[q] : mx;
+        }
+        pub[0] = any;
+        pub[1] = kr.err[0];
+        pub[2] = mx;
+    }
 }
 
 // After the first pass: re-orthogonalise only if |w'|^2 = |w|^2 - |h1|^2 fell below
@@ -1770,19 +1814,6 @@ __global__ __launch_bounds__(kRedBlock) void k_gs_reduce1(const Sys* sys, Krylov
     gs_reduce_sys<1>(sys, kr, k, part, P, si);
 }
 
-// Summary flags for the host, written to mapped host memory: any system still solving, the
-// non-finite flag, the largest per-system iteration count.
-__global__ void k_publish(Krylov kr, int S, int* pub) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int any = 0, mx = 0;
-    for (int s = 0; s < S; ++s) {
-        any |= kr.solve_active[s];
-        mx = kr.iters[s] > mx ? kr.iters[s] : mx;
-    }
-    pub[0] = any;
-    pub[1] = kr.err[0];
-    pub[2] = mx;
-}
 
 __global__ void k_solve_y(Krylov kr, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2624,12 +2655,10 @@ template void launch_xupdate<double>(const Dev&, const zd*, long long, const int
 template void launch_xupdate<float>(const Dev&, const zf*, long long, const int*, const double*, int, zd*,
                                     const int*, hipStream_t);
 
-void launch_cycle_init(const Dev& d, const Krylov& kr, bool first, hipStream_t st) {
+void launch_cycle_start(const Dev& d, const Krylov& kr, const double* part, bool first, int* pub, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);
-    hipLaunchKernelGGL(k_cycle_init, dim3((d.S + 63) / 64), dim3(64), 0, st, kr, d.S, first ? 1 : 0);
-}
-void launch_publish(const Dev& d, const Krylov& kr, int* pub, hipStream_t st) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, kr, d.S, pub);
+    hipLaunchKernelGGL(k_cycle_start, dim3(d.S), dim3(kBlock), 0, st, d.sys, kr, d.S, first ? 1 : 0, part,
+                       (long long)d.ntiles, pub);
 }
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st) {
     ProbeScope ps(d, KID_SMALL, st);
