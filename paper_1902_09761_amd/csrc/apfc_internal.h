@@ -73,7 +73,7 @@ enum Slot { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kBB = 4, kE0 = 5, kE1 = 6, k
 // Kernel identifiers for the timing probe.
 enum KernelId {
     KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
-    KID_RESIDUAL, KID_MDOT, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_COUNT
+    KID_RESIDUAL, KID_GS, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_COUNT
 };
 const char* kernel_name(int kid);
 int kernel_id(const char* name);
@@ -110,8 +110,7 @@ struct Krylov {
     double* y;          // [S][m] complex
     double* hsum;       // [S][m+1] complex, h1 + h2 of the current column
     double* hinv;       // [S] 1/||w''||
-    double* red1;       // [S][nv1] reduced first projection
-    double* red2;       // [S][nv1+1] reduced second projection and ||w'||^2
+    double* red1;       // [S][nv1+1] reduction scratch (autotuner)
     double* redr;       // [S][2] reduced |r|^2, |b|^2
     double* bnorm;      // [S]
     double* target;     // [S]
@@ -126,7 +125,7 @@ struct Krylov {
     int* iters;         // [S]
     int* cycles;        // [S]
     int* err;           // [1]
-    int* tick_c;        // [S] workgroups of the system done in the current second-pass launch
+    int* tick_c;        // [S] chunks of the system done in the current second-pass launch
     int* tick_p;        // [1] workgroups done in the current cycle-start launch
     int m;
     int nv1;            // 2*(m+1)
@@ -174,11 +173,11 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
 
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
-// second Gram-Schmidt pass on the systems flagged for it; the last workgroup of each such system also
-// reduces the pass (phase 2 of the Gram-Schmidt reduction)
+// Both Gram-Schmidt passes of Arnoldi step k: the first from the operator apply's per-tile partials
+// part1, the second (only for the systems that need it) into part2; then the Hessenberg column.
 template <typename VT>
-void launch_mdot(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 double* part, const int* mask, const Krylov& kr, int k, hipStream_t st);
+void launch_gs(const Dev& d, const Krylov& kr, int k, const double* part1, const VT* V, long long vstride,
+               const zd* w, double* part2, hipStream_t st);
 template <typename T>
 void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
                       double* part, const int* mask, hipStream_t st);
@@ -196,8 +195,6 @@ void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* 
 // last workgroup also writes the host summary (any system still solving, non-finite flag, largest
 // iteration count) to pub.
 void launch_cycle_start(const Dev& d, const Krylov& kr, const double* part, bool first, int* pub, hipStream_t st);
-// phase 1 of the Gram-Schmidt reduction (phase 2 runs inside k_mdot)
-void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st);
 void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,

@@ -352,7 +352,6 @@ size_t carve(apfc_ctx& c, char* base) {
     k.hsum = (double*)take(sizeof(double) * S * 2 * (m + 1));
     k.hinv = (double*)take(sizeof(double) * S);
     k.red1 = (double*)take(sizeof(double) * S * (k.nv1 + 1));
-    k.red2 = (double*)take(sizeof(double) * S * (k.nv1 + 1));
     k.redr = (double*)take(sizeof(double) * S * kSlots);
     k.bnorm = (double*)take(sizeof(double) * S);
     k.target = (double*)take(sizeof(double) * S);
@@ -779,8 +778,7 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, V, vs, nv, c->apart, act, st);
     // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
-    launch_gs_reduce1(d, kr, k, c->apart, st);
-    launch_mdot<cx<T>>(d, V, vs, nv, c->W, kr.red1, kr.nv1 + 1, c->cpart, kr.reorth, kr, k, st);
+    launch_gs<cx<T>>(d, kr, k, c->apart, V, vs, c->W, c->cpart, st);
     launch_proj_final<cx<T>>(d, V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
 }
 

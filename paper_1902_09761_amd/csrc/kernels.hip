@@ -114,8 +114,6 @@ __device__ __forceinline__ bool last_of_system(int* ticket, int si, int n, int* 
     return last;
 }
 
-template <int PHASE>
-__device__ void gs_reduce_sys(const Sys* sys, const Krylov& kr, int k, const double* part, long long P, int si);
 
 // ------------------------------------------------------------------------------------------
 // geometry: periodic neighbours of node (x, y, z)
@@ -1417,58 +1415,6 @@ __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long
     _Pragma("unroll") for (int u_ = 0; u_ < kChunk / kBlock; ++u_)                    \
         if (const long long e = (long long)ch.e0 + threadIdx.x + (long long)u_ * kBlock; e < twoN)
 
-// Partials of V_i^H w' (i < nv) and |w'|^2 with w' = w - sum_l coef_l V_l (the second, re-
-// orthogonalising Gram-Schmidt pass).  Each thread walks its elements one at a time and keeps the
-// nv basis values of the element in registers, so V is read once.
-template <int NV, typename VT>
-__global__ __launch_bounds__(kBlock) void k_mdot(const Sys* sys, const Chunk* chunks, const int* mask, const VT* V,
-                                                long long vstride, int nv, const zd* w, const double* coef,
-                                                int coef_ld, double* part, int nchunks, long long NT, Krylov kr,
-                                                int kit) {
-    constexpr int EPT = kChunk / kBlock;
-    __shared__ double lds[4 * (2 * NV + 1)];
-    __shared__ zd cf[NV];
-    CHUNK_PROLOGUE();
-    if (threadIdx.x < NV)
-        cf[threadIdx.x] = (int)threadIdx.x < nv ? zd{coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x],
-                                                    coef[ch.sys * (long long)coef_ld + 2 * threadIdx.x + 1]}
-                                                : zd{0.0, 0.0};
-    __syncthreads();
-    double acc[2 * NV + 1];
-#pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    for (int u = 0; u < EPT; ++u) {
-        const long long e = (long long)ch.e0 + threadIdx.x + (long long)u * kBlock;
-        if (e >= twoN) break;
-        const long long gi = elem_index(s, NT, e);
-        zd vv[NV];
-#pragma unroll
-        for (int l = 0; l < NV; ++l) vv[l] = l < nv ? ld<double>(V, l * vstride + gi) : zd{0.0, 0.0};
-        zd wv = w[gi];
-#pragma unroll
-        for (int l = 0; l < NV; ++l) wv = wv - cmul(cf[l], vv[l]);
-#pragma unroll
-        for (int l = 0; l < NV; ++l) {
-            const zd t = cdot(vv[l], wv);
-            acc[2 * l] += t.x;
-            acc[2 * l + 1] += t.y;
-        }
-        acc[2 * NV] += abs2(wv);
-    }
-    block_sum<2 * NV + 1>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (l < nv) {
-                part[(2 * l) * (long long)nchunks + blockIdx.x] = acc[2 * l];
-                part[(2 * l + 1) * (long long)nchunks + blockIdx.x] = acc[2 * l + 1];
-            }
-        part[(2 * nv) * (long long)nchunks + blockIdx.x] = acc[2 * NV];
-    }
-    __shared__ int flag;
-    if (last_of_system(kr.tick_c, ch.sys, s.cend - s.cbeg, &flag)) gs_reduce_sys<2>(sys, kr, kit, part, nchunks, ch.sys);
-}
-
 // out = (w - sum_l hcoef_l V_l) * hinv, formed in FP64 and stored in the basis precision
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chunk* chunks, const int* mask,
@@ -1655,23 +1601,6 @@ __global__ __launch_bounds__(kBlock) void k_cycle_start(const Sys* sys, Krylov k
     }
 }
 
-// After the first pass: re-orthogonalise only if |w'|^2 = |w|^2 - |h1|^2 fell below
-// reorth_theta |w|^2.  One classical Gram-Schmidt pass leaves the new basis vector orthogonal to
-// about eps |w| / |w'|, so theta is chosen from rtol (api.hip); otherwise the second pass is
-// skipped and its results set to h2 = 0, |w'|^2 = |w|^2 - |h1|^2.  h1, h2: the passes' sums in LDS.
-__device__ int reorth_decide(const Krylov& kr, int s, int k, const double* h1, double* h2) {
-    double hn = 0.0;
-    for (int i = 0; i <= k; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
-    const double wn2 = h1[2 * (k + 1)];
-    const int need = (kr.always_reorth || wn2 - hn < kr.reorth_theta * wn2) ? 1 : 0;
-    kr.reorth[s] = need;
-    if (!need) {
-        for (int i = 0; i <= k; ++i) h2[2 * i] = h2[2 * i + 1] = 0.0;
-        h2[2 * (k + 1)] = wn2 - hn;
-    }
-    return need;
-}
-
 // Column k of the Hessenberg matrix from the two projections, Givens rotations, residual estimate,
 // convergence / breakdown / restart decision for system s.  Reads only LDS (h1, h2; rot = the previous
 // rotations cs[0..k), sn[0..2k) and g[2k], g[2k+1]; col: scratch for the column) and the two scalars
@@ -1751,69 +1680,119 @@ __device__ void arnoldi_update(const Krylov& kr, int s, int k, const double* h1,
     }
 }
 
-// Per-system reduction of a Gram-Schmidt pass (one whole workgroup): sum the 2(k+1)+1 partials in a
-// fixed order, one wave per value, while the other threads stage the previous rotations in LDS; then
-// (phase 1) decide the second pass or (phase 2, or phase 1 without a second pass) update the
-// Hessenberg column.
-template <int PHASE>
-__device__ void gs_reduce_sys(const Sys* sys, const Krylov& kr, int k, const double* part, long long P, int si) {
-    constexpr int NH = 2 * (kMaxRestart + 1) + 1;
-    __shared__ double hh[2][NH], rot[3 * kMaxRestart + 2], col[2 * (kMaxRestart + 1)];
-    const Sys s = sys[si];
+// The rotations of the earlier columns and g[2k], g[2k+1] of system si into LDS (whole workgroup).
+__device__ void stage_rotations(const Krylov& kr, int si, int k, double* rot) {
     const int m = kr.m;
-    const int beg = PHASE == 1 ? s.tbeg : s.cbeg, end = PHASE == 1 ? s.tend : s.cend;
-    const int nvals = 2 * (k + 1) + 1;
-    double* out = (PHASE == 1 ? kr.red1 : kr.red2) + (long long)si * (kr.nv1 + 1);
-    int iters = 0;
-    double target = 0.0;
-    if (threadIdx.x == 0) {
-        iters = kr.iters[si];
-        target = kr.target[si];
-    }
-    // staging: the first-pass sums (phase 2), the rotations and g
-    const int nst = (PHASE == 2 ? nvals : 0) + 3 * k + 2;
-    for (int t = threadIdx.x; t < nst; t += blockDim.x) {
-        int u = t;
-        if (PHASE == 2) {
-            if (u < nvals) {
-                hh[0][u] = kr.red1[(long long)si * (kr.nv1 + 1) + u];
-                continue;
-            }
-            u -= nvals;
-        }
+    for (int u = threadIdx.x; u < 3 * k + 2; u += blockDim.x) {
         if (u < k) rot[u] = kr.cs[(long long)si * m + u];
         else if (u < 3 * k) rot[u] = kr.sn[(long long)si * 2 * m + (u - k)];
         else rot[u] = kr.g[(long long)si * 2 * (m + 1) + 2 * k + (u - 3 * k)];
     }
+    __syncthreads();
+}
+
+// The nvals sums of a pass over partials part[v * P + t], t in [beg, end), in a fixed order (one wave per
+// value), into LDS out (whole workgroup).
+__device__ void pass_sums(const double* part, long long P, int beg, int end, int nvals, double* out) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = (int)blockDim.x >> 6;
     for (int v = wv; v < nvals; v += nw) {
         double a = 0.0;
         for (int t = beg + lane; t < end; t += 64) a += part[v * P + t];
         a = wave_sum(a);
-        if (lane == 0) {
-            out[v] = a;
-            hh[PHASE - 1][v] = a;
-        }
+        if (lane == 0) out[v] = a;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (PHASE == 2 || !reorth_decide(kr, si, k, hh[0], hh[1]))
-            arnoldi_update(kr, si, k, hh[0], hh[1], rot, col, iters, target);
-    }
 }
 
-// Phase 1 as a kernel: one workgroup of kRedBlock threads per system.
-constexpr int kRedBlock = 1024;
-__global__ __launch_bounds__(kRedBlock) void k_gs_reduce1(const Sys* sys, Krylov kr, int k, const double* part,
-                                                        long long P) {
-    const int si = blockIdx.x;
+constexpr int kGsGrid = 512;   // workgroups of k_gs (at least one per system)
+
+// Both Gram-Schmidt passes of Arnoldi step k in one launch.  Workgroup b serves system b % S as its
+// (b / S)-th workgroup; each reduces the system's first pass (the per-tile partials of the operator
+// apply, part1) into LDS in the same fixed order, so all of them take the same decision on the second
+// pass.  Without it, the system's first workgroup finishes the Arnoldi step and the others exit.  With
+// it, the workgroups form the second pass over the system's chunks (w' = w - sum_l h1_l V_l: partials
+// of V_l^H w' and |w'|^2, part2), and the workgroup of the system's last chunk (ticket) reduces them
+// and finishes the Arnoldi step.
+template <int NV, typename VT>
+__global__ __launch_bounds__(kBlock) void k_gs(const Sys* sys, const Chunk* chunks, Krylov kr, int S, int k,
+                                              const double* part1, long long P1, const VT* V, long long vstride,
+                                              const zd* w, double* part2, int nchunks, long long NT) {
+    constexpr int NH = 2 * (kMaxRestart + 1) + 1;
+    constexpr int EPT = kChunk / kBlock;
+    __shared__ double hh[2][NH], rot[3 * kMaxRestart + 2], col[2 * (kMaxRestart + 1)];
+    __shared__ double lds[4 * (2 * NV + 1)];
+    __shared__ zd cf[NV];
+    __shared__ int flag;
+    const int si = blockIdx.x % S, j = blockIdx.x / S, nb = ((int)gridDim.x - si + S - 1) / S;
     if (!kr.iter_active[si]) {
-        if (threadIdx.x == 0) kr.reorth[si] = 0;
+        if (j == 0 && threadIdx.x == 0) kr.reorth[si] = 0;
         return;
     }
-    gs_reduce_sys<1>(sys, kr, k, part, P, si);
+    const Sys s = sys[si];
+    const int nv = k + 1, nvals = 2 * nv + 1;
+    pass_sums(part1, P1, s.tbeg, s.tend, nvals, hh[0]);
+    // one classical Gram-Schmidt pass leaves the new vector orthogonal to about eps |w| / |w'|: a second
+    // pass when |w'|^2 = |w|^2 - |h1|^2 fell below reorth_theta |w|^2 (theta from rtol, api.hip)
+    double hn = 0.0;
+    for (int i = 0; i <= k; ++i) hn += hh[0][2 * i] * hh[0][2 * i] + hh[0][2 * i + 1] * hh[0][2 * i + 1];
+    const double wn2 = hh[0][2 * nv];
+    const bool need = kr.always_reorth || wn2 - hn < kr.reorth_theta * wn2;
+    if (!need) {
+        if (j != 0) return;
+        if (threadIdx.x == 0) {
+            kr.reorth[si] = 0;
+            for (int i = 0; i <= k; ++i) hh[1][2 * i] = hh[1][2 * i + 1] = 0.0;
+            hh[1][2 * nv] = wn2 - hn;
+        }
+        stage_rotations(kr, si, k, rot);
+        if (threadIdx.x == 0) arnoldi_update(kr, si, k, hh[0], hh[1], rot, col, kr.iters[si], kr.target[si]);
+        return;
+    }
+    if (j == 0 && threadIdx.x == 0) kr.reorth[si] = 1;
+    if (threadIdx.x < NV) cf[threadIdx.x] = (int)threadIdx.x < nv ? zd{hh[0][2 * threadIdx.x], hh[0][2 * threadIdx.x + 1]}
+                                                                  : zd{0.0, 0.0};
+    __syncthreads();
+    const long long twoN = 2 * s.N;
+    for (int ci = s.cbeg + j; ci < s.cend; ci += nb) {
+        const Chunk ch = chunks[ci];
+        double acc[2 * NV + 1];
+#pragma unroll
+        for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
+        for (int u = 0; u < EPT; ++u) {
+            const long long e = (long long)ch.e0 + threadIdx.x + (long long)u * kBlock;
+            if (e >= twoN) break;
+            const long long gi = elem_index(s, NT, e);
+            zd vv[NV];
+#pragma unroll
+            for (int l = 0; l < NV; ++l) vv[l] = l < nv ? ld<double>(V, l * vstride + gi) : zd{0.0, 0.0};
+            zd wv = w[gi];
+#pragma unroll
+            for (int l = 0; l < NV; ++l) wv = wv - cmul(cf[l], vv[l]);
+#pragma unroll
+            for (int l = 0; l < NV; ++l) {
+                const zd t = cdot(vv[l], wv);
+                acc[2 * l] += t.x;
+                acc[2 * l + 1] += t.y;
+            }
+            acc[2 * NV] += abs2(wv);
+        }
+        block_sum<2 * NV + 1>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int l = 0; l < NV; ++l)
+                if (l < nv) {
+                    part2[(2 * l) * (long long)nchunks + ci] = acc[2 * l];
+                    part2[(2 * l + 1) * (long long)nchunks + ci] = acc[2 * l + 1];
+                }
+            part2[(2 * nv) * (long long)nchunks + ci] = acc[2 * NV];
+        }
+        if (last_of_system(kr.tick_c, si, s.cend - s.cbeg, &flag)) {
+            pass_sums(part2, nchunks, s.cbeg, s.cend, nvals, hh[1]);
+            stage_rotations(kr, si, k, rot);
+            if (threadIdx.x == 0) arnoldi_update(kr, si, k, hh[0], hh[1], rot, col, kr.iters[si], kr.target[si]);
+        }
+    }
 }
-
 
 __global__ void k_solve_y(Krylov kr, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2101,7 +2080,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Ti
 // launch plumbing
 // ------------------------------------------------------------------------------------------
 static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init", "pc_final", "apply", "residual",
-                                        "mdot",     "proj_final", "xupdate",  "reduce",   "small", "other",
+                                        "gs",       "proj_final", "xupdate",  "reduce",   "small", "other",
                                         "cheb"};
 const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : "none"; }
 int kernel_id(const char* name) {
@@ -2569,23 +2548,26 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
 }
 
 template <typename VT>
-void launch_mdot(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* coef, int coef_ld,
-                 double* part, const int* mask, const Krylov& kr, int k, hipStream_t st) {
-    // reads w and nv basis vectors (full vectors of 2 NT complex values)
-    ProbeScope ps(d, KID_MDOT, st, 2.0 * d.NT * (sizeof(zd) + nv * sizeof(VT)), mask);
+void launch_gs(const Dev& d, const Krylov& kr, int k, const double* part1, const VT* V, long long vstride,
+               const zd* w, double* part2, hipStream_t st) {
+    // the second pass, where it runs, reads w and nv basis vectors
+    ProbeScope ps(d, KID_GS, st, 2.0 * d.NT * (sizeof(zd) + (k + 1) * sizeof(VT)), kr.reorth);
+    const int per = d.S >= kGsGrid ? 1 : (kGsGrid + d.S - 1) / d.S;
+    const dim3 grid(d.S * per);
+    const int nv = k + 1;
     auto go = [&](auto nvc) {
-        hipLaunchKernelGGL((k_mdot<decltype(nvc)::value, VT>), CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w,
-                           coef, coef_ld, part, d.nchunks, d.NT, kr, k);
+        hipLaunchKernelGGL((k_gs<decltype(nvc)::value, VT>), grid, dim3(kBlock), 0, st, d.sys, d.chunks, kr, d.S, k,
+                           part1, (long long)d.ntiles, V, vstride, w, part2, d.nchunks, d.NT);
     };
     if (nv <= 4) go(std::integral_constant<int, 4>{});
     else if (nv <= 8) go(std::integral_constant<int, 8>{});
     else if (nv <= 16) go(std::integral_constant<int, 16>{});
     else go(std::integral_constant<int, 32>{});
 }
-template void launch_mdot<zd>(const Dev&, const zd*, long long, int, const zd*, const double*, int, double*,
-                              const int*, const Krylov&, int, hipStream_t);
-template void launch_mdot<zf>(const Dev&, const zf*, long long, int, const zd*, const double*, int, double*,
-                              const int*, const Krylov&, int, hipStream_t);
+template void launch_gs<zd>(const Dev&, const Krylov&, int, const double*, const zd*, long long, const zd*, double*,
+                            hipStream_t);
+template void launch_gs<zf>(const Dev&, const Krylov&, int, const double*, const zf*, long long, const zd*, double*,
+                            hipStream_t);
 
 template <typename T>
 void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
@@ -2622,10 +2604,6 @@ template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*
 template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zf*, long long, int, double*,
                                       const int*, hipStream_t);
 
-void launch_gs_reduce1(const Dev& d, const Krylov& kr, int k, const double* part, hipStream_t st) {
-    ProbeScope ps(d, KID_REDUCE, st);
-    hipLaunchKernelGGL(k_gs_reduce1, dim3(d.S), dim3(kRedBlock), 0, st, d.sys, kr, k, part, (long long)d.ntiles);
-}
 
 template <typename VT>
 void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
