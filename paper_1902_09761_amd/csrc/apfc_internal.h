@@ -151,7 +151,8 @@ void launch_narrow(const zd* in, zf* out, long long n, hipStream_t st);
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st);
 void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st);
 
-void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, zd* R, double* part,
+template <typename RT>
+void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, RT* R, double* part,
                      const int* mask, hipStream_t st);
 template <typename T>
 void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st);
@@ -160,12 +161,12 @@ template <typename T>
 void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
                     cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
 
-// vscale (may be null): the input is vscale[sys] * rv (FP64) instead of v, and that scaled vector is also
-// stored to vout in precision T
+// vscale (may be null): the input is vscale[sys] * rv instead of v, and that scaled vector is also
+// stored to vout
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
                          cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                         const zd* rv, cx<T>* vout, const int* mask, hipStream_t st);
+                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st);
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
@@ -185,7 +186,7 @@ template <typename VT>
 void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
                        const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st);
 template <typename VT>
-void launch_scale(const Dev& d, const zd* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st);
+void launch_scale(const Dev& d, const VT* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st);
 template <typename T>
 void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
                     zd* X, const int* mask, hipStream_t st);

@@ -731,7 +731,7 @@ double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
 // stored to vout.
 template <typename T>
 void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mask, hipStream_t st,
-             const double* vscale = nullptr, const zd* rv = nullptr, cx<T>* vout = nullptr) {
+             const double* vscale = nullptr, const cx<T>* rv = nullptr, cx<T>* vout = nullptr) {
     cx<T>** pc = (cx<T>**)c->pc;
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
@@ -753,14 +753,24 @@ bool scale_in_precond(const apfc_ctx* c) { return c->solver.inner_kind == APFC_I
 // products and projections still accumulate in FP64), FP64 otherwise.
 template <typename T>
 cx<T>* basis(apfc_ctx* c) { return (cx<T>*)c->V; }
+// The restart residual r = b - A x is stored in the same precision: only v_0 = r / |r| is formed from
+// it (its norm is reduced from the FP64 values).
+template <typename T>
+cx<T>* residual(apfc_ctx* c) { return (cx<T>*)c->R; }
+void launch_restart_residual(apfc_ctx* c, const Dev& d, const int* mask, hipStream_t st) {
+    if (c->mixed)
+        launch_residual<zf>(d, c->X, c->B, c->dnode, residual<float>(c), c->tpart, mask, st);
+    else
+        launch_residual<zd>(d, c->X, c->B, c->dnode, residual<double>(c), c->tpart, mask, st);
+}
 
 // v_0 = r / beta where the preconditioner does not form it
 void scale_start(apfc_ctx* c, const Dev& d, hipStream_t st) {
     if (scale_in_precond(c)) return;
     if (c->mixed)
-        launch_scale<zf>(d, c->R, c->kr.inv_beta, basis<float>(c), c->kr.iter_active, st);
+        launch_scale<zf>(d, residual<float>(c), c->kr.inv_beta, basis<float>(c), c->kr.iter_active, st);
     else
-        launch_scale<zd>(d, c->R, c->kr.inv_beta, basis<double>(c), c->kr.iter_active, st);
+        launch_scale<zd>(d, residual<double>(c), c->kr.inv_beta, basis<double>(c), c->kr.iter_active, st);
 }
 
 template <typename T>
@@ -771,7 +781,7 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     cx<T>* V = basis<T>(c);
     const int* act = kr.iter_active;
     if (k == 0 && scale_in_precond(c))   // v_0 = r / beta formed by the preconditioner's first stages
-        precond<T>(c, d, nullptr, Z, act, st, kr.inv_beta, c->R, V);
+        precond<T>(c, d, nullptr, Z, act, st, kr.inv_beta, residual<T>(c), V);
     else
         precond<T>(c, d, V + k * vs, Z + k * vs, act, st);
     const int nv = k + 1;
@@ -801,7 +811,7 @@ void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
         launch_xupdate<float>(d, (const zf*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
     else
         launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
-    launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, kr.solve_active, st);
+    launch_restart_residual(c, d, kr.solve_active, st);
     launch_cycle_start(d, kr, c->tpart, false, c->d_pub, st);
     scale_start(c, d, st);
 }
@@ -844,7 +854,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     if (graphs && !c->graphs_valid)
         if (int rc = capture_graphs(c); rc) return rc;
     hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, kr, c->S);
-    launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
+    launch_restart_residual(c, d, nullptr, st);
     launch_cycle_start(d, kr, c->tpart, true, nullptr, st);
     scale_start(c, d, st);
     int launched = 0;
@@ -1351,7 +1361,7 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
                                              st);
                 }
                 launch_reduce(d, c->apart, 0, 5, false, c->kr.red1, c->kr.nv1 + 1, nullptr, st);
-                launch_residual(d, c->X, c->B, c->dnode, c->R, c->tpart, nullptr, st);
+                launch_restart_residual(c, d, nullptr, st);
             };
             body();
             HIPCHK(hipEventRecord(e0, st));

@@ -783,10 +783,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
 }
 
 // R = B - A X and per-tile partials of |R|^2, |B|^2 (slots kRR, kBB), on column-marching tiles.
-template <int TY>
+// R is stored in precision RT (the Krylov basis precision: only v_0 = r / |r| is formed from it); the
+// norms come from the FP64 values.
+template <int TY, typename RT>
 __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Tile* tiles, const int* mask,
                                                       const zd* __restrict__ X, const zd* __restrict__ B,
-                                                      const double* __restrict__ dnode, zd* __restrict__ R,
+                                                      const double* __restrict__ dnode, RT* __restrict__ R,
                                                       double* part, long long NT, int ntiles) {
     constexpr int RR = TY / 4;
     __shared__ double lds[8];
@@ -799,8 +801,8 @@ __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Til
     auto emit = [&](long long il, const zd& y1, const zd& y2) {
         const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
         const zd r1 = b1 - y1, r2 = b2 - y2;
-        R[s.off + il] = r1;
-        R[NT + s.off + il] = r2;
+        stv(R, s.off + il, r1);
+        stv(R, NT + s.off + il, r2);
         acc[0] += abs2(r1) + abs2(r2);
         acc[1] += abs2(b1) + abs2(b2);
     };
@@ -865,9 +867,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
     }
 }
 
-template <int TY>
+template <int TY, typename RT>
 __global__ __launch_bounds__(kBlock) void k_residual3d(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
-                                                      const zd* B, const double* dnode, zd* R, double* part,
+                                                      const zd* B, const double* dnode, RT* R, double* part,
                                                       long long NT, int ntiles) {
     __shared__ double lds[8];
     BRICK_PROLOGUE();
@@ -883,8 +885,8 @@ __global__ __launch_bounds__(kBlock) void k_residual3d(const Sys* sys, const Til
             apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
             const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
             const zd r1 = b1 - y1, r2 = b2 - y2;
-            R[s.off + il] = r1;
-            R[NT + s.off + il] = r2;
+            stv(R, s.off + il, r1);
+            stv(R, NT + s.off + il, r2);
             acc[0] += abs2(r1) + abs2(r2);
             acc[1] += abs2(b1) + abs2(b2);
         });
@@ -1126,7 +1128,7 @@ __host__ __device__ inline SplitCoef split_coef(double h, double cM, double cK) 
 template <typename T, int STAGE, int RX, int RY, int NTH>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v,
                                                cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
-                                               long long NT, const double* vscale, const zd* rv, cx<T>* vout) {
+                                               long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
     constexpr int RP = RX * RY, NP = RP / NTH;
     static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
     // FP32: two region buffers used in turn, so each iteration needs one barrier (its writes go to the
@@ -1144,13 +1146,13 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
     auto gidx = [&](int i) { return s.off + (long long)wrapi(tile.y0 - halo + r0 + i, s.ny) * s.nx + gx; };
     auto lidx = [&](int i) { return (r0 + i) * RX + px; };
     cx<T> X[NP], R[NP], Dd[NP];
-    // The input is v, or, when vscale is set, vscale[sys] * rv (FP64): the first basis vector of a
-    // restart cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it, in
-    // the basis precision T, to vout)
+    // The input is v, or, when vscale is set, vscale[sys] * rv (the restart residual): the first basis
+    // vector of a cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to
+    // vout)
     const double vs = vscale ? vscale[tile.sys] : 1.0;
     auto ldv = [&](long long i) {
         if (!vscale) return v[i];
-        const zd u = rv[i];
+        const zd u = ld<double>(rv, i);
         return cx<T>{T(vs * u.x), T(vs * u.y)};
     };
     // right-hand side of the inner solve
@@ -1221,10 +1223,10 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sy
         const long long g = gidx(i);
         if constexpr (STAGE == 0) {
             x1[g] = X[i];
-            if (vscale) stv(vout, g, vs * rv[g]);
+            if (vscale) stv(vout, g, vs * ld<double>(rv, g));
         } else if constexpr (STAGE == 1) {
             x2[g] = X[i];
-            if (vscale) stv(vout, NT + g, vs * rv[NT + g]);
+            if (vscale) stv(vout, NT + g, vs * ld<double>(rv, NT + g));
         } else {
             const cx<T> chi2 = X[i];
             z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
@@ -1456,13 +1458,13 @@ __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chu
 }
 
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_scale(const Sys* sys, const Chunk* chunks, const int* mask, const zd* r,
+__global__ __launch_bounds__(kBlock) void k_scale(const Sys* sys, const Chunk* chunks, const int* mask, const VT* r,
                                                  const double* inv_beta, VT* v0, long long NT) {
     CHUNK_PROLOGUE();
     const double sc = inv_beta[ch.sys];
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
-        stv(v0, gi, sc * r[gi]);
+        stv(v0, gi, sc * ld<double>(r, gi));
     }
 }
 
@@ -2275,18 +2277,23 @@ void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_t
         });
     });
 }
-void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, zd* R, double* part,
+template <typename RT>
+void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, RT* R, double* part,
                      const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_RESIDUAL, st, (double)d.NT * (6.0 * sizeof(zd) + 8.0 / d.J));
+    ProbeScope ps(d, KID_RESIDUAL, st, (double)d.NT * (4.0 * sizeof(zd) + 2.0 * sizeof(RT) + 8.0 / d.J), mask);
     dispatch(d, [&](auto D, auto TY) {
         if constexpr (D() == 3)
-            hipLaunchKernelGGL((k_residual3d<TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+            hipLaunchKernelGGL((k_residual3d<TY(), RT>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
                                d.ntiles);
         else
-            hipLaunchKernelGGL((k_residual2d<TY()>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
+            hipLaunchKernelGGL((k_residual2d<TY(), RT>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
                                d.ntiles);
     });
 }
+template void launch_residual<zd>(const Dev&, const zd*, const zd*, const double*, zd*, double*, const int*,
+                                  hipStream_t);
+template void launch_residual<zf>(const Dev&, const zd*, const zd*, const double*, zf*, double*, const int*,
+                                  hipStream_t);
 template <typename T>
 void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st) {
     // reads z (2 half vectors) and d (per instance), writes w (2 FP64 half vectors)
@@ -2372,12 +2379,11 @@ template void launch_precond<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, z
 
 template <typename T, int RX, int RY, int NTH>
 static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
-                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale, const zd* rv,
-                        cx<T>* vout, const int* mask, hipStream_t st) {
+                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                        const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
-    // input half read (FP64 residual or basis vector) and, with vscale, the basis vector written
-    const double pts = (double)d.NT, vin = vscale ? (double)sizeof(zd) : (double)sizeof(cx<T>),
-                 vb = vscale ? (double)sizeof(cx<T>) : 0.0;
+    // input half read (residual or basis vector) and, with vscale, the basis vector written
+    const double pts = (double)d.NT, vin = (double)sizeof(cx<T>), vb = vscale ? (double)sizeof(cx<T>) : 0.0;
     {
         ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
         hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
@@ -2396,7 +2402,7 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
                          cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                         const zd* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
     switch (shape) {
         case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
         case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
@@ -2408,7 +2414,7 @@ void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctil
 template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
                                           const double*, const zd*, zd*, const int*, hipStream_t);
 template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
-                                         const double*, const zd*, zf*, const int*, hipStream_t);
+                                         const double*, const zf*, zf*, const int*, hipStream_t);
 
 // stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D
 template <int DIM, int TY, typename T, int STAGE>
@@ -2613,7 +2619,7 @@ void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, con
                        d.NT);
 }
 template <typename VT>
-void launch_scale(const Dev& d, const zd* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st) {
+void launch_scale(const Dev& d, const VT* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st) {
     hipLaunchKernelGGL(k_scale<VT>, CHUNK_GRID, d.sys, d.chunks, mask, r, inv_beta, v0, d.NT);
 }
 template void launch_proj_final<zd>(const Dev&, const zd*, long long, int, const zd*, const double*, const double*,
@@ -2621,7 +2627,7 @@ template void launch_proj_final<zd>(const Dev&, const zd*, long long, int, const
 template void launch_proj_final<zf>(const Dev&, const zf*, long long, int, const zd*, const double*, const double*,
                                     int, zf*, const int*, hipStream_t);
 template void launch_scale<zd>(const Dev&, const zd*, const double*, zd*, const int*, hipStream_t);
-template void launch_scale<zf>(const Dev&, const zd*, const double*, zf*, const int*, hipStream_t);
+template void launch_scale<zf>(const Dev&, const zf*, const double*, zf*, const int*, hipStream_t);
 template <typename T>
 void launch_xupdate(const Dev& d, const cx<T>* Z, long long zstride, const int* kcount, const double* y, int ldy,
                     zd* X, const int* mask, hipStream_t st) {
