@@ -1706,7 +1706,7 @@ __device__ void pass_sums(const double* part, long long P, int beg, int end, int
     __syncthreads();
 }
 
-constexpr int kGsGrid = 512;   // workgroups of k_gs (at least one per system)
+constexpr int kGsGrid = 128;   // workgroups of k_gs (at least one per system)
 
 // Both Gram-Schmidt passes of Arnoldi step k in one launch.  Workgroup b serves system b % S as its
 // (b / S)-th workgroup; each reduces the system's first pass (the per-tile partials of the operator
