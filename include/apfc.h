@@ -123,14 +123,22 @@ int apfc_lattice_default(int kind, apfc_lattice* lattice);
  * for the bulk energy of Eq. (5) on this lattice; 0 if only the liquid exists). Host only. */
 int apfc_uniform_amplitude(const apfc_lattice* lattice, const apfc_params* params, double* phi);
 
-/* One instance.  Validates mesh, lattice and params and builds the host-side tables; no
- * device work happens before apfc_set_workspace. */
+/* One instance of the problem of Sec. II: amplitudes eta_j of the lattice's reciprocal vectors k_j
+ * (Eq. (1); triangular set of Eq. (7)) on a rectangular (2D) or box (3D) domain, here periodic,
+ * evolving by Eq. (3)-(4) with the bulk energy of Eq. (5) and its parameters a0..a3; the mesh
+ * stands for the finest level of the adaptive mesh of Sec. II.A.  mesh, lattice and params are read
+ * once (host memory, caller-owned, not kept); *out receives a context owned by the caller
+ * (apfc_destroy).  Validates the arguments (APFC_ERR_INVALID with apfc_last_error() set: non-uniform
+ * h, n[d] < 4, |k_j| = 0, resonant products the kernels do not cover, out-of-range solver fields) and
+ * builds the host-side tables; no device work happens before apfc_set_workspace. */
 int apfc_create(const apfc_mesh* mesh, const apfc_lattice* lattice, const apfc_params* params,
                 apfc_ctx** out);
 
-/* count independent instances of possibly different mesh sizes and energy parameters
- * (meshes[count], params[count]; solver fields taken from params[0] and required equal),
- * all solved together by the same batched launches. */
+/* count (1..4096) independent instances of the problem of Sec. II (as apfc_create), of possibly
+ * different mesh sizes and energy parameters a0..a3 (meshes[count], params[count], host arrays read
+ * once; one lattice and one dimension for all; solver fields taken from params[0] and required
+ * equal, else APFC_ERR_INVALID), all solved together by the same batched launches.  Instance b's
+ * amplitude j is system b*J + j of the batch (the order of apfc_stats.iters). */
 int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* lattice,
                       const apfc_params* params, apfc_ctx** out);
 
@@ -243,6 +251,7 @@ int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
 
 /* Use hipGraph replays of whole restart cycles (1) or direct launches (0, default). */
 int apfc_set_graphs(apfc_ctx* ctx, int enable);
+
 
 int apfc_destroy(apfc_ctx* ctx);
 const char* apfc_status_string(int status);

@@ -34,6 +34,9 @@ class SolverCache:
 
 def _forward_steps(solver: apfc.Solver, eta: torch.Tensor, zeta: torch.Tensor, dt: float, steps: int,
                    keep: bool) -> Tuple[torch.Tensor, torch.Tensor, List[torch.Tensor]]:
+    # every segment starts a new trajectory for the extrapolated initial guess (x0_order > 0), so that the
+    # backward pass recomputes a segment from the same initial guesses as the forward pass did
+    solver.reset_history()
     e = eta.clone()
     z = zeta.clone()
     traj = [e.clone()] if keep else []

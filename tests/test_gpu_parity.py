@@ -251,7 +251,9 @@ def test_operator_A_matches_oracle():
                                      ((256, 192), (16, 3)), ((96, 80), (8, 4))])
 def test_preconditioner_matches_oracle(inner, precision, tol, n, tiles):
     """P^{-1} by its four steps on the GPU vs the oracle's four steps with the same inner solver
-    (Jacobi-PCG 3/5 or Chebyshev 4/4), element by element."""
+    (Jacobi-PCG 3/5 or Chebyshev 4/4), element by element: the largest deviation over all nodes of both
+    fields, relative to the largest entry of the oracle's result, so that a wrong value on a single row or
+    column at a tile or halo edge fails the test."""
     nx, ny = n
     mesh = inputs.Mesh(2, (nx, ny, 1), (nx * H_TRI, ny * H_TRI, 1.0))
     zin, ein = _rand_pair(3, mesh.N, 22)
@@ -268,7 +270,8 @@ def test_preconditioner_matches_oracle(inner, precision, tol, n, tiles):
                                  mass_iters=its[0], diff_iters=its[1])
         ref = np.concatenate([c1, c2])
         got = np.concatenate([gz[j], ge[j]])
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), (j, np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= tol, (j, err)
 
 
 @pytest.mark.parametrize("inner,precision,tol", [(apfc.APFC_INNER_CHEB, apfc.APFC_FP64, 1e-12),
@@ -276,7 +279,8 @@ def test_preconditioner_matches_oracle(inner, precision, tol, n, tiles):
                                                  (apfc.APFC_INNER_PCG, apfc.APFC_FP64, 1e-12)])
 def test_preconditioner_3d_matches_oracle(inner, precision, tol):
     """bcc lattice on a 12 x 10 x 8 hex mesh: the 3D preconditioner (one launch per Chebyshev
-    iteration, or Jacobi-PCG) vs the oracle's four steps."""
+    iteration, or Jacobi-PCG) vs the oracle's four steps, element by element (largest deviation relative to
+    the largest entry)."""
     h = 60.0 * inputs.BCC_SPACING / 128.0
     mesh = inputs.Mesh(3, (12, 10, 8), (12 * h, 10 * h, 8 * h))
     zin, ein = _rand_pair(6, mesh.N, 23)
@@ -293,7 +297,8 @@ def test_preconditioner_3d_matches_oracle(inner, precision, tol):
                                  mass_iters=its[0], diff_iters=its[1])
         ref = np.concatenate([c1, c2])
         got = np.concatenate([gz[j], ge[j]])
-        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), j
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= tol, (j, err)
 
 
 @pytest.mark.parametrize("precision", [apfc.APFC_FP64, apfc.APFC_MIXED])
@@ -339,7 +344,7 @@ def test_bcc_3d_ragged_bricks(tile_rows):
                 c1, c2 = o.precond_apply(j, zin[j], ein[j], 0.9, inner="cheb", mass_iters=4, diff_iters=4)
                 ref = np.concatenate([c1, c2])
             got = np.concatenate([gz[j], ge[j]])
-            assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), (op, j)
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), (op, j)
     ref = eta_lin
     for _ in range(2):
         _, ref = o.step(ref, 1.0)
@@ -369,16 +374,23 @@ def test_tiles_taller_than_the_mesh(tile_rows, inner):
 def test_second_gram_schmidt_pass(precision):
     """rtol 5e-14 sets the second-pass threshold to (100 eps / rtol)^2 = 0.19 (re-orthogonalise
     whenever the first pass removed more than 81% of |w|^2), so the second pass and its fused reduction
-    run in many iterations; 4 steps of the 64^2 grain (mixed precision at rtol 1e-12: 3 steps) against
-    the oracle."""
+    run in many iterations; 4 steps of the 64^2 grain (mixed precision: 3 steps) against
+    the oracle.  The timing probe on k_gs counts the launches in which some system took the second pass
+    (launches where none did are left out of its count), which must be nonzero."""
     wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
     o = oracle_for(wl.mesh, tri_k(), wl.dB)
     steps = 4 if precision == apfc.APFC_FP64 else 3
     ref = wl.eta0
     for _ in range(steps):
         _, ref = o.step(ref, wl.dt)
-    rtol = 5e-14 if precision == apfc.APFC_FP64 else 1e-12
+    rtol = 5e-14
     s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB], rtol=rtol, precision=precision,
                    inner_kind=apfc.APFC_INNER_CHEB, mass_iters=5, diff_iters=3, restart=8, max_iters=2000)
+    s.probe_enable("gs", 1)
     got, _, infos = run_gpu(s, [wl.eta0], wl.dt, steps)
+    n_second, _, _ = s.probe_read()
+    s.probe_enable(None, 1)
+    # the probe keeps a k_gs launch only if some system took the second pass in it
+    print("launches with a second pass", n_second)
+    assert n_second > 0
     assert rel_l2(got[0], ref) < 1e-10

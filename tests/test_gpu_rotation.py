@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle.apfc_oracle import Grid, bcc_k, refinement_h, rotation_field, tri_k
+from oracle.apfc_oracle import Grid, bcc_k, nodal_gradient, refinement_h, rotation_field, tri_k
 from paper_1902_09761_amd import apfc, inputs
 from tests.gpu_util import H_TRI, oracle_for, phi_of, solver_for, to_dev
 
@@ -22,6 +22,18 @@ def _gpu(s, eta, ncomp, N):
     return om.cpu().numpy().reshape(ncomp, N) if ncomp > 1 else om.cpu().numpy(), h.cpu().numpy()
 
 
+def _check_h(g, eta, h, h_ref):
+    """h must equal the oracle's everywhere except at threshold ties: nodes where |grad A| lies within
+    rounding (1e-9 relative) of grad_A_eps or A within rounding of A_min, where either branch of Eq. (17)
+    is a correct result.  Every mismatch must be such a tie."""
+    A = 2.0 * np.sum(np.abs(eta) ** 2, axis=0)
+    gA = np.sqrt(np.sum(nodal_gradient(g, A[None])[:, 0] ** 2, axis=0))
+    tie = (np.abs(gA - RP["grad_A_eps"]) <= 1e-9 * RP["grad_A_eps"]) | (np.abs(A - RP["A_min"]) <= 1e-9 * RP["A_min"])
+    ok = np.isclose(h, h_ref, rtol=1e-8, atol=0.0)
+    assert np.all(ok | tie), np.flatnonzero(~(ok | tie))[:10]
+    return int(np.sum(~ok))
+
+
 def test_rotation_2d_grain_matches_oracle():
     wl = inputs.small_grain_2d(tri_k(), phi_of(tri_k()), n=64, seed=1)
     o = oracle_for(wl.mesh, tri_k(), wl.dB)
@@ -33,7 +45,7 @@ def test_rotation_2d_grain_matches_oracle():
     s = solver_for([wl.mesh], apfc.APFC_TRI2D, [wl.dB])
     om, h = _gpu(s, eta, 1, g.N)
     np.testing.assert_allclose(om, om_ref, rtol=1e-10, atol=1e-13)
-    assert np.mean(np.isclose(h, h_ref, rtol=1e-10, atol=0.0)) > 0.999
+    _check_h(g, eta, h, h_ref)
     # inside the rotated grain omega is close to sin(5 degrees)
     r = np.linalg.norm(np.stack(np.meshgrid(np.arange(64), np.arange(64), indexing="xy"), -1).reshape(-1, 2) * g.h
                        - 0.5 * wl.mesh.length[0], axis=1)
@@ -52,4 +64,4 @@ def test_rotation_3d_matches_oracle():
     s = solver_for([mesh], apfc.APFC_BCC3D, [0.02])
     om, hh = _gpu(s, eta, 3, g.N)
     np.testing.assert_allclose(om, om_ref, rtol=1e-10, atol=1e-13)
-    assert np.mean(np.isclose(hh, h_ref, rtol=1e-10, atol=0.0)) > 0.999
+    _check_h(g, eta, hh, h_ref)

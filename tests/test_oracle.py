@@ -212,6 +212,53 @@ def test_bcc_resonance_count():
     assert len(cubic) == 8 and len(quart_distinct) == 6
 
 
+def bcc_bulk_by_hand(eta, p):
+    """The bcc bulk energy written out by hand (reading R10 of the oracle, derived here without
+    the enumeration).  With sqrt 2 k = (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1), (0,1,-1):
+      triads   k1 - k3 - k6 = k1 - k4 - k5 = k2 - k3 + k5 = k2 - k4 + k6 = 0,
+      quartets k1 + k2 = k3 + k4,  k1 - k2 = k5 + k6,  k3 - k4 = k5 - k6.
+    A product of p distinct factors occurs in p! orderings in <n^p>, and each comes with its complex
+    conjugate: a triad T carries -(a3/(3 a0)) 3! (T + T^*) = -(2 a3/a0)(T + T^*), a quartet Q carries
+    (a2/(3 a0)) 4! (Q + Q^*) = (8 a2/a0)(Q + Q^*).  Pair terms give (a1/a0) A + (a2/a0)(A^2 - 2 sum |eta|^4)
+    as for Eq. (5)."""
+    e = eta
+    c = np.conj
+    A = 2.0 * np.sum(np.abs(e) ** 2, axis=0)
+    triads = e[0] * c(e[2]) * c(e[5]) + e[0] * c(e[3]) * c(e[4]) + e[1] * c(e[2]) * e[4] + e[1] * c(e[3]) * e[5]
+    quartets = e[0] * e[1] * c(e[2]) * c(e[3]) + e[0] * c(e[1]) * c(e[4]) * c(e[5]) + e[2] * c(e[3]) * c(e[4]) * e[5]
+    f = (p.a1 / p.a0 * A + p.a2 / p.a0 * (A ** 2 - 2.0 * np.sum(np.abs(e) ** 4, axis=0))
+         - 2.0 * p.a3 / p.a0 * 2.0 * triads.real + 8.0 * p.a2 / p.a0 * 2.0 * quartets.real)
+    return f
+
+
+def test_bcc_bulk_matches_hand_polynomial():
+    """The oracle's enumerated bcc f^s equals the hand-written polynomial at random amplitudes, and one
+    distinct-index quartet (eta_1 eta_2 eta_3^* eta_4^*) carries exactly 8 a2/a0."""
+    p = Params(a0=0.9, a1=0.03, a2=0.3, a3=0.7)
+    b = BulkEnergy(bcc_k(), p)
+    eta = rand_eta(6, 40, seed=11)
+    np.testing.assert_allclose(b.f(eta), bcc_bulk_by_hand(eta, p), rtol=1e-13, atol=1e-15)
+    key = (1, 1, 0, 0, 0, 0, 0, 0, 1, 1, 0, 0)     # exponents of (eta_1..eta_6, eta_1^*..eta_6^*)
+    assert math.isclose(b.terms[key], 8.0 * p.a2 / p.a0, rel_tol=1e-14)
+    key_t = (1, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 1)   # eta_1 eta_3^* eta_6^*
+    assert math.isclose(b.terms[key_t], -2.0 * p.a3 / p.a0, rel_tol=1e-14)
+
+
+def test_bcc_uniform_energy_closed_form():
+    """At eta_j = phi (real) the bcc bulk energy is (12 a1 phi^2 - 16 a3 phi^3 + 180 a2 phi^4)/a0:
+    A = 12 phi^2, 4 triads of 2 (-2 a3/a0) phi^3, pair terms (144 - 12) a2 phi^4/a0 and 3 quartets of
+    2 (8 a2/a0) phi^4.  The oracle's relaxed amplitude is the positive root of its derivative."""
+    p = Params()
+    b = BulkEnergy(bcc_k(), p)
+    for phi in (0.05, 0.13, 0.31):
+        ref = (12 * p.a1 * phi ** 2 - 16 * p.a3 * phi ** 3 + 180 * p.a2 * phi ** 4) / p.a0
+        assert math.isclose(float(b.f(np.full((6, 1), phi, dtype=complex))[0]), ref, rel_tol=1e-13)
+    phi = uniform_amplitude(b)
+    # d/dphi: 24 a1 phi - 48 a3 phi^2 + 720 a2 phi^3 = 0  ->  phi = (48 a3 + sqrt(48^2 a3^2 - 4 720 24 a1 a2)) / (2 720 a2)
+    ref = (48 * p.a3 + math.sqrt(48 ** 2 * p.a3 ** 2 - 4 * 720 * 24 * p.a1 * p.a2)) / (2 * 720 * p.a2)
+    assert math.isclose(phi, ref, rel_tol=1e-13)
+
+
 # ----------------------------------------------------------------------------------------
 # Uniform-crystal equilibrium (P1) and its energy (P5)
 # ----------------------------------------------------------------------------------------
