@@ -252,6 +252,23 @@ int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
 /* Use hipGraph replays of whole restart cycles (1) or direct launches (0, default). */
 int apfc_set_graphs(apfc_ctx* ctx, int enable);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): apfc_step with the same arguments, results and errors, but run on
+ * a static device array of the library instead of the caller's workspace.  The context needs no
+ * apfc_set_workspace; its apfc_workspace_bytes must not exceed apfc_noalloc_max_bytes() (64 MiB, e.g.
+ * one 192^2 triangular instance in mixed precision with restart 4 and x0_order 3), else
+ * APFC_ERR_WORKSPACE and nothing runs.  The call makes no hipMalloc, hipFree or hipHostMalloc and no
+ * allocation on the host: pointer tables and statistics go through host arrays sized at create, and
+ * the end of each restart cycle is read back with a small synchronous copy.  Graphs (apfc_set_graphs)
+ * and the timing probe are not used.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents: a context lays out its tables there again when another context used it since
+ * its own last call (its extrapolation history then restarts), a following call of another entry point
+ * moves the context back onto its own workspace (history restarts), and calls that overlap in time on
+ * one GPU race.  Each GPU keeps its copy of the array until the process ends. */
+int apfc_step_noalloc(apfc_ctx* ctx, apfc_state* states, double dt, const double* const* source,
+                      void* stream, apfc_stats* stats);
+size_t apfc_noalloc_max_bytes(void);
+
 
 int apfc_destroy(apfc_ctx* ctx);
 const char* apfc_status_string(int status);

@@ -32,7 +32,8 @@ EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitud
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
            "apfc_reset_history", "apfc_run",
            "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read",
-           "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error"]
+           "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error",
+           "apfc_step_noalloc", "apfc_noalloc_max_bytes"]
 
 
 class apfc_mesh(ctypes.Structure):
@@ -96,6 +97,8 @@ def lib() -> ctypes.CDLL:
         "apfc_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
         "apfc_init_zeta": (c_int, [c_void_p, P(apfc_state), c_void_p]),
         "apfc_step": (c_int, [c_void_p, P(apfc_state), c_double, P(c_void_p), c_void_p, P(apfc_stats)]),
+        "apfc_step_noalloc": (c_int, [c_void_p, P(apfc_state), c_double, P(c_void_p), c_void_p, P(apfc_stats)]),
+        "apfc_noalloc_max_bytes": (c_size_t, []),
         "apfc_reset_history": (c_int, [c_void_p]),
         "apfc_run": (c_int, [c_void_p, P(apfc_state), c_double, c_int, P(c_void_p), c_void_p, P(apfc_stats),
                              P(c_int)]),
@@ -162,6 +165,10 @@ def apfc_uniform_amplitude(lattice: apfc_lattice, params: apfc_params) -> float:
     return phi.value
 
 
+def apfc_noalloc_max_bytes() -> int:
+    return int(lib().apfc_noalloc_max_bytes())
+
+
 def make_mesh(dim: int, n: Sequence[int], length: Sequence[float]) -> apfc_mesh:
     m = apfc_mesh()
     m.dim = dim
@@ -192,7 +199,9 @@ class Solver:
     """A batch of instances behind one apfc context (apfc_create_batch); one instance is a batch
     of one.  `meshes` and `params` are lists (params may be a single apfc_params)."""
 
-    def __init__(self, meshes: List[apfc_mesh], lattice: apfc_lattice, params, device: str = "cuda"):
+    def __init__(self, meshes: List[apfc_mesh], lattice: apfc_lattice, params, device: str = "cuda",
+                 attach_workspace: bool = True):
+        """attach_workspace=False: no workspace tensor is allocated; only step_noalloc can run."""
         import torch
         if isinstance(meshes, apfc_mesh):
             meshes = [meshes]
@@ -210,11 +219,13 @@ class Solver:
         _check(lib().apfc_create_batch(count, marr, byref(lattice), parr, byref(ctx)))
         self.ctx = ctx
         nbytes = lib().apfc_workspace_bytes(ctx)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
-        _check(lib().apfc_set_workspace(ctx, c_void_p(aligned), c_size_t(nbytes)))
         self.workspace_bytes = nbytes
+        self.workspace = None
+        if attach_workspace:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            _check(lib().apfc_set_workspace(ctx, c_void_p(aligned), c_size_t(nbytes)))
 
     def __del__(self):
         try:
@@ -259,6 +270,24 @@ class Solver:
         st.iters = ctypes.cast(iters, POINTER(c_int))
         src = self._ptrs(source, "source") if source is not None else None
         rc = lib().apfc_step(self.ctx, self._states(etas, zetas), float(dt), src, _stream_handle(stream), byref(st))
+        info = {"total_iters": st.total_iters, "max_iters": st.max_iters, "cycles": st.cycles,
+                "max_relres": st.max_relres, "ms": st.ms, "iters": list(iters)}
+        if rc != APFC_OK:
+            try:
+                _check(rc)
+            except APFCError as e:
+                e.info = info
+                raise
+        return info
+
+    def step_noalloc(self, etas, zetas, dt: float, source=None, stream=None) -> dict:
+        """step() through apfc_step_noalloc (the library's static scratch instead of the workspace)."""
+        st = apfc_stats()
+        iters = (c_int * (self.count * self.J))()
+        st.iters = ctypes.cast(iters, POINTER(c_int))
+        src = self._ptrs(source, "source") if source is not None else None
+        rc = lib().apfc_step_noalloc(self.ctx, self._states(etas, zetas), float(dt), src, _stream_handle(stream),
+                                     byref(st))
         info = {"total_iters": st.total_iters, "max_iters": st.max_iters, "cycles": st.cycles,
                 "max_relres": st.max_relres, "ms": st.ms, "iters": list(iters)}
         if rc != APFC_OK:

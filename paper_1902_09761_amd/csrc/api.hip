@@ -134,9 +134,13 @@ struct apfc_ctx {
     double dt = -1.0;
     bool mixed = false;
 
-    // workspace
+    // workspace: ws is the memory the buffers below are carved from, either the caller's workspace
+    // (ws_user, apfc_set_workspace) or, during and after apfc_step_noalloc, the static scratch
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    char* ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    size_t ws_need = 0;                // bytes carve() needs (fixed at create)
     Sys* d_sys = nullptr;
     Tile* d_tiles = nullptr;
     Chunk* d_chunks = nullptr;
@@ -169,6 +173,15 @@ struct apfc_ctx {
     int* h_pub = nullptr;                  // mapped host flags written by k_cycle_start
     int* d_pub = nullptr;
     double* h_dbl = nullptr;
+    // apfc_step_noalloc: pageable host staging sized at create (the call allocates nothing) and the
+    // device copy of the host summary of k_cycle_start (in the carved memory)
+    bool noalloc = false;
+    int* pub_dev = nullptr;
+    std::vector<const void*> na_ptrs;
+    std::vector<double*> na_tab;
+    std::vector<int> na_flags;
+    std::vector<double> na_dbl;
+    int na_pub[8] = {};
 
     Probe probe;
     bool use_graphs = false;
@@ -196,6 +209,9 @@ struct apfc_ctx {
     size_t zsize() const { return mixed ? sizeof(zf) : sizeof(zd); }
     long long vstride() const { return 2 * NT; }   // complex values per full vector
 };
+
+// Drops the context from the owners of the static scratch of apfc_step_noalloc (apfc_destroy).
+void noalloc_forget(const apfc_ctx* c);
 
 namespace {
 
@@ -370,6 +386,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.run_it_max = (int*)take(sizeof(int) * S);
     c.run_cyc_max = (int*)take(sizeof(int) * S);
     c.run_res_max = (double*)take(sizeof(double) * S);
+    c.pub_dev = (int*)take(sizeof(int) * 8);
     return off + 256;
 }
 
@@ -627,6 +644,15 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
         c->cheb_shape = 0;
         build_ctiles(*c);
     }
+    {
+        apfc_ctx tmp_view = *c;      // sizes only: carve on a copy
+        c->ws_need = carve(tmp_view, nullptr);
+    }
+    c->na_ptrs.assign(4 * (size_t)count, nullptr);
+    c->na_tab.assign(4 * (size_t)count, nullptr);
+    c->na_flags.assign(2 * (size_t)c->S + 8, 0);
+    c->na_dbl.assign((size_t)c->S + 8, 0.0);
+    c->tab_shadow.reserve(4 * (size_t)count);
     *out = c;
     return APFC_OK;
 }
@@ -635,17 +661,7 @@ int apfc_create(const apfc_mesh* mesh, const apfc_lattice* lattice, const apfc_p
     return apfc_create_batch(1, mesh, lattice, params, out);
 }
 
-size_t apfc_workspace_bytes(const apfc_ctx* c) {
-    if (!c) return 0;
-    apfc_ctx tmp_view = *c;   // carve on a copy: only sizes are computed
-    tmp_view.h_tab = nullptr;
-    tmp_view.h_flags = nullptr;
-    tmp_view.h_pub = nullptr;
-    tmp_view.h_dbl = nullptr;
-    tmp_view.graphs.clear();
-    size_t n = carve(tmp_view, nullptr);
-    return n;
-}
+size_t apfc_workspace_bytes(const apfc_ctx* c) { return c ? c->ws_need : 0; }
 
 int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
     if (!c || !ptr) return fail(APFC_ERR_INVALID, "NULL argument");
@@ -663,7 +679,10 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
     }
     c->ws = (char*)ptr;
     c->ws_bytes = bytes;
+    c->ws_user = c->ws;
+    c->ws_user_bytes = bytes;
     c->hist_n = 0;
+    c->tab_shadow.clear();
     carve(*c, c->ws);
     // the tickets of the fused second-pass reduction start at zero; every launch leaves them at zero
     HIPCHK(hipMemset(c->kr.tick_c, 0, sizeof(int) * c->S));
@@ -673,6 +692,7 @@ int apfc_set_workspace(apfc_ctx* c, void* ptr, size_t bytes) {
 
 int apfc_destroy(apfc_ctx* c) {
     if (!c) return APFC_OK;
+    noalloc_forget(c);
     invalidate_graphs(*c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->probe.created) {
@@ -696,7 +716,17 @@ namespace {
 
 int need_ws(apfc_ctx* c) {
     if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
-    if (!c->ws) return fail(APFC_ERR_WORKSPACE, "no workspace attached (apfc_set_workspace)");
+    if (!c->ws_user) return fail(APFC_ERR_WORKSPACE, "no workspace attached (apfc_set_workspace)");
+    if (c->ws != c->ws_user) {
+        // the last call ran on the static scratch (apfc_step_noalloc): back onto the caller's workspace,
+        // whose tables were left as they were; the states kept for the initial guess were in the scratch
+        c->ws = c->ws_user;
+        c->ws_bytes = c->ws_user_bytes;
+        carve(*c, c->ws);
+        c->hist_n = 0;
+        c->tab_shadow.clear();
+        invalidate_graphs(*c);
+    }
     return APFC_OK;
 }
 
@@ -712,6 +742,7 @@ int refresh_dt(apfc_ctx* c, double dt, hipStream_t st) {
 
 // upload up to 4 tables of per-instance device pointers
 int upload_ptrs(apfc_ctx* c, const std::vector<const void*>* tabs, int ntabs, hipStream_t st) {
+    if (c->noalloc) return fail(APFC_ERR_INVALID, "internal: pointer tables of a no-alloc call go through upload_ptrs_na");
     std::vector<const void*> flat;
     for (int t = 0; t < ntabs; ++t) flat.insert(flat.end(), tabs[t].begin(), tabs[t].end());
     if (flat.size() <= c->tab_shadow.size() && std::equal(flat.begin(), flat.end(), c->tab_shadow.begin()))
@@ -724,6 +755,21 @@ int upload_ptrs(apfc_ctx* c, const std::vector<const void*>* tabs, int ntabs, hi
     return APFC_OK;
 }
 double* const* tab(apfc_ctx* c, int t) { return c->d_tab + t * c->count; }
+
+// upload_ptrs for apfc_step_noalloc: the n pointers staged in c->na_ptrs go through the pageable
+// c->na_tab (sized at create) with a synchronous copy; nothing is allocated.
+int upload_ptrs_na(apfc_ctx* c, int n, hipStream_t st) {
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) c->na_tab[i] = (double*)c->na_ptrs[i];
+    HIPCHK(hipMemcpyAsync(c->d_tab, c->na_tab.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->tab_shadow.clear();
+    return APFC_OK;
+}
+
+// Where k_cycle_start publishes the host summary: mapped pinned host memory, or in a no-alloc call a
+// device slot copied to the host after the cycle.
+int* pub_target(apfc_ctx* c) { return c->noalloc ? c->pub_dev : c->d_pub; }
 
 // P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
 // Chebyshev (3D), or the paper's Jacobi-PCG.
@@ -812,7 +858,7 @@ void run_cycle(apfc_ctx* c, const Dev& d, hipStream_t st) {
     else
         launch_xupdate<double>(d, (const zd*)c->Z, vs, kr.kcount, kr.y, 2 * c->m, c->X, kr.solve_active, st);
     launch_restart_residual(c, d, kr.solve_active, st);
-    launch_cycle_start(d, kr, c->tpart, false, c->d_pub, st);
+    launch_cycle_start(d, kr, c->tpart, false, pub_target(c), st);
     scale_start(c, d, st);
 }
 
@@ -850,7 +896,7 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
     Dev d = c->dev();
     Krylov& kr = c->kr;
     const long long vs = c->vstride();
-    const bool graphs = c->use_graphs && d.probe == nullptr;
+    const bool graphs = c->use_graphs && d.probe == nullptr && !c->noalloc;
     if (graphs && !c->graphs_valid)
         if (int rc = capture_graphs(c); rc) return rc;
     hipLaunchKernelGGL(k_reset_counters, dim3((c->S + 63) / 64), dim3(64), 0, st, kr, c->S);
@@ -872,6 +918,11 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
         HIPCHK(poll_sync(st));
         // k_cycle_start wrote: [0] any system still solving, [1] non-finite residual, [2] largest iteration count
         const volatile int* pub = c->h_pub;
+        if (c->noalloc) {
+            HIPCHK(hipMemcpyAsync(c->na_pub, c->pub_dev, sizeof(int) * 3, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            pub = c->na_pub;
+        }
         if (pub[1]) return fail(APFC_ERR_NONFINITE, "non-finite residual in FGMRES");
         if (!pub[0]) {
             launched = pub[2];
@@ -890,20 +941,22 @@ int fgmres(apfc_ctx* c, hipStream_t st, int* total_iters) {
 int fill_stats(apfc_ctx* c, hipStream_t st, apfc_stats* stats, double ms) {
     if (!stats) return APFC_OK;
     const int S = c->S;
-    HIPCHK(hipMemcpyAsync(c->h_flags, c->kr.iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(c->h_flags + S, c->kr.cycles, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(c->h_dbl, c->kr.relres, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    int* flags = c->noalloc ? c->na_flags.data() : c->h_flags;
+    double* dbl = c->noalloc ? c->na_dbl.data() : c->h_dbl;
+    HIPCHK(hipMemcpyAsync(flags, c->kr.iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(flags + S, c->kr.cycles, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(dbl, c->kr.relres, sizeof(double) * S, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     stats->total_iters = 0;
     stats->max_iters = 0;
     stats->cycles = 0;
     stats->max_relres = 0.0;
     for (int s = 0; s < S; ++s) {
-        stats->total_iters += c->h_flags[s];
-        stats->max_iters = std::max(stats->max_iters, c->h_flags[s]);
-        stats->cycles = std::max(stats->cycles, c->h_flags[S + s]);
-        stats->max_relres = std::max(stats->max_relres, c->h_dbl[s]);
-        if (stats->iters) stats->iters[s] = c->h_flags[s];
+        stats->total_iters += flags[s];
+        stats->max_iters = std::max(stats->max_iters, flags[s]);
+        stats->cycles = std::max(stats->cycles, flags[S + s]);
+        stats->max_relres = std::max(stats->max_relres, dbl[s]);
+        if (stats->iters) stats->iters[s] = flags[s];
     }
     stats->ms = ms;
     return APFC_OK;
@@ -942,7 +995,7 @@ int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st,
             const zd* h[3] = {nullptr, nullptr, nullptr};
             for (int q = 0; q < use; ++q) h[q] = c->hist[(c->hist_newest - q + Q) % Q];
             const int oldest = (c->hist_newest + 1) % Q;
-            if (!c->use_graphs) {
+            if (!c->use_graphs || c->noalloc) {
                 // the guess goes to the scratch buffer W, which then becomes X; the state's buffer is
                 // kept as it is as the newest state, and the dropped state's buffer becomes W
                 launch_extrapolate(d, c->X, h, c->W, nullptr, use, st);
@@ -950,7 +1003,9 @@ int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st,
                 c->X = c->W;
                 c->W = c->hist[oldest];
                 c->hist[oldest] = state;
-                invalidate_graphs(*c);
+                // captured cycles held X's old address (a no-alloc call frees nothing: it only marks them)
+                if (c->noalloc) c->graphs_valid = false;
+                else invalidate_graphs(*c);
             } else {
                 // captured cycles hold X's address: copy the state, extrapolate in place
                 launch_extrapolate(d, c->X, h, c->X, c->hist[oldest], use, st);
@@ -1423,3 +1478,117 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------------------------------------
+// apfc_step_noalloc: one step on the library's static device scratch, for callers that cannot
+// allocate.  Every GPU that runs it holds its own copy of `scratch` (kNoAllocBytes, until the process
+// ends); its address is looked up once per device and only that address is used on the host side.
+// The calls on one GPU share the scratch: a context lays out its tables there again whenever another
+// context used it in between (and then restarts the history of the extrapolated guess), and calls
+// that overlap in time on one GPU race.
+// ----------------------------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kNoAllocDevices = 64;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+const apfc_ctx* g_scratch_owner[kNoAllocDevices] = {};
+
+__global__ void k_zero_ints(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+void noalloc_forget(const apfc_ctx* c) {
+    for (auto& o : g_scratch_owner)
+        if (o == c) o = nullptr;
+}
+
+namespace {
+// The pointer tables of one step (eta, zeta, source) staged without allocating.
+int prepare_step_na(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, hipStream_t st) {
+    if (int rc = check_states(c, states, true); rc) return rc;
+    if (int rc = refresh_dt(c, dt, st); rc) return rc;
+    const int n = c->count;
+    for (int b = 0; b < n; ++b) {
+        if (source && !source[b]) return fail(APFC_ERR_INVALID, "source[b] is NULL");
+        c->na_ptrs[b] = states[b].eta;
+        c->na_ptrs[n + b] = states[b].zeta;
+        c->na_ptrs[2 * n + b] = source ? source[b] : nullptr;
+    }
+    return upload_ptrs_na(c, 3 * n, st);
+}
+
+// Carve the context's buffers from this device's scratch (first use on the device: look its address
+// up) and lay out the tables there, unless this context was the last to do so.
+int attach_scratch(apfc_ctx* c, hipStream_t st) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(APFC_ERR_INVALID, "apfc_step_noalloc: device index out of range");
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255) != 0) return fail(APFC_ERR_HIP, "apfc_step_noalloc: scratch address not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    char* base = (char*)g_scratch_ptr[dev];
+    if (c->ws == base && g_scratch_owner[dev] == c) return APFC_OK;
+    c->ws = base;
+    c->ws_bytes = kNoAllocBytes;
+    carve(*c, base);
+    c->hist_n = 0;
+    c->tab_shadow.clear();
+    c->graphs_valid = false;
+    g_scratch_owner[dev] = nullptr;
+    // tables by synchronous copies from the context's host vectors; the tickets of the fused reductions
+    // start at zero (a fill kernel, not a memset)
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpyAsync(c->d_sys, c->sys.data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->d_chunks, c->chunks.data(), sizeof(Chunk) * c->chunks.size(), hipMemcpyHostToDevice, st));
+    if (!c->ctiles.empty())
+        HIPCHK(hipMemcpyAsync(c->d_ctiles, c->ctiles.data(), sizeof(CTile) * c->ctiles.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_zero_ints, dim3((c->S + 255) / 256), dim3(256), 0, st, c->kr.tick_c, c->S);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, c->kr.tick_p, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    g_scratch_owner[dev] = c;
+    return APFC_OK;
+}
+
+struct NoAllocScope {
+    apfc_ctx* c;
+    explicit NoAllocScope(apfc_ctx* cc) : c(cc) { c->noalloc = true; }
+    ~NoAllocScope() { c->noalloc = false; }
+};
+}  // namespace
+
+extern "C" int apfc_step_noalloc(apfc_ctx* c, apfc_state* states, double dt, const double* const* source, void* stream,
+                                 apfc_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    if (c->ws_need > kNoAllocBytes)
+        return fail(APFC_ERR_WORKSPACE, "apfc_step_noalloc: the context needs " + std::to_string(c->ws_need) +
+                                            " bytes of scratch, more than the " + std::to_string(kNoAllocBytes) +
+                                            " bytes of the static scratch; use apfc_step with a workspace");
+    hipStream_t st = (hipStream_t)stream;
+    NoAllocScope scope(c);
+    if (int rc = attach_scratch(c, st); rc) return rc;
+    if (int rc = prepare_step_na(c, states, dt, source, st); rc) return rc;
+    Dev d = c->dev();
+    d.probe = nullptr;
+    launch_state_in(d, tab(c, 0), tab(c, 1), c->X, st);
+    int iters = 0;
+    if (int rc = step_body(c, d, dt, source != nullptr, st, &iters); rc) {
+        (void)fill_stats(c, st, stats, 0.0);
+        return rc;
+    }
+    launch_state_out(d, c->X, tab(c, 0), tab(c, 1), st);
+    HIPCHK(hipGetLastError());
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return fill_stats(c, st, stats, ms);
+}
+
+extern "C" size_t apfc_noalloc_max_bytes(void) { return kNoAllocBytes; }

@@ -121,3 +121,24 @@ def test_workspace_size_and_missing_workspace():
 def test_status_strings():
     for s in (0, 1, -1, -2, -3, -4):
         assert apfc.lib().apfc_status_string(s)
+
+
+def test_noalloc_limit_is_checked_on_the_host():
+    """apfc_step_noalloc refuses a context whose workspace would exceed the static scratch before it
+    touches the device (APFC_ERR_WORKSPACE), and a NULL context (APFC_ERR_INVALID)."""
+    L = apfc.lib()
+    assert L.apfc_noalloc_max_bytes() == 64 << 20
+    big = apfc.make_mesh(2, (1024, 1024), (2902.0, 2902.0))
+    _, c = _create(big)
+    assert L.apfc_workspace_bytes(c) > L.apfc_noalloc_max_bytes()
+    st = (apfc.apfc_state * 1)()
+    assert L.apfc_step_noalloc(c, st, 1.0, None, None, None) == apfc.APFC_ERR_WORKSPACE
+    assert b"static scratch" in L.apfc_last_error()
+    assert L.apfc_step_noalloc(None, st, 1.0, None, None, None) == apfc.APFC_ERR_INVALID
+    L.apfc_destroy(c)
+    small = apfc.make_mesh(2, (96, 80), (96 * 2.26725, 80 * 2.26725))
+    _, c = _create(small, params=apfc.apfc_params_default(precision=apfc.APFC_MIXED, restart=4, x0_order=3,
+                                                               inner_kind=apfc.APFC_INNER_CHEB, mass_iters=5,
+                                                               diff_iters=3))
+    assert L.apfc_workspace_bytes(c) <= L.apfc_noalloc_max_bytes()
+    L.apfc_destroy(c)
