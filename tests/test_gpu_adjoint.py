@@ -48,9 +48,34 @@ def test_autograd_checkpointed_gradient_matches_oracle():
     etaT = ag.run(eta0, dBt, cache, dt, steps, checkpoint_every=2)
     L = _loss(etaT, to_dev(target), dBt, cache, wl.mesh.h ** 2)
     L.backward()
-    assert abs(float(L) - L_ref) < 1e-10 * abs(L_ref)
+    assert abs(float(L.detach()) - L_ref) < 1e-10 * abs(L_ref)
     assert rel_l2(from_dev(eta0.grad), g_ref) < 1e-8
     assert abs(float(dBt.grad) - ddB_ref) < 1e-8 * abs(ddB_ref)
+
+
+def test_checkpoint_cadence_gradient_matches_oracle():
+    """The differentiation workload's recipe on a 64^2 mesh at its real cadence: 50 FP64 steps, a checkpoint
+    every 10 steps, loss = w |eta(T) - target|^2 + E(eta(T)).  The oracle's gradient (direct solves and
+    their conjugate transposes), the target (the oracle's run at Delta B = 0.03) and the loss are read from
+    tests/golden/twograin64_gradient.npz, written by tests/golden/make_twograin_gradient.py."""
+    import os
+    from paper_1902_09761_amd import autograd as ag
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "twograin64_gradient.npz"))
+    n, dt, steps, dB = int(ref["n"]), float(ref["dt"]), int(ref["steps"]), float(ref["dB"])
+    wl = inputs.two_grains_2d(tri_k(), phi_of(tri_k()), n=n, seed=int(ref["seed"]), dB=dB)
+    cache = ag.SolverCache(apfc.make_mesh(2, wl.mesh.n, wl.mesh.length), apfc.apfc_lattice_default(apfc.APFC_TRI2D),
+                           rtol=1e-13)
+    eta0 = to_dev(wl.eta0).requires_grad_(True)
+    dBt = torch.tensor(dB, dtype=torch.float64, device="cuda", requires_grad=True)
+    etaT = ag.run(eta0, dBt, cache, dt, steps, checkpoint_every=10)
+    L = _loss(etaT, to_dev(ref["target"]), dBt, cache, wl.mesh.h ** 2)
+    L.backward()
+    err_g = rel_l2(from_dev(eta0.grad), ref["grad_eta0"])
+    err_d = abs(float(dBt.grad) - float(ref["grad_dB"])) / abs(float(ref["grad_dB"]))
+    print("loss", float(L.detach()), "ref", float(ref["loss"]), "grad rel-L2", err_g, "dL/dDeltaB rel", err_d)
+    assert abs(float(L.detach()) - float(ref["loss"])) < 1e-10 * abs(float(ref["loss"]))
+    assert err_g < 1e-8
+    assert err_d < 1e-8
 
 
 def test_differentiation_workload_finite_differences():
