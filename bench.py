@@ -12,10 +12,18 @@ Workloads (seeded, synthetic, resident in HBM before the timed region starts):
   bcc128   128^3 bcc lattice (6 amplitudes), spherical grain rotated 5 degrees about [001], 20 steps
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tri1024|batch64|bcc128]
-                    [--precision mixed|fp64] [--no-compare] [--probe KERNEL] [--no-cpu-baseline]
+                    [--precision mixed|fp64] [--no-compare] [--no-variants] [--probe KERNEL] [--no-cpu-baseline]
 
 Prints one JSON line; value = (sum over instances of J * N) * K / seconds of the K timed steps.  The
 other precision runs the same steps afterwards (unless --no-compare) for the eta and energy differences.
+With the default workload the line also carries `variants.batch64` and `variants.bcc128`: the same
+K steps (after the same W warm-up steps) of the other two workloads, each with its own throughput,
+roofline and mixed-vs-FP64 differences (--no-variants skips them).
+
+Roofline: during the W warm-up steps the timing probe times every launch of every kernel family (HIP
+events on the launch stream): `kernels` lists every family with a byte model (algorithmic bytes per
+launch / average duration of its working launches) and its share of the kernel time.  The family with
+the largest share is then sampled alone (every 7th launch) inside the timed region: `roofline`.
 """
 import argparse
 import hashlib
@@ -30,8 +38,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "amplitude DOF-steps/s at 1e-8 rel. residual + % HBM peak; plain vs mixed/batch"
 HBM_PEAK_GBS = 8000.0
-KERNELS_SRC = os.path.join(ROOT, "paper_1902_09761_amd", "csrc", "kernels.hip")
-TRAFFIC_MD = os.path.join(ROOT, "profiles", "apply_dot_tri1024_mixed_hbm_counters.md")
+CSRC = os.path.join(ROOT, "paper_1902_09761_amd", "csrc")
+KERNEL_SOURCES = ["apfc_internal.h", "kernels_common.h", "kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip"]
+PROFILES = os.path.join(ROOT, "profiles")
+# kernel families with a byte model, as the library's probe names them, and the kernels they cover
+FAMILIES = {"cheb": "k_cheb2d (3D: k_cb_*)", "apply": "k_apply_dot2d/3d", "proj_final": "k_proj_final",
+            "residual": "k_residual2d/3d", "extrapolate": "k_extrapolate", "rhs": "k_rhs_nonlinear",
+            "pcg_spmv": "k_cg_spmv", "pcg_update": "k_cg_update"}
 
 
 def parse():
@@ -45,6 +58,8 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the run in the other precision (FP64 vs mixed: eta and energy differences)")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the batch64 and bcc128 runs that the default workload's line carries")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
     ap.add_argument("--restart", type=int, default=4)
     ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
@@ -53,7 +68,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=None, help="time step (default: the workload's, 1.0)")
     ap.add_argument("--mass-iters", type=int, default=None)
     ap.add_argument("--diff-iters", type=int, default=None)
-    ap.add_argument("--probe", default="apply", help="kernel timed with HIP events for the roofline ('none': off)")
+    ap.add_argument("--probe", default="all",
+                    help="kernel family timed with HIP events for the roofline ('all': every family; 'none': off)")
     ap.add_argument("--probe-every", type=int, default=7,
                     help="time every n-th launch of the probed kernel (an event pair idles the stream briefly; "
                          "keep n coprime with the restart length so that every Arnoldi index is sampled)")
@@ -69,30 +85,31 @@ def parse():
     return ap.parse_args()
 
 
-def make_workload(args):
+def make_workload(args, workload):
     """Returns (lattice, list of inputs.Workload, dim)."""
     import numpy as np
     from paper_1902_09761_amd import apfc, inputs
-    kind = apfc.APFC_BCC3D if args.workload == "bcc128" else apfc.APFC_TRI2D
+    kind = apfc.APFC_BCC3D if workload == "bcc128" else apfc.APFC_TRI2D
     lat = apfc.apfc_lattice_default(kind)
     dim = 3 if kind == apfc.APFC_BCC3D else 2
     kk = np.array(apfc.lattice_k(lat, dim))
 
     def phi_of(dB):
         return apfc.apfc_uniform_amplitude(lat, apfc.apfc_params_default(a1=0.5 * dB))
-    if args.workload == "tri1024":
+    if workload == "tri1024":
         wls = [inputs.voronoi_2d(kk, phi_of, n=args.n or 1024, seed=1)]
-    elif args.workload == "batch64":
+    elif workload == "batch64":
         wls = inputs.batch_2d(kk, phi_of, count=64, seed=1)
     else:
         wls = [inputs.sphere_3d(kk, phi_of, n=args.n or 128, seed=1)]
     return lat, wls, dim
 
 
-def run_gpu(args, precision, probe=None):
+def run_gpu(args, precision, probe=None, workload=None, graphs=None):
     import torch
     from paper_1902_09761_amd import apfc, inputs
-    lat, wls, dim = make_workload(args)
+    workload = workload or args.workload
+    lat, wls, dim = make_workload(args, workload)
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
     inner = apfc.APFC_INNER_CHEB if args.inner == "cheb" else apfc.APFC_INNER_PCG
     mi = args.mass_iters or (5 if args.inner == "cheb" else 3)
@@ -102,7 +119,8 @@ def run_gpu(args, precision, probe=None):
           for w in wls]
     ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
     s = apfc.Solver(ms, lat, ps)
-    s.set_graphs(args.graphs)
+    graphs = args.graphs if graphs is None else graphs
+    s.set_graphs(graphs)
     if args.tiles:
         tr = [int(v) for v in args.tiles.split(",")]
         s.set_tiles(tr[0], tr[1] if len(tr) > 1 else 0)
@@ -113,8 +131,23 @@ def run_gpu(args, precision, probe=None):
     zts = [torch.zeros_like(e) for e in ets]
     s.init_zeta(ets, zts)
     dt = args.dt if args.dt is not None else wls[0].dt
+    fam_probe = {}
     if args.warmup > 0:
+        if probe == "all":
+            # the warm-up steps sample every launch of every family: the per-family table and the family
+            # with the largest share of the kernel time, which the timed region then samples alone
+            s.probe_enable("all", 1)
         s.run(ets, zts, dt, args.warmup)
+        if probe == "all":
+            for f in FAMILIES:
+                n, ms_, bpl, issued = s.probe_read_kernel(f)
+                if n > 0:
+                    fam_probe[f] = {"launches": n, "ms": ms_, "bytes_per_launch": bpl, "issued": issued}
+            s.probe_read()
+            s.probe_enable(None)
+    if probe == "all":
+        ranked = rooflines({"probe": fam_probe})
+        probe = ranked[0]["family"] if ranked else "cheb"
     if probe:
         s.probe_enable(probe, args.probe_every)
     iters, total = [], []
@@ -134,30 +167,88 @@ def run_gpu(args, precision, probe=None):
     J = lat.J
     dofs = sum(J * w.mesh.N for w in wls)
     out = {"sec": sec, "iters": iters, "total_iters": total, "tile_rows": ty, "dofs": dofs, "J": J, "dt": dt,
-           "relres": info["max_relres"], "instances": len(wls), "mesh": wls[0].name}
+           "relres": info["max_relres"], "instances": len(wls), "mesh": wls[0].name, "graphs": bool(graphs),
+           "workload": workload}
     if probe:
-        n, ms_, bpl = s.probe_read()
-        out["probe"] = {"kernel": probe, "launches": n, "ms": ms_, "bytes_per_launch": bpl,
-                        "every": args.probe_every}
+        out["probe"] = {}
+        n, ms_, bpl, issued = s.probe_read_kernel(probe)
+        if n > 0:
+            out["probe"][probe] = {"launches": n, "ms": ms_, "bytes_per_launch": bpl, "issued": issued}
+        s.probe_read()
         s.probe_enable(None)
+    out["warmup_probe"] = fam_probe
     out["energy"] = s.energy(ets)
     out["eta_host"] = [e.cpu().numpy() for e in ets]
     return out
 
 
-def traffic_from_profile(tile_rows):
-    """HBM bytes per k_apply_dot launch from the committed counter summary, if it was taken with the
-    current kernel source and the same tile rows (null otherwise)."""
-    if not os.path.exists(TRAFFIC_MD):
+def kernel_sources_sha256():
+    """sha256 over the kernel sources (in the order of KERNEL_SOURCES): a counter summary is valid only
+    for the kernels it was taken on."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(family, workload, tiles):
+    """HBM bytes per working launch of one kernel family from the committed counter summary
+    profiles/<family>_<workload>_hbm_counters.md, if it was taken with the current kernel source and the
+    same tiling (null otherwise)."""
+    path = os.path.join(PROFILES, f"{family}_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
         return None, None
-    text = open(TRAFFIC_MD).read()
+    text = open(path).read()
     m1 = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
-    m2 = re.search(r"kernels_hip_sha256:\s*([0-9a-f]+)", text)
-    m3 = re.search(r"tile_rows:\s*([0-9]+)", text)
-    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
-    if not (m1 and m2 and m3) or m2.group(1) != sha or int(m3.group(1)) != tile_rows:
-        return None, os.path.relpath(TRAFFIC_MD, ROOT)
-    return float(m1.group(1)), os.path.relpath(TRAFFIC_MD, ROOT)
+    m2 = re.search(r"kernel_sources_sha256:\s*([0-9a-f]+)", text)
+    m3 = re.search(r"tiles:\s*([0-9]+),([0-9]+)", text)
+    sha = kernel_sources_sha256()
+    rel = os.path.relpath(path, ROOT)
+    if not (m1 and m2 and m3) or m2.group(1) != sha or (int(m3.group(1)), int(m3.group(2))) != tuple(tiles):
+        return None, rel
+    return float(m1.group(1)), rel
+
+
+def rooflines(res):
+    """Per-family roofline entries from the probe's samples, and the family with the largest share of the
+    sampled kernel time (the dominant kernel)."""
+    pr = res.get("probe") or {}
+    fams = []
+    for f, d in pr.items():
+        if d["launches"] <= 0 or d["bytes_per_launch"] <= 0:
+            continue
+        avg_ms = d["ms"] / d["launches"]
+        ach = d["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+        fams.append({"family": f, "kernel": FAMILIES.get(f, f), "bytes_per_launch": d["bytes_per_launch"],
+                     "avg_launch_us": 1e3 * avg_ms, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
+                     "sampled_launches": d["launches"], "issued": d["issued"],
+                     # sampled time scaled by the sampling rate: the family's share of the kernel time
+                     "est_ms": d["ms"] * d["issued"] / max(1, d["launches"])})
+    fams.sort(key=lambda e: -e["est_ms"])
+    tot = sum(e["est_ms"] for e in fams)
+    for e in fams:
+        e["time_share"] = e["est_ms"] / tot if tot > 0 else 0.0
+    return fams
+
+
+def roofline_entry(fam, workload, tiles, every):
+    traffic, src = traffic_from_profile(fam["family"], workload, tiles)
+    return {"bound": "hbm", "kernel": fam["kernel"], "family": fam["family"], "achieved": fam["achieved"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fam["frac"], "traffic": traffic, "traffic_source": src,
+            "avg_launch_us": fam["avg_launch_us"], "launches": fam["sampled_launches"], "sampled_every": every,
+            "bytes_per_launch": fam["bytes_per_launch"], "time_share": fam["time_share"]}
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
 def cpu_baseline(args):
@@ -177,8 +268,49 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     o.step(wl.eta0, args.dt if args.dt is not None else wl.dt)
     sec = time.perf_counter() - t0
+    h = host_info()
     return {"value": len(k) * wl.mesh.N / sec, "unit": "amplitude-DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}; SuperLU factor + solve per amplitude, single-threaded; {sec:.1f} s"}
+            "sample": f"{what}; SuperLU factor + solve per amplitude, single-threaded; {sec:.1f} s",
+            "host_cpu": h["cpu_model"], "host_nproc": h["nproc"]}
+
+
+def measure(args, workload, precision, probe, compare, graphs=None):
+    """One workload: the timed run, its rooflines and (compare) the other precision's run of the same
+    steps.  Returns the fields of a bench line (or of a variant)."""
+    import numpy as np
+    res = run_gpu(args, precision, probe=probe, workload=workload, graphs=graphs)
+    K = args.steps
+    out = {"value": res["dofs"] * K / res["sec"], "ms_per_step": 1e3 * res["sec"] / K,
+           "fgmres_iters_per_step": float(np.mean(res["iters"])), "final_relres": res["relres"],
+           "config": {"workload": workload, "instances": res["instances"], "first_instance": res["mesh"],
+                      "amplitude_dofs": res["dofs"], "J": res["J"], "dt": res["dt"], "rtol": 1e-8,
+                      "precision": precision, "inner": args.inner, "restart": args.restart,
+                      "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
+                      "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
+                      "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "x0_order": args.x0,
+                      "graphs": res["graphs"], "entry": "apfc_step" if args.per_step else "apfc_run"}}
+    timed = rooflines(res)
+    if timed:
+        out["roofline"] = roofline_entry(timed[0], workload, res["tile_rows"], args.probe_every)
+    listed = rooflines({"probe": res["warmup_probe"]})
+    if timed:
+        share = [e["time_share"] for e in listed if e["family"] == timed[0]["family"]]
+        out["roofline"]["time_share"] = share[0] if share else None
+    if listed:
+        # every family with a byte model, from the warm-up steps (every launch timed)
+        out["kernels"] = [{k: e[k] for k in ("family", "kernel", "bytes_per_launch", "avg_launch_us", "achieved",
+                                             "frac", "time_share", "sampled_launches")} for e in listed]
+    if compare:
+        other = "fp64" if precision == "mixed" else "mixed"
+        r2 = run_gpu(args, other, workload=workload, graphs=graphs)
+        a, b = (res, r2) if precision == "fp64" else (r2, res)
+        diffs = [float(np.linalg.norm(y - x) / np.linalg.norm(x)) for x, y in zip(a["eta_host"], b["eta_host"])]
+        ediff = [abs(y - x) / abs(x) for x, y in zip(a["energy"], b["energy"])]
+        out["other_precision"] = {other: {"value": res["dofs"] * K / r2["sec"], "ms_per_step": 1e3 * r2["sec"] / K,
+                                          "fgmres_iters_per_step": float(np.mean(r2["iters"]))},
+                                  "mixed_vs_fp64_eta_rel_l2": max(diffs),
+                                  "mixed_vs_fp64_energy_rel": max(ediff)}
+    return out
 
 
 def main():
@@ -188,56 +320,39 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
     probe = None if args.probe in ("", "none") else args.probe
-    res = run_gpu(args, args.precision, probe=probe)
     K = args.steps
-    value = res["dofs"] * K / res["sec"]
+    m = measure(args, args.workload, args.precision, probe, args.compare)
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": m["value"],
         "unit": "amplitude-DOF-steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * res["sec"] / K,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "instances": res["instances"], "first_instance": res["mesh"],
-                   "amplitude_dofs": res["dofs"], "J": res["J"], "dt": res["dt"], "rtol": 1e-8,
-                   "precision": args.precision, "inner": args.inner, "restart": args.restart,
-                   "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
-                   "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
-                   "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "x0_order": args.x0,
-                   "graphs": bool(args.graphs), "entry": "apfc_step" if args.per_step else "apfc_run"},
-        "fgmres_iters_per_step": float(np.mean(res["iters"])),
-        "final_relres": res["relres"],
+        "config": m["config"],
+        "fgmres_iters_per_step": m["fgmres_iters_per_step"],
+        "final_relres": m["final_relres"],
     }
-    pr = res.get("probe")
-    if pr and pr["launches"] > 0:
-        avg_ms = pr["ms"] / pr["launches"]
-        ach = pr["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-        traffic, src = (traffic_from_profile(res["tile_rows"][0])
-                        if (pr["kernel"] == "apply" and args.workload == "tri1024" and args.precision == "mixed")
-                        else (None, None))
-        line["roofline"] = {"bound": "hbm", "kernel": "k_apply_dot" if pr["kernel"] == "apply" else pr["kernel"],
-                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                            "traffic": traffic, "traffic_source": src, "avg_launch_us": 1e3 * avg_ms,
-                            "launches": pr["launches"], "sampled_every": pr["every"],
-                            "bytes_per_launch": pr["bytes_per_launch"]}
-    if args.compare:
-        other = "fp64" if args.precision == "mixed" else "mixed"
-        r2 = run_gpu(args, other)
-        a, b = (res, r2) if args.precision == "fp64" else (r2, res)
-        diffs = [float(np.linalg.norm(y - x) / np.linalg.norm(x)) for x, y in zip(a["eta_host"], b["eta_host"])]
-        ediff = [abs(y - x) / abs(x) for x, y in zip(a["energy"], b["energy"])]
-        line["variants"] = {other: {"value": res["dofs"] * K / r2["sec"], "ms_per_step": 1e3 * r2["sec"] / K,
-                                    "fgmres_iters_per_step": float(np.mean(r2["iters"]))},
-                            "mixed_vs_fp64_eta_rel_l2": max(diffs),
-                            "mixed_vs_fp64_energy_rel": max(ediff)}
+    for key in ("roofline", "kernels"):
+        if key in m:
+            line[key] = m[key]
+    variants = {}
+    if "other_precision" in m:
+        variants.update(m["other_precision"])
+    if args.variants and args.workload == "tri1024" and args.n is None:
+        for wl in ("batch64", "bcc128"):
+            v = measure(args, wl, args.precision, probe, args.compare)
+            v.pop("kernels", None)
+            variants[wl] = v
+    if variants:
+        line["variants"] = variants
     if args.calibrate_copy:
         import torch
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")

@@ -52,9 +52,9 @@ enum {
     APFC_ERR_NONFINITE = -4       /* a residual norm became NaN or Inf                   */
 };
 
-enum { APFC_TRI2D = 0, APFC_BCC3D = 1, APFC_CUSTOM = 2 };
+enum { APFC_TRI2D = 0, APFC_BCC3D = 1, APFC_CUSTOM = 2, APFC_FCC3D = 3 };
 enum { APFC_FP64 = 0, APFC_MIXED = 1 };          /* preconditioner + Z basis precision */
-enum { APFC_INNER_PCG = 0, APFC_INNER_CHEB = 1 }; /* inner solver of the preconditioner  */
+enum { APFC_INNER_PCG = 0, APFC_INNER_CHEB = 1, APFC_INNER_MG = 2 }; /* inner solver of the preconditioner */
 
 /* Periodic uniform Q1 mesh: dim in {2,3}; n[d] nodes (= elements) per direction, n[d] >= 4;
  * length[d] = n[d] * h for one common h (checked to 1e-12 relative).  n[2], length[2] are
@@ -65,10 +65,11 @@ typedef struct {
     double length[3];
 } apfc_mesh;
 
-/* Reciprocal lattice vectors.  apfc_lattice_default fills k for APFC_TRI2D (Eq. (7), J = 3)
- * and APFC_BCC3D (six unit <110>/sqrt(2) vectors, J = 6).  APFC_CUSTOM takes J <= 8 vectors
- * as given; apfc_create rejects sets whose resonant products are not all pair terms or terms
- * with distinct amplitude indices. */
+/* Reciprocal lattice vectors.  apfc_lattice_default fills k for APFC_TRI2D (Eq. (7), J = 3),
+ * APFC_BCC3D (six unit <110>/sqrt(2) vectors, J = 6) and APFC_FCC3D (the FCC lattice that the paper's 3D
+ * runs use, Sec. II after Eq. (7) and Sec. III: four <111>/sqrt(3) vectors summing to zero and three
+ * <200>/sqrt(3) vectors, J = 7).  APFC_CUSTOM takes J <= 8 vectors as given; apfc_create rejects sets
+ * whose resonant products are not all pair terms or terms with distinct amplitude indices. */
 typedef struct {
     int kind;
     int J;
@@ -84,8 +85,19 @@ typedef struct {
     int max_iters;           /* FGMRES iterations per solve before APFC_ERR_NOT_CONVERGED */
     int precision;           /* APFC_FP64 or APFC_MIXED                                 */
     int mass_iters;          /* inner iterations of the mass solve (paper: 3)            */
-    int diff_iters;          /* inner iterations of each diffusion solve (paper: 5)      */
-    int inner_kind;          /* APFC_INNER_PCG (paper) or APFC_INNER_CHEB                */
+    int diff_iters;          /* inner iterations of each diffusion solve (paper: 5); with
+                                APFC_INNER_MG the Chebyshev smoothing iterations before and
+                                after each coarse-grid correction                         */
+    int inner_kind;          /* APFC_INNER_PCG (paper: Jacobi-PCG), APFC_INNER_CHEB
+                                (Chebyshev-Jacobi) or APFC_INNER_MG (the paper's multigrid
+                                variant of Sec. III: one V-cycle per diffusion solve, a
+                                geometric hierarchy of meshes of 2, 4, ... times the mesh
+                                size while every direction of every instance halves to at
+                                least 16 (2D) / 8 (3D) nodes, Chebyshev-Jacobi smoothing on
+                                the upper quarter of the spectrum, transposed Q1
+                                interpolation, the coarsest level (at most 8192 nodes per
+                                instance, else APFC_ERR_INVALID) by 24 Chebyshev
+                                iterations; the mass solve as APFC_INNER_CHEB)             */
     int x0_order;            /* FGMRES initial guess of the first Picard solve of a step:
                                 0 = the state passed in (default); 1 / 2 / 3 = linear /
                                 quadratic / cubic extrapolation in time from the states
@@ -116,12 +128,19 @@ typedef struct apfc_ctx apfc_ctx;
  * Sec. III) and solver defaults (K = 1, rtol 1e-8, restart 30, max_iters 500, FP64). */
 void apfc_params_default(apfc_params* params);
 
-/* Fill lattice for kind APFC_TRI2D or APFC_BCC3D. Returns APFC_ERR_INVALID for other kinds. */
+/* Fill lattice for kind APFC_TRI2D, APFC_BCC3D or APFC_FCC3D. Returns APFC_ERR_INVALID for other kinds. */
 int apfc_lattice_default(int kind, apfc_lattice* lattice);
 
 /* Relaxed amplitude phi of the uniform crystal eta_j = phi (positive root of d f^s / d phi = 0
  * for the bulk energy of Eq. (5) on this lattice; 0 if only the liquid exists). Host only. */
 int apfc_uniform_amplitude(const apfc_lattice* lattice, const apfc_params* params, double* phi);
+
+/* Relaxed real amplitudes phi[J] (host array) of the uniform crystal of the bulk energy of Eq. (5) on this
+ * lattice, one value per shell of equal |k_j| (the amplitudes of a shell are equivalent): for one shell
+ * (APFC_TRI2D, APFC_BCC3D) the value of apfc_uniform_amplitude; for several (APFC_FCC3D: <111> and
+ * <200>) the stationary point of f^s over the shell values found by Newton's method from that value.
+ * All zero when only the liquid exists; APFC_ERR_INVALID if the iteration leaves phi > 0.  Host only. */
+int apfc_equilibrium_amplitudes(const apfc_lattice* lattice, const apfc_params* params, double* phi);
 
 /* One instance of the problem of Sec. II: amplitudes eta_j of the lattice's reciprocal vectors k_j
  * (Eq. (1); triangular set of Eq. (7)) on a rectangular (2D) or box (3D) domain, here periodic,
@@ -238,14 +257,26 @@ int apfc_rotation(apfc_ctx* ctx, const apfc_state* states, double* const* omega,
 int apfc_probe_enable(apfc_ctx* ctx, const char* name, int every);
 int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* bytes_per_launch);
 
+/* name = "all" in apfc_probe_enable samples every kernel family at once, each on its own count (every
+ * every-th launch of each).  apfc_probe_read_kernel gives one family's figures from the records kept
+ * since the last apfc_probe_read (it does not reset them): sampled working launches, their summed
+ * duration, their mean algorithmic bytes (0 for families without a byte model: xupdate, gs's first
+ * pass, the small kernels) and, in issued, every launch of the family so far, sampled or not.  Family
+ * names: "cheb" (fused and per-iteration Chebyshev preconditioner stages), "apply" (operator apply with
+ * the first Gram-Schmidt pass), "residual", "proj_final", "xupdate", "gs", "extrapolate", "rhs",
+ * "pcg_spmv", "pcg_update", "pcg_init", "pc_final", "reduce", "small", "other". */
+int apfc_probe_read_kernel(apfc_ctx* ctx, const char* name, int* launches, double* total_ms,
+                           double* bytes_per_launch, long long* issued);
+
 /* Tile-height autotuner: times the stencil kernels for each candidate tile on the attached
  * workspace and keeps the fastest.  Optional; the default tile is used otherwise. */
 int apfc_autotune(apfc_ctx* ctx, void* stream, int* chosen_tile_rows);
 
 /* Set the tiling by hand instead of apfc_autotune: tile_rows in {4, 8, 16, 32} (rows of the 64-wide
- * stencil tiles) and precond_region in 0..4 (LDS region of the fused 2D Chebyshev preconditioner:
- * 128x32 nodes / 512 threads, 64x32 / 256, 64x64 / 512, 128x36 / 512, 128x40 / 512; the taller regions
- * give fewer tiles, which can fill the chip in fewer rounds).  Needs the workspace. */
+ * stencil tiles) and precond_region in 0..5 (LDS region of the fused 2D Chebyshev preconditioner, nodes /
+ * threads / FP32 region buffers: 128x32 / 512 / 2, 64x32 / 256 / 1, 64x64 / 512 / 1, 128x36 / 512 / 2,
+ * 128x36 / 512 / 1, 128x72 / 1024 / 1; taller regions recompute less halo, one buffer leaves room for more
+ * workgroups per CU).  Needs the workspace. */
 int apfc_set_tiles(apfc_ctx* ctx, int tile_rows, int precond_region);
 int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
 
@@ -268,7 +299,6 @@ int apfc_set_graphs(apfc_ctx* ctx, int enable);
 int apfc_step_noalloc(apfc_ctx* ctx, apfc_state* states, double dt, const double* const* source,
                       void* stream, apfc_stats* stats);
 size_t apfc_noalloc_max_bytes(void);
-
 
 int apfc_destroy(apfc_ctx* ctx);
 const char* apfc_status_string(int status);

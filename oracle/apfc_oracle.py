@@ -39,6 +39,13 @@ R9  Periodic boundary conditions; zeta^0 = M^{-1} G eta^0.
 R10 bcc lattice: k_j = the six unit <110>/sqrt(2) vectors; f^s is the zero-wave-vector
     part of (a1/a0) n^2 - a3/(3 a0) n^3 + a2/(3 a0) n^4 with n from Eq. (1).  For the
     triangular lattice this reproduces Eq. (5)-(6) exactly.
+R17 Multigrid inner solve (the paper uses one algebraic V-cycle from a library): a geometric V-cycle on
+    the structured mesh, coarse operators by rediscretisation (equal to the Galerkin products), symmetric
+    Chebyshev-Jacobi smoothing; see MultigridL.
+R16 FCC lattice (J = 7; the paper takes its vectors and bulk polynomial from another work): the
+    first two shells of the fcc reciprocal lattice, four <111>/sqrt 3 vectors (one of each +- pair,
+    chosen to sum to zero, |k| = 1) and three <200>/sqrt 3 vectors (|k| = 2/sqrt 3); f^s by the same
+    enumeration as R10.
 """
 from __future__ import annotations
 
@@ -79,6 +86,12 @@ def bcc_k() -> np.ndarray:
     """bcc reciprocal vectors (R10): one of each +-<110>/sqrt(2) pair."""
     v = np.array([[1, 1, 0], [1, -1, 0], [1, 0, 1], [1, 0, -1], [0, 1, 1], [0, 1, -1]], float)
     return v / math.sqrt(2.0)
+
+
+def fcc_k() -> np.ndarray:
+    """FCC reciprocal vectors (R16): <111>/sqrt 3 (summing to zero) and <200>/sqrt 3."""
+    v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1], [2, 0, 0], [0, 2, 0], [0, 0, 2]], float)
+    return v / math.sqrt(3.0)
 
 
 def kappas(k: np.ndarray, p: Params) -> np.ndarray:
@@ -198,6 +211,31 @@ def uniform_amplitude(bulk: BulkEnergy) -> float:
     if disc < 0:
         return 0.0
     return (-3.0 * c[3] + math.sqrt(disc)) / (8.0 * c[4])
+
+
+def equilibrium_amplitudes(bulk: BulkEnergy) -> np.ndarray:
+    """Relaxed real amplitudes of the uniform crystal, one value per shell of equal |k_j| (the
+    amplitudes of one shell are equivalent under the lattice's point group): a stationary point of
+    f^s(phi_shell(j)) with every phi > 0, found by Newton's method on the shell gradient
+    d f / d phi_s = sum_{j in s} 2 Re F^s_j, started from the single-shell root (a library root finder
+    on the oracle's own polynomial).  One shell (triangular, bcc): uniform_amplitude.  Zeros when the
+    single-shell root is the liquid."""
+    import scipy.optimize
+    k2 = np.round(np.sum(bulk.k * bulk.k, axis=1), 12)
+    shells = sorted(set(k2.tolist()))
+    phi0 = uniform_amplitude(bulk)
+    if len(shells) == 1 or phi0 == 0.0:
+        return np.full(bulk.J, phi0)
+    which = np.array([shells.index(v) for v in k2])
+
+    def grad(x):
+        eta = x[which].astype(np.complex128)[:, None]
+        F = bulk.F(eta)[:, 0]
+        return np.array([2.0 * np.sum(F[which == s].real) for s in range(len(shells))])
+
+    sol = scipy.optimize.root(grad, np.full(len(shells), phi0), method="hybr", tol=1e-13)
+    assert np.max(np.abs(sol.fun)) < 1e-15 and np.all(sol.x > 0.0), sol
+    return sol.x[which]
 
 
 # ---------------------------------------------------------------------------------------
@@ -461,10 +499,11 @@ class Oracle:
             ll.append((Mh / math.sqrt(dt) + math.sqrt(kap) * Kh) / DL)
         return (min(lm), max(lm)), (min(ll), max(ll))
 
-    def precond_apply(self, j, beta1, beta2, dt, inner=None, mass_iters=3, diff_iters=5):
+    def precond_apply(self, j, beta1, beta2, dt, inner=None, mass_iters=3, diff_iters=5, mg_options=None):
         """x = P^{-1} b by the four steps; inner=None uses exact (direct) inner solves,
         inner='pcg' uses fixed-count Jacobi-preconditioned CG from a zero start, inner='cheb'
-        fixed-count Chebyshev iteration with the exact Jacobi spectral bounds."""
+        fixed-count Chebyshev iteration with the exact Jacobi spectral bounds, inner='mg' one multigrid
+        V-cycle for each L solve (MultigridL with mg_options) and Chebyshev for the mass solve."""
         kap = self.kappa[j]
         L = (self.M / math.sqrt(dt) + math.sqrt(kap) * self.K).tocsc()
         if inner is None:
@@ -473,6 +512,11 @@ class Oracle:
         elif inner == "pcg":
             solve_M = lambda b: jacobi_pcg(self.M, b, mass_iters)
             solve_L = lambda b: jacobi_pcg(L, b, diff_iters)
+        elif inner == "mg":
+            bm, _ = self.jacobi_bounds(j, dt)
+            mg = MultigridL(self.grid, kap, dt, **(mg_options or {}))
+            solve_M = lambda b: chebyshev(self.M, b, mass_iters, *bm)
+            solve_L = lambda b: mg.cycle(b)
         else:
             bm, bl = self.jacobi_bounds(j, dt)
             solve_M = lambda b: chebyshev(self.M, b, mass_iters, *bm)
@@ -496,6 +540,82 @@ class Oracle:
         Minv = np.linalg.inv(M)
         upper = np.block([[np.eye(N), Minv @ K], [np.zeros((N, N)), Minv @ L]])
         return lower @ upper
+
+
+# ---------------------------------------------------------------------------------------
+# Multigrid V-cycle for the diffusion operator L (the multigrid inner solve of Sec. III; R17)
+# ---------------------------------------------------------------------------------------
+
+def coarse_grid(g: Grid) -> Grid:
+    """The grid of twice the mesh size on the same periodic domain (n even in every direction)."""
+    return Grid(g.dim, tuple(v // 2 for v in g.n[: g.dim]), tuple(g.length[: g.dim]))
+
+
+def interpolation(gc: Grid) -> sp.csr_matrix:
+    """Prolongation from the coarse grid gc to the grid of half its mesh size: the Q1 interpolant, i.e.
+    the embedding of the coarse finite-element space in the fine one.  Per direction fine node 2i takes
+    coarse node i and fine node 2i + 1 the mean of coarse nodes i and i + 1 (periodic); tensor product,
+    x fastest.  Restriction is its transpose."""
+    def one(nc):
+        rows, cols, vals = [], [], []
+        for i in range(nc):
+            rows += [2 * i, 2 * i + 1, 2 * i + 1]
+            cols += [i, i, (i + 1) % nc]
+            vals += [1.0, 0.5, 0.5]
+        return sp.csr_matrix((vals, (rows, cols)), shape=(2 * nc, nc))
+    ops = [one(n) for n in gc.n[: gc.dim]]
+    out = ops[gc.dim - 1]
+    for d in range(gc.dim - 2, -1, -1):
+        out = sp.kron(out, ops[d], format="csr")
+    return out
+
+
+class MultigridL:
+    """One V-cycle, from a zero initial guess, for L = M/sqrt(dt) + sqrt(kappa) K (R17).
+
+    Levels: the fine grid, then coarser grids of twice the mesh size while every n is even and n/2 >=
+    coarse_min (and at most max_levels levels in all).  Each level's L is the finite-element L assembled on that level's grid, which equals the
+    Galerkin product P^T L P for the Q1 interpolation P (nested spaces; pinned by a test).  Smoother:
+    nu Chebyshev-Jacobi iterations for the upper part [lam_max/alpha, lam_max] of the spectrum of D^{-1}L
+    (lam_max exact from the symbol), the same polynomial before and after the coarse-grid correction, so
+    the cycle is symmetric.  Coarsest level: coarse_iters Chebyshev-Jacobi iterations over the whole
+    spectrum [lam_min, lam_max].  The cycle:
+      x = S(b);  r = b - L x;  x += P V(P^T r);  x += S(b - L x)."""
+
+    def __init__(self, grid: Grid, kappa: float, dt: float, nu: int = 2, alpha: float = 4.0,
+                 coarse_min: int = 16, coarse_iters: int = 24, max_levels: Optional[int] = None):
+        self.nu, self.alpha, self.coarse_iters = nu, alpha, coarse_iters
+        self.levels = []
+        g = grid
+        while True:
+            M, K, _ = assemble(g, np.zeros((0, g.dim)))
+            L = (M / math.sqrt(dt) + math.sqrt(kappa) * K).tocsr()
+            lam = []
+            D = L.diagonal()[0]
+            for corner in itertools.product((0.0, math.pi), repeat=g.dim):
+                Mh, Kh, _ = symbols_at(g, np.zeros(g.dim), corner)
+                lam.append((Mh / math.sqrt(dt) + math.sqrt(kappa) * Kh) / D)
+            self.levels.append({"grid": g, "L": L, "lam": (min(lam), max(lam))})
+            more = max_levels is None or len(self.levels) < max_levels
+            if more and all(v % 2 == 0 and v // 2 >= coarse_min for v in g.n[: g.dim]):
+                gc = coarse_grid(g)
+                self.levels[-1]["P"] = interpolation(gc)
+                g = gc
+            else:
+                break
+
+    def smooth(self, lev, b):
+        lo, hi = lev["lam"]
+        return chebyshev(lev["L"], b, self.nu, hi / self.alpha, hi)
+
+    def cycle(self, b, level=0):
+        lev = self.levels[level]
+        if level == len(self.levels) - 1:
+            return chebyshev(lev["L"], b, self.coarse_iters, *lev["lam"])
+        L, P = lev["L"], lev["P"]
+        x = self.smooth(lev, b)
+        x = x + P @ self.cycle(P.T @ (b - L @ x), level + 1)
+        return x + self.smooth(lev, b - L @ x)
 
 
 def jacobi_pcg(A, b, iters):

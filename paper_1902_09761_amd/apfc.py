@@ -23,15 +23,16 @@ APFC_ERR_INVALID = -1
 APFC_ERR_HIP = -2
 APFC_ERR_WORKSPACE = -3
 APFC_ERR_NONFINITE = -4
-APFC_TRI2D, APFC_BCC3D, APFC_CUSTOM = 0, 1, 2
+APFC_TRI2D, APFC_BCC3D, APFC_CUSTOM, APFC_FCC3D = 0, 1, 2, 3
 APFC_FP64, APFC_MIXED = 0, 1
-APFC_INNER_PCG, APFC_INNER_CHEB = 0, 1
+APFC_INNER_PCG, APFC_INNER_CHEB, APFC_INNER_MG = 0, 1, 2
 APFC_OP_A, APFC_OP_PINV = 0, 1
 
-EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_create",
+EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_equilibrium_amplitudes",
+           "apfc_create",
            "apfc_create_batch", "apfc_workspace_bytes", "apfc_set_workspace", "apfc_init_zeta", "apfc_step",
            "apfc_reset_history", "apfc_run",
-           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read",
+           "apfc_energy", "apfc_energy_grad", "apfc_step_adjoint", "apfc_apply", "apfc_rotation", "apfc_probe_enable", "apfc_probe_read", "apfc_probe_read_kernel",
            "apfc_autotune", "apfc_set_tiles", "apfc_get_tiles", "apfc_set_graphs", "apfc_destroy", "apfc_status_string", "apfc_last_error",
            "apfc_step_noalloc", "apfc_noalloc_max_bytes"]
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "apfc_params_default": (None, [P(apfc_params)]),
         "apfc_lattice_default": (c_int, [c_int, P(apfc_lattice)]),
         "apfc_uniform_amplitude": (c_int, [P(apfc_lattice), P(apfc_params), P(c_double)]),
+        "apfc_equilibrium_amplitudes": (c_int, [P(apfc_lattice), P(apfc_params), P(c_double)]),
         "apfc_create": (c_int, [P(apfc_mesh), P(apfc_lattice), P(apfc_params), P(c_void_p)]),
         "apfc_create_batch": (c_int, [c_int, P(apfc_mesh), P(apfc_lattice), P(apfc_params), P(c_void_p)]),
         "apfc_workspace_bytes": (c_size_t, [c_void_p]),
@@ -110,6 +112,7 @@ def lib() -> ctypes.CDLL:
         "apfc_rotation": (c_int, [c_void_p, P(apfc_state), P(c_void_p), P(c_void_p), P(apfc_refine_params), c_void_p]),
         "apfc_probe_enable": (c_int, [c_void_p, c_char_p, c_int]),
         "apfc_probe_read": (c_int, [c_void_p, P(c_int), P(c_double), P(c_double)]),
+        "apfc_probe_read_kernel": (c_int, [c_void_p, c_char_p, P(c_int), P(c_double), P(c_double), P(c_int64)]),
         "apfc_autotune": (c_int, [c_void_p, c_void_p, P(c_int)]),
         "apfc_set_tiles": (c_int, [c_void_p, c_int, c_int]),
         "apfc_get_tiles": (c_int, [c_void_p, P(c_int), P(c_int)]),
@@ -167,6 +170,12 @@ def apfc_uniform_amplitude(lattice: apfc_lattice, params: apfc_params) -> float:
 
 def apfc_noalloc_max_bytes() -> int:
     return int(lib().apfc_noalloc_max_bytes())
+
+
+def apfc_equilibrium_amplitudes(lattice: apfc_lattice, params: apfc_params) -> List[float]:
+    phi = (c_double * lattice.J)()
+    _check(lib().apfc_equilibrium_amplitudes(byref(lattice), byref(params), phi))
+    return list(phi)
 
 
 def make_mesh(dim: int, n: Sequence[int], length: Sequence[float]) -> apfc_mesh:
@@ -377,3 +386,10 @@ class Solver:
         b = c_double()
         _check(lib().apfc_probe_read(self.ctx, byref(n), byref(ms), byref(b)))
         return n.value, ms.value, b.value
+
+    def probe_read_kernel(self, name: str):
+        """(sampled working launches, their total ms, mean algorithmic bytes, launches issued) of one
+        kernel family since the last probe_read (which resets the records)."""
+        n, ms, b, issued = c_int(), c_double(), c_double(), c_int64()
+        _check(lib().apfc_probe_read_kernel(self.ctx, name.encode(), byref(n), byref(ms), byref(b), byref(issued)))
+        return n.value, ms.value, b.value, issued.value

@@ -50,10 +50,12 @@ struct Sys {
 struct Tile { int sys, x0, y0, z; };
 // Interior tile of the fused Chebyshev preconditioner kernels (region = interior + halo).
 struct CTile { int sys, x0, y0, z; };
-// LDS region shapes (width, height, threads) of the fused preconditioner kernels.
-constexpr int kChebShapes = 5;
-constexpr int kChebShape[kChebShapes][3] = {{128, 32, 512}, {64, 32, 256}, {64, 64, 512}, {128, 36, 512},
-                                            {128, 40, 512}};
+// LDS region shapes (width, height, threads) of the fused preconditioner kernels; every thread owns
+// height * width / threads consecutive rows of one column.
+constexpr int kChebShapes = 6;
+constexpr int kChebShape[kChebShapes][3] = {{128, 32, 512}, {64, 32, 256}, {64, 64, 512},
+                                            {128, 36, 512}, {128, 64, 1024}, {256, 32, 1024}};
+
 struct Chunk { int sys; int e0; };     // element offset inside the system's 2N-element full vector
 
 // Resonant products of the bulk energy with distinct amplitude indices: term value
@@ -72,19 +74,21 @@ enum Slot { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kBB = 4, kE0 = 5, kE1 = 6, k
 
 // Kernel identifiers for the timing probe.
 enum KernelId {
-    KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
-    KID_RESIDUAL, KID_GS, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_COUNT
+    KID_ALL = -2, KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
+    KID_RESIDUAL, KID_GS, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_EXTRAP,
+    KID_RHS, KID_MG, KID_COUNT
 };
 const char* kernel_name(int kid);
 int kernel_id(const char* name);
 
 struct Probe {
-    int target = KID_NONE;
+    int target = KID_NONE;    // one kernel family, or KID_ALL: every family, each sampled on its own
     int n = 0;
-    int every = 1;            // record every `every`-th launch of the target
-    long long seen = 0;       // launches of the target since the probe was enabled
+    int every = 1;            // record every `every`-th launch of the target (of each family with KID_ALL)
+    long long seen[KID_COUNT] = {};   // launches per family since the probe was enabled
     static constexpr int kMax = 8192;
     hipEvent_t ev[2 * kMax];
+    int kid[kMax];              // family of recorded launch i
     double bytes[kMax];         // algorithmic HBM bytes of recorded launch i with every system active
     double* d_frac = nullptr;   // device [kMax]: share of the nodes whose systems launch i worked on
     bool created = false;
@@ -99,6 +103,19 @@ struct Dev {
     long long NT = 0;                // half-vector length (complex values)
     Terms terms{};
     Probe* probe = nullptr;
+};
+
+// Levels of the multigrid inner solve below the fine one (APFC_INNER_MG): level l + 1 of the V-cycle is
+// lev[l] (its own Sys and tile tables, 16-row tiles) with its buffers in the storage precision.
+constexpr int kMgMaxLevels = 16;
+constexpr int kMgCoarseMax = 8192;   // nodes of a system on the coarsest level (solved in LDS)
+struct MgLevels {
+    int n = 0;
+    Dev lev[kMgMaxLevels];
+    void *x[kMgMaxLevels] = {}, *b[kMgMaxLevels] = {}, *r[kMgMaxLevels] = {}, *d0[kMgMaxLevels] = {},
+         *d1[kMgMaxLevels] = {};
+    int nu = 2;             // Chebyshev smoothing iterations before and after the coarse correction
+    int coarse_its = 24;    // Chebyshev iterations on the coarsest level
 };
 
 // Krylov bookkeeping on the device (all [S]-indexed, see api.hip).
@@ -200,6 +217,15 @@ void launch_solve_y(const Dev& d, const Krylov& kr, hipStream_t st);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part,
                        int iters, hipStream_t st);
+// One multigrid V-cycle x = V(b) for L on every system (kernels_mg.hip); fine-level work buffers r, d0, d1.
+template <typename T>
+void launch_mg_vcycle(const Dev& fine, const MgLevels& mg, const cx<T>* b, cx<T>* x, cx<T>* r, cx<T>* d0, cx<T>* d1,
+                      const int* mask, hipStream_t st);
+// The block preconditioner with the multigrid L solves: step 1 by mass_iters Chebyshev iterations, steps 2
+// and 3 by one V-cycle each, step 4.
+template <typename T>
+void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r,
+                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, const int* mask, hipStream_t st);
 void launch_energy_parts(const Dev& d, const zd* eta, const zd* zeta, double* part, hipStream_t st);
 void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* const* grad_tab, double* part,
                         hipStream_t st);

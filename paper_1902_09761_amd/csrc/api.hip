@@ -133,6 +133,15 @@ struct apfc_ctx {
     int max_tiles = 0;
     double dt = -1.0;
     bool mixed = false;
+    // multigrid inner solve (APFC_INNER_MG): the levels below the fine one, each with its own system and
+    // tile tables and five work vectors (x, b, r, d0, d1) in the preconditioner precision
+    int mg_n = 0;
+    std::vector<Sys> mg_sys[kMgMaxLevels];
+    std::vector<Tile> mg_tiles[kMgMaxLevels];
+    long long mg_NT[kMgMaxLevels] = {};
+    Sys* d_mg_sys[kMgMaxLevels] = {};
+    Tile* d_mg_tiles[kMgMaxLevels] = {};
+    void* mg_buf[kMgMaxLevels][5] = {};
 
     // workspace: ws is the memory the buffers below are carved from, either the caller's workspace
     // (ws_user, apfc_set_workspace) or, during and after apfc_step_noalloc, the static scratch
@@ -277,17 +286,100 @@ void cheb_table(Sys& y) {
     }
 }
 
+void sys_dt(Sys& y, double dt) {
+    y.inv_dt = 1.0 / dt;
+    y.isq_dt = 1.0 / std::sqrt(dt);
+    y.sq_kap = std::sqrt(y.kappa);
+    y.isq_kap = 1.0 / std::sqrt(y.kappa);
+    y.diagL = y.diagM * y.isq_dt + y.sq_kap * y.diagK;
+    cheb_bounds(y, y.thM, y.deM, y.thL, y.deL);
+    cheb_table(y);
+}
+
+// Multigrid smoother: Chebyshev-Jacobi iterations for the upper part [lam_max/alpha, lam_max] of the
+// spectrum of D^{-1} L (lam_max = thL + deL), in the L table (cb[1]) of a level that is not the
+// coarsest; the coarsest level keeps the whole-spectrum table of cheb_table.
+constexpr double kMgAlpha = 4.0;
+void mg_smoother_table(Sys& y) {
+    const double hi = y.thL + y.deL, lo = hi / kMgAlpha;
+    const double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo), sig = th / de;
+    double rho = 1.0 / sig;
+    y.cb[1][0][0] = 1.0 / (th * y.diagL);
+    y.cb[1][0][1] = 0.0;
+    for (int j = 1; j < kMaxCheb; ++j) {
+        const double rn = 1.0 / (2.0 * sig - rho);
+        y.cb[1][j][0] = rn * rho;
+        y.cb[1][j][1] = 2.0 * rn / (de * y.diagL);
+        rho = rn;
+    }
+}
+
 void set_dt_scalars(apfc_ctx& c, double dt) {
     for (auto& y : c.sys) {
-        y.inv_dt = 1.0 / dt;
-        y.isq_dt = 1.0 / std::sqrt(dt);
-        y.sq_kap = std::sqrt(y.kappa);
-        y.isq_kap = 1.0 / std::sqrt(y.kappa);
-        y.diagL = y.diagM * y.isq_dt + y.sq_kap * y.diagK;
-        cheb_bounds(y, y.thM, y.deM, y.thL, y.deL);
-        cheb_table(y);
+        sys_dt(y, dt);
+        if (c.mg_n > 0) mg_smoother_table(y);
     }
+    for (int l = 0; l < c.mg_n; ++l)
+        for (auto& y : c.mg_sys[l]) {
+            sys_dt(y, dt);
+            if (l + 1 < c.mg_n) mg_smoother_table(y);
+        }
     c.dt = dt;
+}
+
+// The multigrid levels (APFC_INNER_MG): coarsen all systems together while every direction of every
+// system is even and its half at least kMgCoarseMin nodes (16 in 2D, 8 in 3D); a coarse level is the
+// same periodic domain with twice the mesh size.  The coarsest level of each system must hold at most
+// kMgCoarseMax nodes (it is solved in LDS).
+int build_mg_levels(apfc_ctx& c) {
+    const int cmin = c.dim == 3 ? 8 : 16;
+    std::vector<Sys> prev = c.sys;
+    c.mg_n = 0;
+    for (;;) {
+        bool ok = c.mg_n + 1 < kMgMaxLevels;
+        for (const Sys& y : prev) {
+            const int n[3] = {y.nx, y.ny, y.nz};
+            for (int d = 0; d < y.dim; ++d) ok = ok && n[d] % 2 == 0 && n[d] / 2 >= cmin;
+        }
+        if (!ok) break;
+        const int l = c.mg_n;
+        c.mg_sys[l].clear();
+        c.mg_tiles[l].clear();
+        long long off = 0;
+        for (int si = 0; si < (int)prev.size(); ++si) {
+            Sys y = prev[si];
+            y.nx /= 2;
+            y.ny /= 2;
+            if (y.dim == 3) y.nz /= 2;
+            y.N = (long long)y.nx * y.ny * y.nz;
+            y.off = off;
+            off += y.N;
+            y.h *= 2.0;
+            y.w = std::pow(y.h, y.dim);
+            y.diagM = std::pow(2.0 * y.h / 3.0, y.dim);
+            y.diagK = y.dim * (2.0 / y.h) * std::pow(2.0 * y.h / 3.0, y.dim - 1);
+            y.tbeg = (int)c.mg_tiles[l].size();
+            if (y.dim == 3) {
+                for (int z0 = 0; z0 < y.nz; z0 += 4)
+                    for (int y0 = 0; y0 < y.ny; y0 += 4)
+                        for (int x0 = 0; x0 < y.nx; x0 += kTX) c.mg_tiles[l].push_back(Tile{si, x0, y0, z0});
+            } else {
+                for (int y0 = 0; y0 < y.ny; y0 += 16)
+                    for (int x0 = 0; x0 < y.nx; x0 += kTX) c.mg_tiles[l].push_back(Tile{si, x0, y0, 0});
+            }
+            y.tend = (int)c.mg_tiles[l].size();
+            c.mg_sys[l].push_back(y);
+        }
+        c.mg_NT[l] = off;
+        prev = c.mg_sys[l];
+        c.mg_n += 1;
+    }
+    for (const Sys& y : prev)
+        if (y.N > kMgCoarseMax)
+            return fail(APFC_ERR_INVALID, "APFC_INNER_MG: a system's coarsest multigrid level has " + std::to_string(y.N) +
+                                              " nodes, more than " + std::to_string(kMgCoarseMax) +
+                                              " (use mesh sizes that halve further)");
+    return APFC_OK;
 }
 
 int cheb_halo(const apfc_params& p) { return std::max(p.mass_iters - 1, p.diff_iters); }
@@ -306,6 +398,11 @@ void build_ctiles(apfc_ctx& c) {
 
 int upload_tables(apfc_ctx& c) {
     HIPCHK(hipMemcpy(c.d_sys, c.sys.data(), sizeof(Sys) * c.S, hipMemcpyHostToDevice));
+    for (int l = 0; l < c.mg_n; ++l) {
+        HIPCHK(hipMemcpy(c.d_mg_sys[l], c.mg_sys[l].data(), sizeof(Sys) * c.S, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c.d_mg_tiles[l], c.mg_tiles[l].data(), sizeof(Tile) * c.mg_tiles[l].size(),
+                         hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(c.d_tiles, c.tiles.data(), sizeof(Tile) * c.tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c.d_chunks, c.chunks.data(), sizeof(Chunk) * c.chunks.size(), hipMemcpyHostToDevice));
     if (!c.ctiles.empty())
@@ -387,6 +484,11 @@ size_t carve(apfc_ctx& c, char* base) {
     c.run_cyc_max = (int*)take(sizeof(int) * S);
     c.run_res_max = (double*)take(sizeof(double) * S);
     c.pub_dev = (int*)take(sizeof(int) * 8);
+    for (int l = 0; l < c.mg_n; ++l) {
+        c.d_mg_sys[l] = (Sys*)take(sizeof(Sys) * S);
+        c.d_mg_tiles[l] = (Tile*)take(sizeof(Tile) * c.mg_tiles[l].size());
+        for (int b = 0; b < 5; ++b) c.mg_buf[l][b] = take(zs * c.mg_NT[l]);
+    }
     return off + 256;
 }
 
@@ -443,7 +545,7 @@ int check_params(const apfc_params& p) {
     if (p.precision != APFC_FP64 && p.precision != APFC_MIXED) return fail(APFC_ERR_INVALID, "params.precision");
     if (p.mass_iters < 1 || p.mass_iters > kMaxCheb || p.diff_iters < 1 || p.diff_iters > kMaxCheb)
         return fail(APFC_ERR_INVALID, "params: inner iterations must be in [1,64]");
-    if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB)
+    if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB && p.inner_kind != APFC_INNER_MG)
         return fail(APFC_ERR_INVALID, "params.inner_kind");
     if (p.x0_order < 0 || p.x0_order > 3) return fail(APFC_ERR_INVALID, "params.x0_order must be in [0,3]");
     return APFC_OK;
@@ -522,7 +624,17 @@ int apfc_lattice_default(int kind, apfc_lattice* L) {
             for (int c = 0; c < 3; ++c) L->k[j][c] = r * v[j][c];
         return APFC_OK;
     }
-    return fail(APFC_ERR_INVALID, "apfc_lattice_default: kind must be APFC_TRI2D or APFC_BCC3D");
+    if (kind == APFC_FCC3D) {
+        // the first two shells of the fcc reciprocal lattice: <111> (|k| = 1, one of each +- pair, summing
+        // to zero) and <200> (|k| = 2/sqrt 3)
+        const double r = 1.0 / std::sqrt(3.0);
+        const double v[7][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}};
+        L->J = 7;
+        for (int j = 0; j < 7; ++j)
+            for (int c = 0; c < 3; ++c) L->k[j][c] = r * v[j][c];
+        return APFC_OK;
+    }
+    return fail(APFC_ERR_INVALID, "apfc_lattice_default: kind must be APFC_TRI2D, APFC_BCC3D or APFC_FCC3D");
 }
 
 int apfc_uniform_amplitude(const apfc_lattice* L, const apfc_params* p, double* phi) {
@@ -536,6 +648,94 @@ int apfc_uniform_amplitude(const apfc_lattice* L, const apfc_params* p, double* 
     const double disc = 9.0 * c3 * c3 - 32.0 * c2 * c4;
     *phi = (disc < 0.0 || !(c4 > 0.0)) ? 0.0 : (-3.0 * c3 + std::sqrt(disc)) / (8.0 * c4);
     if (*phi < 0.0) *phi = 0.0;
+    return APFC_OK;
+}
+
+int apfc_equilibrium_amplitudes(const apfc_lattice* L, const apfc_params* p, double* phi) {
+    if (!L || !p || !phi) return fail(APFC_ERR_INVALID, "NULL argument");
+    double phi0 = 0.0;
+    if (int rc = apfc_uniform_amplitude(L, p, &phi0); rc) return rc;
+    Terms T;
+    if (int rc = build_terms(*L, T); rc) return rc;
+    const int J = L->J;
+    // shells of equal |k_j|^2
+    int shell[kMaxJ], ns = 0;
+    double s2[kMaxJ];
+    for (int j = 0; j < J; ++j) {
+        const double k2 = L->k[j][0] * L->k[j][0] + L->k[j][1] * L->k[j][1] + L->k[j][2] * L->k[j][2];
+        int s = 0;
+        while (s < ns && std::fabs(s2[s] - k2) > 1e-9 * k2) ++s;
+        if (s == ns) s2[ns++] = k2;
+        shell[j] = s;
+    }
+    for (int j = 0; j < J; ++j) phi[j] = phi0;
+    if (ns == 1 || phi0 == 0.0) return APFC_OK;
+    // d f / d phi_s for real amplitudes eta_j = x[shell(j)]: pair part and the resonant products of T
+    auto grad = [&](const double* x, double* g) {
+        double e[kMaxJ], A = 0.0;
+        for (int j = 0; j < J; ++j) {
+            e[j] = x[shell[j]];
+            A += 2.0 * e[j] * e[j];
+        }
+        double gj[kMaxJ];
+        for (int j = 0; j < J; ++j)
+            gj[j] = p->a1 / p->a0 * 4.0 * e[j] + p->a2 / p->a0 * (8.0 * A * e[j] - 8.0 * e[j] * e[j] * e[j]);
+        for (int t = 0; t < T.n; ++t) {
+            const double c = T.order[t] == 3 ? -2.0 * p->a3 / p->a0 : 8.0 * p->a2 / p->a0;
+            for (int q = 0; q < T.order[t]; ++q) {
+                double prod = 2.0 * c;
+                for (int r = 0; r < T.order[t]; ++r)
+                    if (r != q) prod *= e[T.idx[t][r]];
+                gj[T.idx[t][q]] += prod;
+            }
+        }
+        for (int s = 0; s < ns; ++s) g[s] = 0.0;
+        for (int j = 0; j < J; ++j) g[shell[j]] += gj[j];
+    };
+    // Newton's method from the single-shell root, Jacobian by central differences of the gradient
+    double x[kMaxJ], g[kMaxJ];
+    for (int s = 0; s < ns; ++s) x[s] = phi0;
+    for (int it = 0; it < 100; ++it) {
+        grad(x, g);
+        double gn = 0.0;
+        for (int s = 0; s < ns; ++s) gn = std::max(gn, std::fabs(g[s]));
+        if (gn < 1e-16) break;
+        double Jm[kMaxJ][kMaxJ + 1];
+        for (int c = 0; c < ns; ++c) {
+            double xp[kMaxJ], xm[kMaxJ], gp[kMaxJ], gm[kMaxJ];
+            const double hstep = 1e-6 * phi0;
+            for (int s = 0; s < ns; ++s) xp[s] = xm[s] = x[s];
+            xp[c] += hstep;
+            xm[c] -= hstep;
+            grad(xp, gp);
+            grad(xm, gm);
+            for (int r = 0; r < ns; ++r) Jm[r][c] = (gp[r] - gm[r]) / (2.0 * hstep);
+        }
+        for (int r = 0; r < ns; ++r) Jm[r][ns] = -g[r];
+        // Gaussian elimination with partial pivoting
+        for (int c = 0; c < ns; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < ns; ++r)
+                if (std::fabs(Jm[r][c]) > std::fabs(Jm[piv][c])) piv = r;
+            for (int q = 0; q <= ns; ++q) std::swap(Jm[c][q], Jm[piv][q]);
+            if (Jm[c][c] == 0.0) return fail(APFC_ERR_INVALID, "apfc_equilibrium_amplitudes: singular Newton system");
+            for (int r = c + 1; r < ns; ++r) {
+                const double f = Jm[r][c] / Jm[c][c];
+                for (int q = c; q <= ns; ++q) Jm[r][q] -= f * Jm[c][q];
+            }
+        }
+        double dx[kMaxJ];
+        for (int r = ns - 1; r >= 0; --r) {
+            double v = Jm[r][ns];
+            for (int q = r + 1; q < ns; ++q) v -= Jm[r][q] * dx[q];
+            dx[r] = v / Jm[r][r];
+        }
+        for (int s = 0; s < ns; ++s) x[s] += dx[s];
+    }
+    for (int s = 0; s < ns; ++s)
+        if (!(x[s] > 0.0) || !std::isfinite(x[s]))
+            return fail(APFC_ERR_INVALID, "apfc_equilibrium_amplitudes: no crystal with all amplitudes positive");
+    for (int j = 0; j < J; ++j) phi[j] = x[shell[j]];
     return APFC_OK;
 }
 
@@ -628,6 +828,12 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
         y.cbeg = (int)c->chunks.size();
         for (long long e0 = 0; e0 < 2 * y.N; e0 += kChunk) c->chunks.push_back(Chunk{s, (int)e0});
         y.cend = (int)c->chunks.size();
+    }
+    if (params[0].inner_kind == APFC_INNER_MG) {
+        if (int rc = build_mg_levels(*c); rc) {
+            delete c;
+            return rc;
+        }
     }
     std::vector<Tile> t4;
     build_tiles(*c, 4, t4);
@@ -775,11 +981,37 @@ int* pub_target(apfc_ctx* c) { return c->noalloc ? c->pub_dev : c->d_pub; }
 // Chebyshev (3D), or the paper's Jacobi-PCG.
 // With vscale set (fused 2D Chebyshev only), the input is vscale[sys] * rv instead of v and is also
 // stored to vout.
+// The multigrid levels' device view (tables and buffers of the attached workspace).
+MgLevels mg_levels(apfc_ctx* c, const Dev& fine) {
+    MgLevels m;
+    m.n = c->mg_n;
+    m.nu = c->solver.diff_iters;
+    m.coarse_its = 24;
+    for (int l = 0; l < c->mg_n; ++l) {
+        Dev d = fine;
+        d.sys = c->d_mg_sys[l];
+        d.tiles = c->d_mg_tiles[l];
+        d.ntiles = (int)c->mg_tiles[l].size();
+        d.TY = 16;
+        d.NT = c->mg_NT[l];
+        m.lev[l] = d;
+        m.x[l] = c->mg_buf[l][0];
+        m.b[l] = c->mg_buf[l][1];
+        m.r[l] = c->mg_buf[l][2];
+        m.d0[l] = c->mg_buf[l][3];
+        m.d1[l] = c->mg_buf[l][4];
+    }
+    return m;
+}
+
 template <typename T>
 void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mask, hipStream_t st,
              const double* vscale = nullptr, const cx<T>* rv = nullptr, cx<T>* vout = nullptr) {
     cx<T>** pc = (cx<T>**)c->pc;
-    if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
+    if (c->solver.inner_kind == APFC_INNER_MG)
+        launch_precond_mg<T>(d, mg_levels(c, d), v, z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5],
+                             c->solver.mass_iters, mask, st);
+    else if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
                                pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, vscale, rv, vout, mask,
                                st);
@@ -1318,7 +1550,7 @@ int apfc_set_tiles(apfc_ctx* c, int tile_rows, int precond_region) {
     if (int rc = need_ws(c); rc) return rc;
     if (tile_rows != 4 && tile_rows != 8 && tile_rows != 16 && tile_rows != 32)
         return fail(APFC_ERR_INVALID, "tile_rows must be 4, 8, 16 or 32");
-    if (precond_region < 0 || precond_region >= kChebShapes) return fail(APFC_ERR_INVALID, "precond_region must be in 0..4");
+    if (precond_region < 0 || precond_region >= kChebShapes) return fail(APFC_ERR_INVALID, "precond_region must be in 0..5");
     c->TY = tile_rows;
     build_tiles(*c, c->TY, c->tiles);
     if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2) {
@@ -1354,19 +1586,21 @@ int apfc_probe_enable(apfc_ctx* c, const char* name, int every) {
     }
     c->probe.target = kid;
     c->probe.every = every;
-    c->probe.seen = 0;
+    for (auto& v : c->probe.seen) v = 0;
     c->probe.n = 0;
     return APFC_OK;
 }
 
-int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_per_launch) {
-    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+namespace {
+// Sums over the recorded launches of family kid (KID_ALL: every family) in which some system worked.
+int probe_sum(apfc_ctx* c, int kid, int* launches, double* total_ms, double* bytes_per_launch, long long* seen) {
     double tot = 0.0, bytes = 0.0;
     const int n = c->probe.n;
     int used = 0;
     std::vector<double> frac(n);
     if (n > 0) HIPCHK(hipMemcpy(frac.data(), c->probe.d_frac, sizeof(double) * n, hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i) {
+        if (kid != KID_ALL && c->probe.kid[i] != kid) continue;
         HIPCHK(hipEventSynchronize(c->probe.ev[2 * i + 1]));
         if (frac[i] <= 0.0) continue;   // every system masked: an empty launch, not a sample of the kernel
         float ms = 0.f;
@@ -1378,8 +1612,29 @@ int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_
     if (launches) *launches = used;
     if (total_ms) *total_ms = tot;
     if (bytes_per_launch) *bytes_per_launch = used > 0 ? bytes / used : 0.0;
+    if (seen) {
+        *seen = 0;
+        for (int k = 0; k < KID_COUNT; ++k)
+            if (kid == KID_ALL || k == kid) *seen += c->probe.seen[k];
+    }
+    return APFC_OK;
+}
+}  // namespace
+
+int apfc_probe_read(apfc_ctx* c, int* launches, double* total_ms, double* bytes_per_launch) {
+    if (!c) return fail(APFC_ERR_INVALID, "ctx is NULL");
+    const int kid = c->probe.target == KID_NONE ? KID_ALL : c->probe.target;
+    if (int rc = probe_sum(c, kid, launches, total_ms, bytes_per_launch, nullptr); rc) return rc;
     c->probe.n = 0;
     return APFC_OK;
+}
+
+int apfc_probe_read_kernel(apfc_ctx* c, const char* name, int* launches, double* total_ms, double* bytes_per_launch,
+                           long long* issued) {
+    if (!c || !name) return fail(APFC_ERR_INVALID, "NULL argument");
+    const int kid = kernel_id(name);
+    if (kid == KID_NONE || kid == KID_ALL) return fail(APFC_ERR_INVALID, std::string("unknown kernel name: ") + name);
+    return probe_sum(c, kid, launches, total_ms, bytes_per_launch, issued);
 }
 
 int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {

@@ -1,380 +1,11 @@
-// HIP kernels of the APFC time step for gfx950 (CDNA4, wave64).
-//
-// Every operator here is a constant-coefficient tensor-product stencil of the Q1 element on a
-// periodic uniform mesh, built from the 1D weights
-//     mass m = h/6 [1 4 1],  stiffness k = 1/h [-1 2 -1],  derivative d = 1/2 [-1 0 1]
-// (row = test function, column = trial function), so that
-//     M = m (x) m (x) m,   K = sum_d k_d (x) m (x) m,   T_j = 2 sum_d k_{j,d} d_d (x) m (x) m,
-//     G_j = -K + i T_j                                  (Sec. II.A, Eq. (8)-(11)).
-// The stencils are evaluated separably (x pass, then y, then z) from neighbour loads; all
-// kernels stream HBM with 64-wide rows per wave.  Reductions are deterministic: one partial
-// per workgroup, summed in a fixed order.
-#include "apfc_internal.h"
-
-#include <hip/hip_ext.h>
-#include <type_traits>
-#include <utility>
+// HIP kernels of the APFC time step for gfx950 (CDNA4, wave64): state conversion, right-hand side and
+// nodal nonlinearity, Jacobi-PCG and per-iteration Chebyshev preconditioner stages, Krylov chunk kernels,
+// Gram-Schmidt reduction, energy, rotation and adjoint pieces, and their launchers.  The operator apply
+// lives in kernels_apply.hip, the fused 2D Chebyshev preconditioner in kernels_cheb2d.hip; the shared
+// device helpers in kernels_common.h.
+#include "kernels_common.h"
 
 namespace apfc {
-
-// ------------------------------------------------------------------------------------------
-// complex helpers
-// ------------------------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename R>
-__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename R>
-__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.x, s * a.y}; }
-template <typename R>
-__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-template <typename R>
-__device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.x, -a.y}; }
-template <typename R>
-__device__ __forceinline__ R abs2(cx<R> a) { return a.x * a.x + a.y * a.y; }
-// conj(a) * b
-template <typename R>
-__device__ __forceinline__ cx<R> cdot(cx<R> a, cx<R> b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
-// i * a
-template <typename R>
-__device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.y, a.x}; }
-
-template <typename R, typename S>
-__device__ __forceinline__ cx<R> ld(const cx<S>* p, long long i) {
-    const cx<S> v = p[i];
-    return {R(v.x), R(v.y)};
-}
-template <typename S, typename R>
-__device__ __forceinline__ void stv(cx<S>* p, long long i, cx<R> v) {
-    p[i] = cx<S>{S(v.x), S(v.y)};
-}
-
-// ------------------------------------------------------------------------------------------
-// reductions
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Sum NV per-thread values over the workgroup; thread 0 receives the totals.  lds >= 4*NV.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const double t = wave_sum(v[i]);
-        if (lane == 0) lds[wv * NV + i] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = ((lds[i] + lds[NV + i]) + lds[2 * NV + i]) + lds[3 * NV + i];
-    }
-    __syncthreads();
-}
-
-// The same fixed-order sum of part[slot*P + t], t in [beg, end), in every workgroup.
-template <int NS>
-__device__ __forceinline__ void sum_partials(const double* part, long long P, const int (&slot)[NS], int beg,
-                                             int end, double (&out)[NS], double* lds) {
-    if (threadIdx.x < 64) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            double a = 0.0;
-            for (int t = beg + (int)threadIdx.x; t < end; t += 64) a += part[slot[k] * P + t];
-            a = wave_sum(a);
-            if (threadIdx.x == 0) lds[k] = a;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NS; ++k) out[k] = lds[k];
-    __syncthreads();
-}
-
-// The workgroups of one system write their partials, then count themselves on the system's ticket; the
-// last one to arrive (device-wide) sees every partial and runs the per-system reduction in the fixed
-// order a kernel of its own would, and re-arms the ticket.  No workgroup waits for another.  The
-// device-scope release fence this needs writes back the L2, so it is used only where few workgroups
-// take part (the second Gram-Schmidt pass, which runs only for systems that need it).
-__device__ __forceinline__ bool last_of_system(int* ticket, int si, int n, int* flag_lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();                      // this workgroup's partials before its ticket
-        const int t = atomicAdd(&ticket[si], 1);
-        const int last = t == n - 1;
-        if (last) ticket[si] = 0;
-        *flag_lds = last;
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last) __threadfence();                // the other workgroups' partials after their tickets
-    return last;
-}
-
-
-// ------------------------------------------------------------------------------------------
-// geometry: periodic neighbours of node (x, y, z)
-// ------------------------------------------------------------------------------------------
-template <int DIM>
-struct Nbr {
-    int xs[3];
-    long long rb[DIM == 3 ? 3 : 1][3];   // [dz][dy] local node index of (0, y+dy, z+dz)
-};
-
-template <int DIM>
-__device__ __forceinline__ void make_nbr(const Sys& s, int x, int y, int z, Nbr<DIM>& n) {
-    n.xs[0] = x == 0 ? s.nx - 1 : x - 1;
-    n.xs[1] = x;
-    n.xs[2] = x == s.nx - 1 ? 0 : x + 1;
-    const int ys[3] = {y == 0 ? s.ny - 1 : y - 1, y, y == s.ny - 1 ? 0 : y + 1};
-    if constexpr (DIM == 2) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) n.rb[0][b] = (long long)ys[b] * s.nx;
-    } else {
-        const int zs[3] = {z == 0 ? s.nz - 1 : z - 1, z, z == s.nz - 1 ? 0 : z + 1};
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) n.rb[c][b] = ((long long)zs[c] * s.ny + ys[b]) * s.nx;
-    }
-}
-
-template <int DIM>
-__device__ __forceinline__ long long nb_index(const Nbr<DIM>& n, int a, int b, int c) {
-    if constexpr (DIM == 2)
-        return n.rb[0][b] + n.xs[a];
-    else
-        return n.rb[c][b] + n.xs[a];
-}
-
-// Separable evaluation of (M u, K u, T_j u) at one node; f(a, b, c) returns u at the
-// neighbour (x + a - 1, y + b - 1, z + c - 1).
-template <int DIM, bool WK, bool WT, typename R, typename F>
-__device__ __forceinline__ void stencil(const F& f, R h, R k0, R k1, R k2, cx<R>& Mu, cx<R>& Ku, cx<R>& Tu) {
-    const R m0 = h * R(1.0 / 6.0), m1 = h * R(4.0 / 6.0), ih = R(1) / h, half = R(0.5);
-    auto mass1 = [&](cx<R> l, cx<R> c, cx<R> r) { return m0 * (l + r) + m1 * c; };
-    auto stiff1 = [&](cx<R> l, cx<R> c, cx<R> r) { return ih * ((c + c) - (l + r)); };
-    auto der1 = [&](cx<R> l, cx<R> r) { return half * (r - l); };
-    if constexpr (DIM == 2) {
-        cx<R> mx[3], kx[3], dx[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const cx<R> l = f(0, b, 1), c = f(1, b, 1), r = f(2, b, 1);
-            mx[b] = mass1(l, c, r);
-            if (WK) kx[b] = stiff1(l, c, r);
-            if (WT) dx[b] = der1(l, r);
-        }
-        Mu = mass1(mx[0], mx[1], mx[2]);
-        if (WK) Ku = mass1(kx[0], kx[1], kx[2]) + stiff1(mx[0], mx[1], mx[2]);
-        if (WT) Tu = R(2) * (k0 * mass1(dx[0], dx[1], dx[2]) + k1 * der1(mx[0], mx[2]));
-    } else {
-        cx<R> mxy[3], kxy[3], dxm[3], dym[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            cx<R> mx[3], kx[3], dx[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const cx<R> l = f(0, b, c), ce = f(1, b, c), r = f(2, b, c);
-                mx[b] = mass1(l, ce, r);
-                if (WK) kx[b] = stiff1(l, ce, r);
-                if (WT) dx[b] = der1(l, r);
-            }
-            mxy[c] = mass1(mx[0], mx[1], mx[2]);
-            if (WK) kxy[c] = mass1(kx[0], kx[1], kx[2]) + stiff1(mx[0], mx[1], mx[2]);
-            if (WT) {
-                dxm[c] = mass1(dx[0], dx[1], dx[2]);
-                dym[c] = der1(mx[0], mx[2]);
-            }
-        }
-        Mu = mass1(mxy[0], mxy[1], mxy[2]);
-        if (WK) Ku = mass1(kxy[0], kxy[1], kxy[2]) + stiff1(mxy[0], mxy[1], mxy[2]);
-        if (WT)
-            Tu = R(2) * (k0 * mass1(dxm[0], dxm[1], dxm[2]) + k1 * mass1(dym[0], dym[1], dym[2]) +
-                         k2 * der1(mxy[0], mxy[2]));
-    }
-}
-
-// G u = -K u + i T u
-template <typename R>
-__device__ __forceinline__ cx<R> gop(cx<R> Ku, cx<R> Tu) {
-    return {-Ku.x - Tu.y, -Ku.y + Tu.x};
-}
-
-// ------------------------------------------------------------------------------------------
-// 3D z-marching.  The x and y passes of the separable stencil at one (x, y) column of one plane are
-// needed by the three output planes z-1, z, z+1; a thread that walks consecutive planes of its
-// column takes them once per plane and keeps the last three in registers, so each input plane is
-// used once per field (9 values instead of 27 per node).  The arithmetic is that of stencil().
-// zmarch loads the 9 values of a plane from global memory (the operator apply and residual, whose
-// basis-vector streams dominate); zmarch_lds stages the planes of the workgroup in LDS (the Chebyshev
-// iterations, whose stencil loads dominate).
-// ------------------------------------------------------------------------------------------
-template <typename R>
-struct Plane {
-    cx<R> m, k, dx, dy, c;   // over x, y: (m m) u, (k m + m k) u, (d m) u, (m d) u; u at (x, y)
-};
-
-template <bool WK, bool WT, typename R, typename F>
-__device__ __forceinline__ Plane<R> plane_pass(const F& f, long long base, const int (&xs)[3],
-                                               const long long (&rs)[3], R m0, R m1, R ih) {
-    const R half = R(0.5);
-    cx<R> mx[3], kx[3], dx[3];
-    Plane<R> p{};
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const cx<R> l = f(base + rs[b] + xs[0]), c = f(base + rs[b] + xs[1]), r = f(base + rs[b] + xs[2]);
-        mx[b] = m0 * (l + r) + m1 * c;
-        if (WK) kx[b] = ih * ((c + c) - (l + r));
-        if (WT) dx[b] = half * (r - l);
-        if (b == 1) p.c = c;
-    }
-    p.m = m0 * (mx[0] + mx[2]) + m1 * mx[1];
-    if (WK) p.k = (m0 * (kx[0] + kx[2]) + m1 * kx[1]) + ih * ((mx[1] + mx[1]) - (mx[0] + mx[2]));
-    if (WT) {
-        p.dx = m0 * (dx[0] + dx[2]) + m1 * dx[1];
-        p.dy = half * (mx[2] - mx[0]);
-    }
-    return p;
-}
-
-// z pass: (M u, K u, T_j u) at the middle plane from the plane passes of planes z-1, z, z+1.
-template <bool WK, bool WT, typename R>
-__device__ __forceinline__ void zcombine(const Plane<R>& a, const Plane<R>& b, const Plane<R>& c, R m0, R m1, R ih,
-                                         R k0, R k1, R k2, cx<R>& Mu, cx<R>& Ku, cx<R>& Tu) {
-    Mu = m0 * (a.m + c.m) + m1 * b.m;
-    if (WK) Ku = (m0 * (a.k + c.k) + m1 * b.k) + ih * ((b.m + b.m) - (a.m + c.m));
-    if (WT)
-        Tu = R(2) * (k0 * (m0 * (a.dx + c.dx) + m1 * b.dx) + k1 * (m0 * (a.dy + c.dy) + m1 * b.dy) +
-                     k2 * (R(0.5) * (c.m - a.m)));
-}
-
-// Walks planes z0-1 .. z0+RR of column (xc, yc) (periodic), load(f, i) returning node i of field f;
-// calls emit(z, P) for the output planes z = z0 .. z0+RR-1 (which may pass nz on a ragged brick),
-// P[f][0..2] holding the plane passes of planes z-1, z, z+1.
-template <int RR, int NF, bool WK, bool WT, typename R, typename LOAD, typename EMIT>
-__device__ __forceinline__ void zmarch(const Sys& s, int xc, int yc, int z0, R m0, R m1, R ih, const LOAD& load,
-                                       const EMIT& emit) {
-    const int xs[3] = {xc == 0 ? s.nx - 1 : xc - 1, xc, xc == s.nx - 1 ? 0 : xc + 1};
-    const long long rs[3] = {(long long)(yc == 0 ? s.ny - 1 : yc - 1) * s.nx, (long long)yc * s.nx,
-                             (long long)(yc == s.ny - 1 ? 0 : yc + 1) * s.nx};
-    const long long plane = (long long)s.nx * s.ny;
-    Plane<R> P[NF][3];
-    int zz = z0 == 0 ? s.nz - 1 : z0 - 1;
-#pragma unroll
-    for (int a = 0; a < RR + 2; ++a) {
-        const long long base = zz * plane;
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-            P[f][2] = plane_pass<WK, WT, R>([&](long long i) { return load(f, i); }, base, xs, rs, m0, m1, ih);
-        if (a >= 2) emit(z0 + a - 2, P);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            P[f][0] = P[f][1];
-            P[f][1] = P[f][2];
-        }
-        zz = zz + 1 == s.nz ? 0 : zz + 1;
-    }
-}
-
-// 3D plane march with the planes of the workgroup's 64 x 4 columns plus a one-node halo (66 x 6) staged in
-// LDS: the workgroup loads a plane with two coalesced loads per thread and field, the next plane while
-// the current one is in use, and every thread takes its x/y pass from LDS (9 LDS reads instead of 9
-// global loads).  buf: [2][NF][66 * 6] values in the storage type S.
-constexpr int kPX = 66, kPY = 6, kPP = kPX * kPY;
-
-template <bool WK, bool WT, typename R, typename S>
-__device__ __forceinline__ Plane<R> plane_pass_lds(const cx<S>* b, int lane, int ty, R m0, R m1, R ih) {
-    const R half = R(0.5);
-    cx<R> mx[3], kx[3], dx[3];
-    Plane<R> p{};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const cx<S>* row = b + (ty + q) * kPX + lane;
-        const cx<R> l{R(row[0].x), R(row[0].y)}, c{R(row[1].x), R(row[1].y)}, r{R(row[2].x), R(row[2].y)};
-        mx[q] = m0 * (l + r) + m1 * c;
-        if (WK) kx[q] = ih * ((c + c) - (l + r));
-        if (WT) dx[q] = half * (r - l);
-        if (q == 1) p.c = c;
-    }
-    p.m = m0 * (mx[0] + mx[2]) + m1 * mx[1];
-    if (WK) p.k = (m0 * (kx[0] + kx[2]) + m1 * kx[1]) + ih * ((mx[1] + mx[1]) - (mx[0] + mx[2]));
-    if (WT) {
-        p.dx = m0 * (dx[0] + dx[2]) + m1 * dx[1];
-        p.dy = half * (mx[2] - mx[0]);
-    }
-    return p;
-}
-
-template <int RR, int NF, bool WK, bool WT, typename R, typename S, typename LOADG, typename EMIT>
-__device__ __forceinline__ void zmarch_lds(const Sys& s, const Tile& tile, int lane, int ty, cx<S> (*buf)[NF][kPP],
-                                           R m0, R m1, R ih, const LOADG& loadg, const EMIT& emit) {
-    const int e0 = (int)threadIdx.x, e1 = (int)threadIdx.x + kBlock;
-    auto goff = [&](int e) {
-        int gx = (tile.x0 - 1 + e % kPX) % s.nx, gy = (tile.y0 - 1 + e / kPX) % s.ny;
-        gx = gx < 0 ? gx + s.nx : gx;
-        gy = gy < 0 ? gy + s.ny : gy;
-        return (long long)gy * s.nx + gx;
-    };
-    const long long o0 = goff(e0), o1 = e1 < kPP ? goff(e1) : 0;
-    const long long plane = (long long)s.nx * s.ny;
-    auto fetch = [&](int b, long long base) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            buf[b][f][e0] = loadg(f, base + o0);
-            if (e1 < kPP) buf[b][f][e1] = loadg(f, base + o1);
-        }
-    };
-    Plane<R> P[NF][3];
-    int zz = tile.z == 0 ? s.nz - 1 : tile.z - 1;
-    fetch(0, zz * plane);
-#pragma unroll
-    for (int a = 0; a < RR + 2; ++a) {
-        __syncthreads();
-        const int zn = zz + 1 == s.nz ? 0 : zz + 1;
-        if (a + 1 < RR + 2) fetch((a + 1) & 1, zn * plane);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) P[f][2] = plane_pass_lds<WK, WT, R>(buf[a & 1][f], lane, ty, m0, m1, ih);
-        if (a >= 2) emit(tile.z + a - 2, P);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            P[f][0] = P[f][1];
-            P[f][1] = P[f][2];
-        }
-        zz = zn;
-    }
-}
-
-// A_j applied at the middle plane of P (field 0: zeta part, field 1: eta part), as apply_A.
-template <typename PL>
-__device__ __forceinline__ void apply_A_planes(const Sys& s, const PL& P, double m0, double m1, double ih, double dn,
-                                               zd& y1, zd& y2) {
-    zd Mz, Kz, Tz, Me, Ke, Te;
-    zcombine<true, true, double>(P[0][0], P[0][1], P[0][2], m0, m1, ih, s.kv[0], s.kv[1], s.kv[2], Mz, Kz, Tz);
-    zcombine<true, true, double>(P[1][0], P[1][1], P[1][2], m0, m1, ih, s.kv[0], s.kv[1], s.kv[2], Me, Ke, Te);
-    y1 = Mz - gop(Ke, Te);
-    y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dn) * P[1][1].c;
-}
-
-// ------------------------------------------------------------------------------------------
-// tile iteration.  2D: a workgroup covers x in [x0, x0+64) and rows y0 + ty + 4 r (r < TY/4).
-// 3D: a brick x in [x0, x0+64), y = y0 + ty (ty < 4), planes z0 + r (r < TY/4), so a thread walks
-// consecutive planes of one (x, y) column (the order the z-marching stencil kernels rely on).
-// ------------------------------------------------------------------------------------------
-#define TILE_PROLOGUE()                                        \
-    const Tile tile = tiles[blockIdx.x];                       \
-    if (mask && !mask[tile.sys]) return;                       \
-    const Sys s = sys[tile.sys];                               \
-    const int x = tile.x0 + (int)(threadIdx.x & 63);           \
-    const int ty = (int)(threadIdx.x >> 6);
-
-#define FOR_ROWS(TY)                                                                  \
-    _Pragma("unroll") for (int rr_ = 0; rr_ < (TY) / 4; ++rr_)                        \
-        if (const int y = DIM == 3 ? tile.y0 + ty : tile.y0 + ty + 4 * rr_,             \
-                      pz = DIM == 3 ? tile.z + rr_ : 0;                                 \
-            x < s.nx && y < s.ny && pz < s.nz)
 
 // ------------------------------------------------------------------------------------------
 // state <-> batched vector
@@ -645,259 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_rhs_nonlinear(const Sys* sys, const 
 }
 
 // ------------------------------------------------------------------------------------------
-// block operator A_j (Eq. (11)): y1 = M zeta - G eta,  y2 = kappa G zeta + M eta/dt + kappa w d eta
-// ------------------------------------------------------------------------------------------
-template <int DIM, typename S>
-__device__ __forceinline__ void apply_A(const Sys& s, const Nbr<DIM>& n, const cx<S>* zz, const cx<S>* ze, double dn,
-                                        zd& y1, zd& y2) {
-    zd Mz, Kz, Tz, Me, Ke, Te;
-    stencil<DIM, true, true, double>(
-        [&](int a, int b, int c) { return ld<double>(zz, s.off + nb_index<DIM>(n, a, b, c)); }, s.h, s.kv[0],
-        s.kv[1], s.kv[2], Mz, Kz, Tz);
-    stencil<DIM, true, true, double>(
-        [&](int a, int b, int c) { return ld<double>(ze, s.off + nb_index<DIM>(n, a, b, c)); }, s.h, s.kv[0],
-        s.kv[1], s.kv[2], Me, Ke, Te);
-    const zd ec = ld<double>(ze, s.off + nb_index<DIM>(n, 1, 1, 1));
-    y1 = Mz - gop(Ke, Te);
-    y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dn) * ec;
-}
-
-template <int DIM, int TY, typename T>
-__global__ __launch_bounds__(kBlock) void k_apply(const Sys* sys, const Tile* tiles, const int* mask,
-                                                 const cx<T>* Z, const double* dnode, zd* W, long long NT) {
-    TILE_PROLOGUE();
-    FOR_ROWS(TY) {
-        Nbr<DIM> n;
-        make_nbr<DIM>(s, x, y, pz, n);
-        const long long il = nb_index<DIM>(n, 1, 1, 1);
-        zd y1, y2;
-        apply_A<DIM, T>(s, n, Z, Z + NT, dnode[s.doff + il], y1, y2);
-        W[s.off + il] = y1;
-        W[NT + s.off + il] = y2;
-    }
-}
-
-// 2D column march: a thread walks rows y0-1 .. y0+RR of column x (periodic); the x pass (mass,
-// stiffness, derivative sums over x-1, x, x+1) of every row is computed once and kept for the next
-// two rows, so each input row is loaded once per field (3 loads instead of 9).  load(f, i) returns node i
-// of the system's zeta (f = 0) or eta (f = 1) part of u; emit(il, y1, y2) receives A_j u at node
-// il = (x, y) for y = y0 .. y0+RR-1 inside the mesh.  CHECK = false: the caller knows that every row and
-// column of the march lies inside the mesh, so the march has no branch and the compiler can issue the
-// loads of later rows while earlier rows are computed.
-template <int RR, bool CHECK, typename LOAD, typename EMIT>
-__device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LOAD& load, const double* dnode,
-                                           const EMIT& emit) {
-    const int xc = x < s.nx ? x : s.nx - 1;                  // clamp for loads of ragged tiles
-    const int xm = xc == 0 ? s.nx - 1 : xc - 1, xp = xc == s.nx - 1 ? 0 : xc + 1;
-    const double h = s.h, m0 = h / 6.0, m1 = 4.0 * h / 6.0, ih = 1.0 / h;
-    const double kx = s.kv[0], ky = s.kv[1];
-    zd mz[3], kz[3], dz[3], me[3], ke[3], de[3], ce[3];
-    // first row y0 - 1, periodic; y0 itself may lie past the mesh (rows of a tile taller than the mesh)
-    int row = y0 == 0 ? s.ny - 1 : (y0 - 1) % s.ny;
-#pragma unroll
-    for (int a = 0; a < RR + 2; ++a, row = row + 1 == s.ny ? 0 : row + 1) {
-        const long long rb = (long long)row * s.nx;
-        {
-            const zd l = load(0, rb + xm), c = load(0, rb + xc), r = load(0, rb + xp);
-            mz[2] = m0 * (l + r) + m1 * c;
-            kz[2] = ih * ((c + c) - (l + r));
-            dz[2] = 0.5 * (r - l);
-        }
-        {
-            const zd l = load(1, rb + xm), c = load(1, rb + xc), r = load(1, rb + xp);
-            me[2] = m0 * (l + r) + m1 * c;
-            ke[2] = ih * ((c + c) - (l + r));
-            de[2] = 0.5 * (r - l);
-            ce[2] = c;
-        }
-        if (a >= 2) {
-            const int y = y0 + a - 2;
-            if (!CHECK || (x < s.nx && y < s.ny)) {
-                auto Msum = [&](const zd* u) { return m0 * (u[0] + u[2]) + m1 * u[1]; };
-                const zd Mz = Msum(mz), Me = Msum(me);
-                const zd Kz = Msum(kz) + ih * ((mz[1] + mz[1]) - (mz[0] + mz[2]));
-                const zd Ke = Msum(ke) + ih * ((me[1] + me[1]) - (me[0] + me[2]));
-                const zd Tz = 2.0 * (kx * Msum(dz) + ky * (0.5 * (mz[2] - mz[0])));
-                const zd Te = 2.0 * (kx * Msum(de) + ky * (0.5 * (me[2] - me[0])));
-                const long long il = (long long)y * s.nx + x;
-                const zd y1 = Mz - gop(Ke, Te);
-                const zd y2 = s.kappa * gop(Kz, Tz) + s.inv_dt * Me + (s.kappa * s.w * dnode[s.doff + il]) * ce[1];
-                emit(il, y1, y2);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            mz[j] = mz[j + 1]; kz[j] = kz[j + 1]; dz[j] = dz[j + 1];
-            me[j] = me[j + 1]; ke[j] = ke[j + 1]; de[j] = de[j + 1]; ce[j] = ce[j + 1];
-        }
-    }
-}
-
-// W = A Z at every node and, fused, the first Gram-Schmidt pass: per-tile partials of V_i^H w
-// (i < nv) and of |w|^2 (slots 2i, 2i+1 and 2 nv of part, stride ntiles).  2D: column-marching
-// tiles (TY/4 rows per thread); 3D: k_apply_dot3d below.
-// NV >= nv basis vectors; with NV <= 8 the launch uses NV = nv exactly, so the basis loads carry no test.
-template <int TY, typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* __restrict__ Z, const double* __restrict__ dnode,
-                                                       zd* __restrict__ W, const cx<T>* __restrict__ V,
-                                                       long long vstride, int nv, double* part, long long NT,
-                                                       int ntiles) {
-    constexpr int RR = TY / 4;
-    __shared__ double lds[4 * (2 * NV + 1)];
-    TILE_PROLOGUE();
-    const int y0 = tile.y0 + ty * RR;
-    double acc[2 * NV + 1];
-#pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    const cx<T>* zz = Z + s.off;
-    const cx<T>* ze = Z + NT + s.off;
-    auto load = [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); };
-    auto emit = [&](long long il, const zd& y1, const zd& y2) {
-        W[s.off + il] = y1;
-        W[NT + s.off + il] = y2;
-        acc[2 * NV] += abs2(y1) + abs2(y2);
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (NV <= 8 || l < nv) {
-                const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
-                         q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
-                acc[2 * l] += p.x + q.x;
-                acc[2 * l + 1] += p.y + q.y;
-            }
-    };
-    if (tile.x0 + 64 <= s.nx && y0 + RR <= s.ny)
-        colmarch_A<RR, false>(s, x, y0, load, dnode, emit);
-    else
-        colmarch_A<RR, true>(s, x, y0, load, dnode, emit);
-    block_sum<2 * NV + 1>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (l < nv) {
-                part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
-                part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
-            }
-        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
-    }
-}
-
-// R = B - A X and per-tile partials of |R|^2, |B|^2 (slots kRR, kBB), on column-marching tiles.
-// R is stored in precision RT (the Krylov basis precision: only v_0 = r / |r| is formed from it); the
-// norms come from the FP64 values.
-template <int TY, typename RT>
-__global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                      const zd* __restrict__ X, const zd* __restrict__ B,
-                                                      const double* __restrict__ dnode, RT* __restrict__ R,
-                                                      double* part, long long NT, int ntiles) {
-    constexpr int RR = TY / 4;
-    __shared__ double lds[8];
-    TILE_PROLOGUE();
-    const int y0 = tile.y0 + ty * RR;
-    double acc[2] = {0.0, 0.0};
-    const zd* xz = X + s.off;
-    const zd* xe = X + NT + s.off;
-    auto load = [&](int f, long long i) { return (f == 0 ? xz : xe)[i]; };
-    auto emit = [&](long long il, const zd& y1, const zd& y2) {
-        const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
-        const zd r1 = b1 - y1, r2 = b2 - y2;
-        stv(R, s.off + il, r1);
-        stv(R, NT + s.off + il, r2);
-        acc[0] += abs2(r1) + abs2(r2);
-        acc[1] += abs2(b1) + abs2(b2);
-    };
-    if (tile.x0 + 64 <= s.nx && y0 + RR <= s.ny)
-        colmarch_A<RR, false>(s, x, y0, load, dnode, emit);
-    else
-        colmarch_A<RR, true>(s, x, y0, load, dnode, emit);
-    block_sum<2>(acc, lds);
-    if (threadIdx.x == 0) {
-        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
-        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
-    }
-}
-
-// 3D versions of k_apply_dot2d and k_residual2d on z-marching bricks (64 x 4 x TY/4 nodes).
-#define BRICK_PROLOGUE()                                                     \
-    TILE_PROLOGUE();                                                         \
-    const int y = tile.y0 + ty;                                              \
-    const int xc = x < s.nx ? x : s.nx - 1, yc = y < s.ny ? y : s.ny - 1;    \
-    const double m0 = s.h * (1.0 / 6.0), m1 = s.h * (4.0 / 6.0), ih = 1.0 / s.h;
-
-template <int TY, typename T, int NV>
-__global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V,
-                                                       long long vstride, int nv, double* part, long long NT,
-                                                       int ntiles) {
-    __shared__ double lds[4 * (2 * NV + 1)];
-    BRICK_PROLOGUE();
-    const cx<T>* zz = Z + s.off;
-    const cx<T>* ze = Z + NT + s.off;
-    double acc[2 * NV + 1];
-#pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    zmarch<TY / 4, 2, true, true, double>(
-        s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); },
-        [&](int z, const auto& P) {
-            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
-            const long long il = ((long long)z * s.ny + y) * s.nx + x;
-            zd y1, y2;
-            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
-            W[s.off + il] = y1;
-            W[NT + s.off + il] = y2;
-            acc[2 * NV] += abs2(y1) + abs2(y2);
-#pragma unroll
-            for (int l = 0; l < NV; ++l)
-                if (NV <= 8 || l < nv) {
-                    const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
-                         q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
-                    acc[2 * l] += p.x + q.x;
-                    acc[2 * l + 1] += p.y + q.y;
-                }
-        });
-    block_sum<2 * NV + 1>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-            if (l < nv) {
-                part[(2 * l) * (long long)ntiles + blockIdx.x] = acc[2 * l];
-                part[(2 * l + 1) * (long long)ntiles + blockIdx.x] = acc[2 * l + 1];
-            }
-        part[(2 * nv) * (long long)ntiles + blockIdx.x] = acc[2 * NV];
-    }
-}
-
-template <int TY, typename RT>
-__global__ __launch_bounds__(kBlock) void k_residual3d(const Sys* sys, const Tile* tiles, const int* mask, const zd* X,
-                                                      const zd* B, const double* dnode, RT* R, double* part,
-                                                      long long NT, int ntiles) {
-    __shared__ double lds[8];
-    BRICK_PROLOGUE();
-    const zd* xz = X + s.off;
-    const zd* xe = X + NT + s.off;
-    double acc[2] = {0.0, 0.0};
-    zmarch<TY / 4, 2, true, true, double>(
-        s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return (f == 0 ? xz : xe)[i]; },
-        [&](int z, const auto& P) {
-            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
-            const long long il = ((long long)z * s.ny + y) * s.nx + x;
-            zd y1, y2;
-            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
-            const zd b1 = B[s.off + il], b2 = B[NT + s.off + il];
-            const zd r1 = b1 - y1, r2 = b2 - y2;
-            stv(R, s.off + il, r1);
-            stv(R, NT + s.off + il, r2);
-            acc[0] += abs2(r1) + abs2(r2);
-            acc[1] += abs2(b1) + abs2(b2);
-        });
-    block_sum<2>(acc, lds);
-    if (threadIdx.x == 0) {
-        part[kRR * (long long)ntiles + blockIdx.x] = acc[0];
-        part[kBB * (long long)ntiles + blockIdx.x] = acc[1];
-    }
-}
-
-// ------------------------------------------------------------------------------------------
 // Block preconditioner (Eq. (12), four steps) with fixed-count Jacobi-PCG inner solves.
 // Operator of an inner solve: OP = 0 -> M (diag diagM), OP = 1 -> L = M/sqrt(dt) + sqrt(kappa) K.
 // The Jacobi diagonal is a constant on the uniform periodic mesh.
@@ -1061,177 +439,6 @@ __global__ __launch_bounds__(kBlock) void k_pc_final(const Sys* sys, const Tile*
     FOR_ROWS(TY) {
         const long long i = s.off + ((long long)pz * s.ny + y) * s.nx + x;
         z[i] = ld<T>(x1, i) - isk * (ld<T>(x2, i) - isd * ld<T>(z, NT + i));
-    }
-}
-
-// ------------------------------------------------------------------------------------------
-// Block preconditioner with Chebyshev-Jacobi inner solves, fused per step (2D).
-//
-// A workgroup owns a region of kChebRX x kChebRY nodes = an interior tile plus `halo` layers
-// (periodic wrap).  Every stencil application inside the region is evaluated from LDS and is
-// exact one layer further in than the previous one, so after `halo` applications the interior
-// holds the same values an unfused sweep over the whole mesh would give.  Three kernels per
-// preconditioner application:
-//   STAGE 0: x1   = Cheb_M^{sM}(beta1)                         (step 1)
-//   STAGE 1: x2   = Cheb_L^{sL}(beta2 - kappa G x1)             (step 2)
-//   STAGE 2: chi2 = Cheb_L^{sL}(M x2);  chi1 = x1 - (x2 - chi2/sqrt(dt))/sqrt(kappa)   (steps 3, 4)
-// Chebyshev iteration for D^{-1} A with spectrum in [theta - delta, theta + delta], x0 = 0
-// (three-term recurrence on the correction d):
-//   d0 = r0/(theta D), rho0 = delta/theta; x_{k+1} = x_k + d_k;
-//   r_{k+1} = r_k - A d_k; rho_{k+1} = 1/(2 theta/delta - rho_k);
-//   d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^{-1} r_{k+1}.
-// The spectral bounds are exact for the constant-coefficient operators (symbol extremes at the
-// corners cos(theta_d) = +-1), so the iteration needs no inner products.
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int wrapi(int g, int n) {
-    g %= n;
-    return g < 0 ? g + n : g;
-}
-
-// The operators of the inner solves in split form.  With P = [1 4 1], Q = [-1 2 -1] = 6 delta - P and
-// E = [-1 0 1], the bilinear element stencils are M = (h/6)^2 P(x)P,
-// K = (1/6)(Q(x)P + P(x)Q) = (delta(x)P + P(x)delta) - P(x)P/3 and T_j = (h/6)(k0 E(x)P + k1 P(x)E).
-// At a node with rows A, B, C (y - 1, y, y + 1), x passes p = P u and e = E u of those rows and centre
-// values uA, uB, uC:
-//   (cM M + cK K) u = a (pA + pC) + b pB + c (uA + uC) + d uB,
-//   a = cM (h/6)^2 - cK/3,  b = 4 a + cK,  c = cK,  d = 4 cK   (M alone: a = (h/6)^2, b = 4 a, c = d = 0),
-//   T_j u = (h/6) (k0 (eA + 4 eB + eC) + k1 (pC - pA)).
-// split_sweep streams rows r0 - 1 .. r0 + NP of column px of an LDS region (clamped at the region
-// border) and calls f(i, pA, pB, pC, uA, uB, uC, eA, eB, eC) for row r0 + i (e only with WE).
-template <typename T, int NP, bool WE, typename F>
-__device__ __forceinline__ void split_sweep(const cx<T>* buf, int px, int r0, int RX, int RY, F&& f) {
-    const int xm = px > 0 ? px - 1 : px, xp = px < RX - 1 ? px + 1 : px;
-    const cx<T> zero{T(0), T(0)};
-    cx<T> pA = zero, pB = zero, uA = zero, uB = zero, eA = zero, eB = zero;
-#pragma unroll
-    for (int a = 0; a < NP + 2; ++a) {
-        int row = r0 - 1 + a;
-        row = row < 0 ? 0 : (row > RY - 1 ? RY - 1 : row);
-        const cx<T> l = buf[row * RX + xm], c = buf[row * RX + px], r = buf[row * RX + xp];
-        const cx<T> pC = T(4) * c + (l + r);
-        const cx<T> eC = WE ? r - l : zero;
-        if (a >= 2) f(a - 2, pA, pB, pC, uA, uB, c, eA, eB, eC);
-        pA = pB; pB = pC;
-        uA = uB; uB = c;
-        eA = eB; eB = eC;
-    }
-}
-
-struct SplitCoef {
-    double a, b, c, d;
-};
-__host__ __device__ inline SplitCoef split_coef(double h, double cM, double cK) {
-    const double m = (h / 6.0) * (h / 6.0), a = cM * m - cK / 3.0;
-    return {a, 4.0 * a + cK, cK, 4.0 * cK};
-}
-
-template <typename T, int STAGE, int RX, int RY, int NTH>
-__global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v,
-                                               cx<T>* x1, cx<T>* x2, cx<T>* z, int sM, int sL, int halo,
-                                               long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
-    constexpr int RP = RX * RY, NP = RP / NTH;
-    static_assert(RP % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
-    // FP32: two region buffers used in turn, so each iteration needs one barrier (its writes go to the
-    // buffer the previous iteration did not read); FP64 regions are too large to double
-    constexpr int NB = sizeof(T) == 4 ? 2 : 1;
-    __shared__ cx<T> bufs[NB][RP];
-    cx<T>* buf = bufs[0];
-    const CTile tile = tiles[blockIdx.x];
-    if (mask && !mask[tile.sys]) return;
-    const Sys s = sys[tile.sys];
-    const int IX = RX - 2 * halo, IY = RY - 2 * halo;
-    // thread -> region column px and NP consecutive rows r0 .. r0 + NP - 1
-    const int px = threadIdx.x % RX, r0 = (threadIdx.x / RX) * NP;
-    const long long gx = wrapi(tile.x0 - halo + px, s.nx);
-    auto gidx = [&](int i) { return s.off + (long long)wrapi(tile.y0 - halo + r0 + i, s.ny) * s.nx + gx; };
-    auto lidx = [&](int i) { return (r0 + i) * RX + px; };
-    cx<T> X[NP], R[NP], Dd[NP];
-    // The input is v, or, when vscale is set, vscale[sys] * rv (the restart residual): the first basis
-    // vector of a cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to
-    // vout)
-    const double vs = vscale ? vscale[tile.sys] : 1.0;
-    auto ldv = [&](long long i) {
-        if (!vscale) return v[i];
-        const zd u = ld<double>(rv, i);
-        return cx<T>{T(vs * u.x), T(vs * u.y)};
-    };
-    // right-hand side of the inner solve
-    if constexpr (STAGE == 0) {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) R[i] = ldv(gidx(i));
-    } else {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) buf[lidx(i)] = STAGE == 1 ? x1[gidx(i)] : x2[gidx(i)];
-        __syncthreads();
-        if constexpr (STAGE == 1) {
-#pragma unroll
-            for (int i = 0; i < NP; ++i) R[i] = ldv(NT + gidx(i));
-            // r = beta2 - kappa G x1 with G = -K + i T_j: r += kappa K x1 - i kappa T_j x1
-            const T k3 = T(s.kappa / 3.0), k4 = T(4.0 * s.kappa), kap = T(s.kappa);
-            const T g0 = T(s.kappa * s.h / 6.0 * s.kv[0]), g1 = T(s.kappa * s.h / 6.0 * s.kv[1]);
-            split_sweep<T, NP, true>(buf, px, r0, RX, RY,
-                                     [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC,
-                                         cx<T> eA, cx<T> eB, cx<T> eC) {
-                                         const cx<T> kk = kap * (uA + uC) + k4 * uB - k3 * ((pA + pC) + pB);
-                                         const cx<T> tt = g0 * (T(4) * eB + (eA + eC)) + g1 * (pC - pA);
-                                         R[i] = R[i] + cx<T>{kk.x + tt.y, kk.y - tt.x};
-                                     });
-        } else {
-            const SplitCoef m = split_coef(s.h, 1.0, 0.0);
-            const T ma = T(m.a), mb = T(m.b);
-            split_sweep<T, NP, false>(buf, px, r0, RX, RY,
-                                      [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T>, cx<T>, cx<T>, cx<T>, cx<T>,
-                                          cx<T>) { R[i] = ma * (pA + pC) + mb * pB; });
-        }
-    }
-    // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
-    constexpr bool isM = STAGE == 0;
-    const int its = isM ? sM : sL;
-    const double(*cb)[2] = sys[tile.sys].cb[isM ? 0 : 1];
-    const SplitCoef oc = split_coef(s.h, isM ? 1.0 : s.isq_dt, isM ? 0.0 : s.sq_kap);
-    const T oa = T(oc.a), ob = T(oc.b), occ = T(oc.c), od = T(oc.d);
-    const T d0 = T(cb[0][0]);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        Dd[i] = d0 * R[i];
-        X[i] = Dd[i];
-    }
-    for (int k = 1; k < its; ++k) {
-        cx<T>* b = bufs[NB == 2 ? (k & 1) : 0];
-        if constexpr (NB == 1) __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NP; ++i) b[lidx(i)] = Dd[i];
-        __syncthreads();
-        const T c1 = T(cb[k][0]), c2 = T(cb[k][1]);
-        split_sweep<T, NP, false>(b, px, r0, RX, RY, [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB,
-                                                         cx<T> uC, cx<T>, cx<T>, cx<T>) {
-            // r -= OP d, as a chain of fused multiply-adds (the mass operator has no centre terms)
-            cx<T> q = R[i] - oa * (pA + pC) - ob * pB;
-            if constexpr (!isM) q = q - occ * (uA + uC) - od * uB;
-            R[i] = q;
-            Dd[i] = c1 * Dd[i] + c2 * R[i];
-            X[i] = X[i] + Dd[i];
-        });
-    }
-    // interior output (no wrap: each mesh node is written by exactly one tile)
-    const int ix = px - halo;
-    if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const int iy = r0 + i - halo;
-        if (iy < 0 || iy >= IY || tile.y0 + iy >= s.ny) continue;
-        const long long g = gidx(i);
-        if constexpr (STAGE == 0) {
-            x1[g] = X[i];
-            if (vscale) stv(vout, g, vs * ld<double>(rv, g));
-        } else if constexpr (STAGE == 1) {
-            x2[g] = X[i];
-            if (vscale) stv(vout, NT + g, vs * ld<double>(rv, NT + g));
-        } else {
-            const cx<T> chi2 = X[i];
-            z[g] = x1[g] - T(s.isq_kap) * (x2[g] - T(s.isq_dt) * chi2);
-            z[NT + g] = chi2;
-        }
     }
 }
 
@@ -2083,10 +1290,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Ti
 // ------------------------------------------------------------------------------------------
 static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init", "pc_final", "apply", "residual",
                                         "gs",       "proj_final", "xupdate",  "reduce",   "small", "other",
-                                        "cheb"};
-const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : "none"; }
+                                        "cheb",     "extrapolate", "rhs",  "mg"};
+const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : (kid == KID_ALL ? "all" : "none"); }
 int kernel_id(const char* name) {
     if (!name) return KID_NONE;
+    if (name[0] == 'a' && name[1] == 'l' && name[2] == 'l' && name[3] == 0) return KID_ALL;
     for (int i = 0; i < KID_COUNT; ++i) {
         const char* a = kNames[i];
         const char* b = name;
@@ -2110,59 +1318,9 @@ __global__ __launch_bounds__(kBlock) void k_active_frac(const Sys* sys, int S, c
     if (threadIdx.x == 0) *out = acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
 }
 
-// HIP events around a sampled launch of the probed kernel; after the closing event (outside the timed
-// window) k_active_frac records which share of the batch the launch worked on.  A launcher that starts
-// its kernel through launch() with ext = true has the two events stamped by the kernel's own dispatch
-// (hipExtLaunchKernel), so no event sits between them and the kernel.
-struct ProbeScope {
-    Probe* p;
-    hipStream_t st;
-    const Sys* sys;
-    int S;
-    const int* mask;
-    bool on, ext;
-    ProbeScope(const Dev& d, int kid, hipStream_t s, double bytes = 0.0, const int* m = nullptr, bool e = false)
-        : p(d.probe), st(s), sys(d.sys), S(d.S), mask(m), ext(e) {
-        on = p && p->target == kid && (p->seen++ % p->every) == 0 && p->n < Probe::kMax;
-        if (on) {
-            if (!ext) (void)hipEventRecord(p->ev[2 * p->n], st);
-            p->bytes[p->n] = bytes;
-        }
-    }
-    template <typename K, typename... A>
-    void launch(K kernel, dim3 grid, dim3 block, A... args) {
-        if (on && ext)
-            hipExtLaunchKernelGGL(kernel, grid, block, 0, st, p->ev[2 * p->n], p->ev[2 * p->n + 1], 0, args...);
-        else
-            hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
-    }
-    ~ProbeScope() {
-        if (on) {
-            if (!ext) (void)hipEventRecord(p->ev[2 * p->n + 1], st);
-            hipLaunchKernelGGL(k_active_frac, dim3(1), dim3(kBlock), 0, st, sys, S, mask, p->d_frac + p->n);
-            p->n += 1;
-        }
-    }
-};
-
-template <typename F>
-static void dispatch(const Dev& d, F&& f) {
-    auto ty = [&](auto dimc) {
-        switch (d.TY) {
-            case 4: f(dimc, std::integral_constant<int, 4>{}); break;
-            case 8: f(dimc, std::integral_constant<int, 8>{}); break;
-            case 32: f(dimc, std::integral_constant<int, 32>{}); break;
-            default: f(dimc, std::integral_constant<int, 16>{}); break;
-        }
-    };
-    if (d.dim == 3)
-        ty(std::integral_constant<int, 3>{});
-    else
-        ty(std::integral_constant<int, 2>{});
+void launch_active_frac(const Sys* sys, int S, const int* mask, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_active_frac, dim3(1), dim3(kBlock), 0, st, sys, S, mask, out);
 }
-
-#define TILE_GRID dim3(d.ntiles), dim3(kBlock), 0, st
-#define CHUNK_GRID dim3(d.nchunks), dim3(kBlock), 0, st
 
 void launch_state_in(const Dev& d, double* const* eta_tab, double* const* zeta_tab, zd* X, hipStream_t st) {
     ProbeScope ps(d, KID_OTHER, st);
@@ -2220,8 +1378,9 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(const zd* X, const zd* h
     }
 }
 void launch_extrapolate(const Dev& d, const zd* X, const zd* const* h, zd* X0, zd* keep, int order, hipStream_t st) {
-    ProbeScope ps(d, KID_OTHER, st);
     const long long n = 2 * d.NT;
+    // reads x and `order` kept states, writes the guess (and the kept copy)
+    ProbeScope ps(d, KID_EXTRAP, st, (double)n * sizeof(zd) * (order + 2 + (keep ? 1 : 0)));
     long long blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
     auto go = [&](auto oc) {
@@ -2270,6 +1429,9 @@ void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dn
 }
 void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_tab, double* dnode, zd* B,
                           hipStream_t st) {
+    // reads eta (each amplitude once; the other amplitudes of a node come through L2), writes B (both
+    // halves) and d (per instance node); a source adds one read of s
+    ProbeScope ps(d, KID_RHS, st, (double)d.NT * (sizeof(zd) * (3.0 + (src_tab ? 1.0 : 0.0)) + 8.0 / d.J));
     dispatch(d, [&](auto D, auto TY) {
         dispatch_jm(d.J, [&](auto JM) {
             hipLaunchKernelGGL((k_rhs_nonlinear<D(), TY(), JM()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half,
@@ -2277,34 +1439,6 @@ void launch_rhs_nonlinear(const Dev& d, const zd* eta_half, double* const* src_t
         });
     });
 }
-template <typename RT>
-void launch_residual(const Dev& d, const zd* X, const zd* B, const double* dnode, RT* R, double* part,
-                     const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_RESIDUAL, st, (double)d.NT * (4.0 * sizeof(zd) + 2.0 * sizeof(RT) + 8.0 / d.J), mask);
-    dispatch(d, [&](auto D, auto TY) {
-        if constexpr (D() == 3)
-            hipLaunchKernelGGL((k_residual3d<TY(), RT>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
-                               d.ntiles);
-        else
-            hipLaunchKernelGGL((k_residual2d<TY(), RT>), TILE_GRID, d.sys, d.tiles, mask, X, B, dnode, R, part, d.NT,
-                               d.ntiles);
-    });
-}
-template void launch_residual<zd>(const Dev&, const zd*, const zd*, const double*, zd*, double*, const int*,
-                                  hipStream_t);
-template void launch_residual<zf>(const Dev&, const zd*, const zd*, const double*, zf*, double*, const int*,
-                                  hipStream_t);
-template <typename T>
-void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const int* mask, hipStream_t st) {
-    // reads z (2 half vectors) and d (per instance), writes w (2 FP64 half vectors)
-    ProbeScope ps(d, KID_APPLY, st, (double)d.NT * (2.0 * sizeof(cx<T>) + 2.0 * sizeof(zd) + 8.0 / d.J), mask);
-    dispatch(d, [&](auto D, auto TY) {
-        hipLaunchKernelGGL((k_apply<D(), TY(), T>), TILE_GRID, d.sys, d.tiles, mask, Z, dnode, W, d.NT);
-    });
-}
-template void launch_apply<double>(const Dev&, const zd*, const double*, zd*, const int*, hipStream_t);
-template void launch_apply<float>(const Dev&, const zf*, const double*, zd*, const int*, hipStream_t);
-
 template <int DIM, int TY, typename T, int OP>
 static void cg_iterations(const Dev& d, cx<T>* xv, cx<T>* r, cx<T>* p0, cx<T>* p1, cx<T>* q, double* part, int n,
                           const int* mask, hipStream_t st) {
@@ -2376,45 +1510,6 @@ template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, 
                                      const int*, hipStream_t);
 template void launch_precond<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
                                     const int*, hipStream_t);
-
-template <typename T, int RX, int RY, int NTH>
-static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
-                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                        const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
-    const dim3 g(nctiles), b(NTH);
-    // input half read (residual or basis vector) and, with vscale, the basis vector written
-    const double pts = (double)d.NT, vin = (double)sizeof(cx<T>), vb = vscale ? (double)sizeof(cx<T>) : 0.0;
-    {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
-        hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT, vscale, rv, vout);
-    }
-    {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb), mask);
-        hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                           diff_iters, halo, d.NT, vscale, rv, vout);
-    }
-    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask);
-    hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                       diff_iters, halo, d.NT, nullptr, nullptr, nullptr);
-}
-
-template <typename T>
-void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
-                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
-    switch (shape) {
-        case 1: cheb_stages<T, 64, 32, 256>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
-        case 2: cheb_stages<T, 64, 64, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
-        case 3: cheb_stages<T, 128, 36, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
-        case 4: cheb_stages<T, 128, 40, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
-        default: cheb_stages<T, 128, 32, 512>(d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st); break;
-    }
-}
-template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
-                                          const double*, const zd*, zd*, const int*, hipStream_t);
-template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
-                                         const double*, const zf*, zf*, const int*, hipStream_t);
 
 // stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D
 template <int DIM, int TY, typename T, int STAGE>
@@ -2530,6 +1625,39 @@ template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd
 template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, int, int,
                                                  const int*, hipStream_t);
 
+template <typename T>
+void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r,
+                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, const int* mask, hipStream_t st) {
+    dispatch(d, [&](auto D, auto TY) {
+        constexpr int DIM = D(), TYv = TY();
+        // step 1: beta1' ~ M^{-1} beta1 by Chebyshev iterations (as the Chebyshev inner solver)
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
+            cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+        }
+        cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
+        // step 2: b = beta2 - kappa G beta1' (the stage-1 start writes it to its residual argument), one V-cycle
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
+            cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, b, d0, d1, st);
+        }
+        launch_mg_vcycle<T>(d, mg, b, x2, r, d0, d1, mask, st);
+        // step 3: b = M beta2', one V-cycle into the eta part of z
+        {
+            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
+            cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, b, d0, d1, st);
+        }
+        launch_mg_vcycle<T>(d, mg, b, z + d.NT, r, d0, d1, mask, st);
+        // step 4
+        ProbeScope ps(d, KID_PC_FINAL, st);
+        hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);
+    });
+}
+template void launch_precond_mg<double>(const Dev&, const MgLevels&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, zd*, int,
+                                        const int*, hipStream_t);
+template void launch_precond_mg<float>(const Dev&, const MgLevels&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, int,
+                                       const int*, hipStream_t);
+
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
                        hipStream_t st) {
     // zeta = M^{-1} G eta by Chebyshev-Jacobi iterations with the exact bounds of D^{-1} M
@@ -2574,41 +1702,6 @@ template void launch_gs<zd>(const Dev&, const Krylov&, int, const double*, const
                             hipStream_t);
 template void launch_gs<zf>(const Dev&, const Krylov&, int, const double*, const zf*, long long, const zd*, double*,
                             hipStream_t);
-
-template <typename T>
-void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
-                      double* part, const int* mask, hipStream_t st) {
-    // reads z, d, nv basis vectors (stored like z); writes w
-    ProbeScope ps(d, KID_APPLY, st,
-                  (double)d.NT * (2.0 * sizeof(cx<T>) * (1 + nv) + 2.0 * sizeof(zd) + 8.0 / d.J), mask, true);
-    dispatch(d, [&](auto D, auto TY) {
-        auto go = [&](auto nvc) {
-            if constexpr (D() == 2)
-                ps.launch(k_apply_dot2d<TY(), T, decltype(nvc)::value>, dim3(d.ntiles), dim3(kBlock), d.sys, d.tiles,
-                          mask, Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
-            else
-                ps.launch(k_apply_dot3d<TY(), T, decltype(nvc)::value>, dim3(d.ntiles), dim3(kBlock), d.sys, d.tiles,
-                          mask, Z, dnode, W, V, vstride, nv, part, d.NT, d.ntiles);
-        };
-        switch (nv) {
-            case 1: go(std::integral_constant<int, 1>{}); return;
-            case 2: go(std::integral_constant<int, 2>{}); return;
-            case 3: go(std::integral_constant<int, 3>{}); return;
-            case 4: go(std::integral_constant<int, 4>{}); return;
-            case 5: go(std::integral_constant<int, 5>{}); return;
-            case 6: go(std::integral_constant<int, 6>{}); return;
-            case 7: go(std::integral_constant<int, 7>{}); return;
-            case 8: go(std::integral_constant<int, 8>{}); return;
-            default: break;
-        }
-        if (nv <= 16) go(std::integral_constant<int, 16>{});
-        else go(std::integral_constant<int, 32>{});
-    });
-}
-template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*, const zd*, long long, int, double*,
-                                       const int*, hipStream_t);
-template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zf*, long long, int, double*,
-                                      const int*, hipStream_t);
 
 
 template <typename VT>

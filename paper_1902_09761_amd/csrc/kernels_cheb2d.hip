@@ -1,0 +1,300 @@
+// The block preconditioner of Eq. (12) with Chebyshev-Jacobi inner solves, fused per step on LDS regions
+// (2D), for gfx950, with its launcher.
+#include "kernels_common.h"
+
+namespace apfc {
+
+// ------------------------------------------------------------------------------------------
+// Block preconditioner with Chebyshev-Jacobi inner solves, fused per step (2D).
+//
+// A workgroup owns a region of kChebRX x kChebRY nodes = an interior tile plus `halo` layers
+// (periodic wrap).  Every stencil application inside the region is evaluated from LDS and is
+// exact one layer further in than the previous one, so after `halo` applications the interior
+// holds the same values an unfused sweep over the whole mesh would give.  Three kernels per
+// preconditioner application:
+//   STAGE 0: x1   = Cheb_M^{sM}(beta1)                         (step 1)
+//   STAGE 1: x2   = Cheb_L^{sL}(beta2 - kappa G x1)             (step 2)
+//   STAGE 2: chi2 = Cheb_L^{sL}(M x2);  chi1 = x1 - (x2 - chi2/sqrt(dt))/sqrt(kappa)   (steps 3, 4)
+// Chebyshev iteration for D^{-1} A with spectrum in [theta - delta, theta + delta], x0 = 0
+// (three-term recurrence on the correction d):
+//   d0 = r0/(theta D), rho0 = delta/theta; x_{k+1} = x_k + d_k;
+//   r_{k+1} = r_k - A d_k; rho_{k+1} = 1/(2 theta/delta - rho_k);
+//   d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^{-1} r_{k+1}.
+// The spectral bounds are exact for the constant-coefficient operators (symbol extremes at the
+// corners cos(theta_d) = +-1), so the iteration needs no inner products.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int wrapi(int g, int n) {
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+// The operators of the inner solves in split form.  With P = [1 4 1], Q = [-1 2 -1] = 6 delta - P and
+// E = [-1 0 1], the bilinear element stencils are M = (h/6)^2 P(x)P,
+// K = (1/6)(Q(x)P + P(x)Q) = (delta(x)P + P(x)delta) - P(x)P/3 and T_j = (h/6)(k0 E(x)P + k1 P(x)E).
+// At a node with rows A, B, C (y - 1, y, y + 1), x passes p = P u and e = E u of those rows and centre
+// values uA, uB, uC:
+//   (cM M + cK K) u = a (pA + pC) + b pB + c (uA + uC) + d uB,
+//   a = cM (h/6)^2 - cK/3,  b = 4 a + cK,  c = cK,  d = 4 cK   (M alone: a = (h/6)^2, b = 4 a, c = d = 0),
+//   T_j u = (h/6) (k0 (eA + 4 eB + eC) + k1 (pC - pA)).
+// The LDS region keeps one pad row above and below the RY region rows (region row q at LDS row q + 1),
+// so a thread's rows r0 - 1 .. r0 + NP are rows of the array with no clamping and every load of the
+// sweep is a fixed offset from the thread's three column addresses.  split_sweep streams them (b = LDS row
+// r0 of the buffer, i.e. region row r0 - 1; columns xm, xc, xp) and calls
+// f(i, pA, pB, pC, uA, uB, uC, eA, eB, eC) for region row r0 + i (e only with WE).  The loads of the next
+// row are issued while the current one is used, and no further (a scheduling barrier per row): hoisting
+// every row's loads ahead would cost registers the workgroups of a CU need.
+template <typename T, int NP, int RX, bool WE, typename F>
+__device__ __forceinline__ void split_sweep(const cx<T>* b, int xm, int xc, int xp, F&& f) {
+    const cx<T> zero{T(0), T(0)};
+    cx<T> pA = zero, pB = zero, uA = zero, uB = zero, eA = zero, eB = zero;
+    const cx<T>* bm = b + xm;
+    const cx<T>* bc = b + xc;
+    const cx<T>* bp = b + xp;
+    cx<T> l = bm[0], c = bc[0], r = bp[0];
+#pragma unroll
+    for (int a = 0; a < NP + 2; ++a) {
+        cx<T> ln = zero, cn = zero, rn = zero;
+        if (a + 1 < NP + 2) {
+            ln = bm[(a + 1) * RX];
+            cn = bc[(a + 1) * RX];
+            rn = bp[(a + 1) * RX];
+        }
+        const cx<T> pC = T(4) * c + (l + r);
+        const cx<T> eC = WE ? r - l : zero;
+        if (a >= 2) f(a - 2, pA, pB, pC, uA, uB, c, eA, eB, eC);
+        pA = pB; pB = pC;
+        uA = uB; uB = c;
+        eA = eB; eB = eC;
+        l = ln; c = cn; r = rn;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+struct SplitCoef {
+    double a, b, c, d;
+};
+__host__ __device__ inline SplitCoef split_coef(double h, double cM, double cK) {
+    const double m = (h / 6.0) * (h / 6.0), a = cM * m - cK / 3.0;
+    return {a, 4.0 * a + cK, cK, 4.0 * cK};
+}
+
+// Global node of the thread's region rows: x wrapped once per thread, rows walked with a running
+// periodic row index (no division per row).
+struct RegionRows {
+    long long base, gx;
+    int gy, nx, ny;
+    __device__ __forceinline__ long long at() const { return base + (long long)gy * nx + gx; }
+    __device__ __forceinline__ void next() { gy = gy + 1 == ny ? 0 : gy + 1; }
+};
+
+// FP32 (mixed precision): two region buffers used in turn; iteration k reads the correction d_{k-1} from
+// one and writes d_k into the other as soon as it is formed, so each iteration needs one barrier and d_k
+// needs no registers (a thread's own d_{k-1} is the centre value of its sweep).  FP64 regions are twice
+// as large: one buffer, d_k kept in registers until the sweep has finished reading.
+template <typename T>
+constexpr int cheb_buffers() { return sizeof(T) == 4 ? 2 : 1; }
+
+template <typename T, int STAGE, int RX, int RY, int NTH>
+__global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
+    const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v, cx<T>* x1, cx<T>* x2, cx<T>* z, int sM,
+    int sL, int halo, long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
+    constexpr int NB = cheb_buffers<T>();
+    constexpr int RL = RY + 2, RP = RX * RL, NP = RX * RY / NTH;
+    static_assert((RX * RY) % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
+    __shared__ cx<T> bufs[NB][RP];
+    const CTile tile = tiles[blockIdx.x];
+    if (mask && !mask[tile.sys]) return;
+    const Sys s = sys[tile.sys];
+    const int IX = RX - 2 * halo, IY = RY - 2 * halo;
+    // thread -> region column px and NP consecutive rows r0 .. r0 + NP - 1
+    const int px = threadIdx.x % RX, r0 = (threadIdx.x / RX) * NP;
+    const int xm = px > 0 ? px - 1 : px, xp = px < RX - 1 ? px + 1 : px;
+    const RegionRows rows0{s.off, (long long)wrapi(tile.x0 - halo + px, s.nx), wrapi(tile.y0 - halo + r0, s.ny), s.nx,
+                           s.ny};
+    auto lrow = [&](cx<T>* b, int i) -> cx<T>& { return b[(r0 + 1 + i) * RX + px]; };
+    // the pad rows only feed the outermost halo rows; zero them so that no stale value is ever read
+    for (int e = threadIdx.x; e < RX; e += NTH)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            bufs[q][e] = cx<T>{T(0), T(0)};
+            bufs[q][(RL - 1) * RX + e] = cx<T>{T(0), T(0)};
+        }
+    cx<T> X[NP], R[NP];
+    // The input is v, or, when vscale is set, vscale[sys] * rv (the restart residual): the first basis
+    // vector of a cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to
+    // vout)
+    const double vs = vscale ? vscale[tile.sys] : 1.0;
+    auto ldv = [&](long long i) {
+        if (!vscale) return v[i];
+        const zd u = ld<double>(rv, i);
+        return cx<T>{T(vs * u.x), T(vs * u.y)};
+    };
+    // right-hand side of the inner solve
+    if constexpr (STAGE == 0) {
+        RegionRows g = rows0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i, g.next()) R[i] = ldv(g.at());
+    } else {
+        {
+            RegionRows g = rows0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i, g.next()) lrow(bufs[0], i) = STAGE == 1 ? x1[g.at()] : x2[g.at()];
+        }
+        if constexpr (STAGE == 1) {
+            RegionRows g = rows0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i, g.next()) R[i] = ldv(NT + g.at());
+        }
+        __syncthreads();
+        if constexpr (STAGE == 1) {
+            // r = beta2 - kappa G x1 with G = -K + i T_j: r += kappa K x1 - i kappa T_j x1
+            const T k3 = T(s.kappa / 3.0), k4 = T(4.0 * s.kappa), kap = T(s.kappa);
+            const T g0 = T(s.kappa * s.h / 6.0 * s.kv[0]), g1 = T(s.kappa * s.h / 6.0 * s.kv[1]);
+            split_sweep<T, NP, RX, true>(bufs[0] + r0 * RX, xm, px, xp,
+                                         [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC,
+                                             cx<T> eA, cx<T> eB, cx<T> eC) {
+                                             const cx<T> kk = kap * (uA + uC) + k4 * uB - k3 * ((pA + pC) + pB);
+                                             const cx<T> tt = g0 * (T(4) * eB + (eA + eC)) + g1 * (pC - pA);
+                                             R[i] = R[i] + cx<T>{kk.x + tt.y, kk.y - tt.x};
+                                         });
+        } else {
+            const SplitCoef m = split_coef(s.h, 1.0, 0.0);
+            const T ma = T(m.a), mb = T(m.b);
+            split_sweep<T, NP, RX, false>(bufs[0] + r0 * RX, xm, px, xp,
+                                          [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T>, cx<T>, cx<T>, cx<T>,
+                                              cx<T>, cx<T>) { R[i] = ma * (pA + pC) + mb * pB; });
+        }
+    }
+    // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
+    constexpr bool isM = STAGE == 0;
+    const int its = isM ? sM : sL;
+    const double(*cb)[2] = sys[tile.sys].cb[isM ? 0 : 1];
+    const SplitCoef oc = split_coef(s.h, isM ? 1.0 : s.isq_dt, isM ? 0.0 : s.sq_kap);
+    const T oa = T(oc.a), ob = T(oc.b), occ = T(oc.c), od = T(oc.d);
+    const T d0 = T(cb[0][0]);
+    if constexpr (NB == 2) {
+        // d_0 into bufs[1]; iteration k reads d_{k-1} from bufs[k & 1] (the barrier at its start orders it
+        // after every write of d_{k-1} and after every read of the buffer it writes, bufs[(k + 1) & 1], by
+        // iteration k - 1 or by the prologue of stages 1 and 2)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const cx<T> dv = d0 * R[i];
+            X[i] = dv;
+            lrow(bufs[1], i) = dv;
+        }
+        auto iteration = [&](int k, auto store) {
+            __syncthreads();
+            const cx<T>* b = bufs[k & 1];
+            cx<T>* bn = bufs[(k + 1) & 1];
+            const T c1 = T(cb[k][0]), c2 = T(cb[k][1]);
+            split_sweep<T, NP, RX, false>(b + r0 * RX, xm, px, xp, [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA,
+                                                                        cx<T> uB, cx<T> uC, cx<T>, cx<T>, cx<T>) {
+                // r -= OP d_{k-1} (uB = this node's d_{k-1}), as a chain of fused multiply-adds (the mass
+                // operator has no centre terms); d_k = c1 d_{k-1} + c2 r; x += d_k
+                cx<T> q = R[i] - oa * (pA + pC) - ob * pB;
+                if constexpr (!isM) q = q - occ * (uA + uC) - od * uB;
+                R[i] = q;
+                const cx<T> dv = c1 * uB + c2 * q;
+                X[i] = X[i] + dv;
+                if constexpr (decltype(store)::value) lrow(bn, i) = dv;
+            });
+        };
+        // the last iteration's d is not needed by anyone: it is not stored
+        for (int k = 1; k + 1 < its; ++k) iteration(k, std::true_type{});
+        if (its > 1) iteration(its - 1, std::false_type{});
+    } else {
+        cx<T> Dd[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            Dd[i] = d0 * R[i];
+            X[i] = Dd[i];
+        }
+        for (int k = 1; k < its; ++k) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NP; ++i) lrow(bufs[0], i) = Dd[i];
+            __syncthreads();
+            const T c1 = T(cb[k][0]), c2 = T(cb[k][1]);
+            split_sweep<T, NP, RX, false>(bufs[0] + r0 * RX, xm, px, xp,
+                                          [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC,
+                                              cx<T>, cx<T>, cx<T>) {
+                                              cx<T> q = R[i] - oa * (pA + pC) - ob * pB;
+                                              if constexpr (!isM) q = q - occ * (uA + uC) - od * uB;
+                                              R[i] = q;
+                                              Dd[i] = c1 * Dd[i] + c2 * R[i];
+                                              X[i] = X[i] + Dd[i];
+                                          });
+        }
+    }
+    // interior output (no wrap: each mesh node is written by exactly one tile)
+    const int ix = px - halo;
+    if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
+    RegionRows g = rows0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i, g.next()) {
+        const int iy = r0 + i - halo;
+        if (iy < 0 || iy >= IY || tile.y0 + iy >= s.ny) continue;
+        const long long gi = g.at();
+        if constexpr (STAGE == 0) {
+            x1[gi] = X[i];
+            if (vscale) stv(vout, gi, vs * ld<double>(rv, gi));
+        } else if constexpr (STAGE == 1) {
+            x2[gi] = X[i];
+            if (vscale) stv(vout, NT + gi, vs * ld<double>(rv, NT + gi));
+        } else {
+            const cx<T> chi2 = X[i];
+            z[gi] = x1[gi] - T(s.isq_kap) * (x2[gi] - T(s.isq_dt) * chi2);
+            z[NT + gi] = chi2;
+        }
+    }
+}
+
+template <typename T, int RX, int RY, int NTH>
+static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
+                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                        const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+    const dim3 g(nctiles), b(NTH);
+    // input half read (residual or basis vector) and, with vscale, the basis vector written
+    const double pts = (double)d.NT, vin = (double)sizeof(cx<T>), vb = vscale ? (double)sizeof(cx<T>) : 0.0;
+    {
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
+        hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z,
+                           mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+    }
+    {
+        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb), mask);
+        hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z,
+                           mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+    }
+    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask);
+    hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
+                       diff_iters, halo, d.NT, nullptr, nullptr, nullptr);
+}
+
+template <typename T>
+void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
+                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+#define APFC_CHEB_SHAPE(I)                                                                                       \
+    case I:                                                                                                      \
+        cheb_stages<T, kChebShape[I][0], kChebShape[I][1], kChebShape[I][2]>(                                    \
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st);          \
+        break;
+    static_assert(kChebShapes == 6, "one case per region shape");
+    switch (shape) {
+        APFC_CHEB_SHAPE(1)
+        APFC_CHEB_SHAPE(2)
+        APFC_CHEB_SHAPE(3)
+        APFC_CHEB_SHAPE(4)
+        APFC_CHEB_SHAPE(5)
+        default: cheb_stages<T, kChebShape[0][0], kChebShape[0][1], kChebShape[0][2]>(
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st);
+    }
+#undef APFC_CHEB_SHAPE
+}
+template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
+                                          const double*, const zd*, zd*, const int*, hipStream_t);
+template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
+                                         const double*, const zf*, zf*, const int*, hipStream_t);
+
+}  // namespace apfc

@@ -11,7 +11,11 @@ with nodes in x-fastest lexicographic order on the periodic uniform grid
 (node (ix, iy, iz) at position (ix*h, iy*h, iz*h), h = L/n).
 
 Units: the triangular lattice spacing for |k|=1 is 4*pi/sqrt(3); the cubic
-constant of the bcc lattice built from the unit <110> vectors is 2*pi*sqrt(2).
+constant of the bcc lattice built from the unit <110> vectors is 2*pi*sqrt(2), that
+of the fcc lattice built from the unit <111> vectors 2*pi*sqrt(3).
+
+The relaxed amplitude phi is a number (every amplitude the same) or one value per
+amplitude (lattices with several shells of |k_j|, such as fcc).
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ import numpy as np
 
 TRI_SPACING = 4.0 * math.pi / math.sqrt(3.0)
 BCC_SPACING = 2.0 * math.pi * math.sqrt(2.0)
+FCC_SPACING = 2.0 * math.pi * math.sqrt(3.0)
 NOISE_AMPLITUDE = 1e-3
 
 
@@ -82,11 +87,17 @@ def delta_k(kvecs: np.ndarray, theta: float, axis=(0.0, 0.0, 1.0)) -> np.ndarray
     return kvecs @ R.T - kvecs
 
 
+def amplitudes(phi, J: int) -> np.ndarray:
+    """phi as a (J, 1) column: one number for every amplitude, or one value per amplitude."""
+    a = np.asarray(phi, dtype=float).reshape(-1, 1)
+    return np.broadcast_to(a, (J, 1)) if a.shape[0] == 1 else a
+
+
 def rotated_grain(kvecs, phi, theta, centre, coords, length, axis=(0.0, 0.0, 1.0)):
-    """eta_j = phi * exp(i dk_j . (r - c)), phase measured from the grain centre (minimum image)."""
+    """eta_j = phi_j * exp(i dk_j . (r - c)), phase measured from the grain centre (minimum image)."""
     dr = min_image(coords - np.asarray(centre)[None, :], length)
     dk = delta_k(np.asarray(kvecs, float), theta, axis)
-    return phi * np.exp(1j * (dr @ dk.T)).T                 # (J, N)
+    return amplitudes(phi, len(kvecs)) * np.exp(1j * (dr @ dk.T)).T     # (J, N)
 
 
 def add_noise(eta: np.ndarray, seed: int, amplitude: float = NOISE_AMPLITUDE) -> np.ndarray:
@@ -106,7 +117,7 @@ def single_grain(mesh: Mesh, kvecs, phi, theta, radius, centre=None, matrix="cry
     J = len(kvecs)
     grain = rotated_grain(kvecs, phi, theta, centre, coords, mesh.length, axis)
     if matrix == "crystal":
-        eta = np.full((J, mesh.N), phi, dtype=np.complex128)
+        eta = np.broadcast_to(amplitudes(phi, J), (J, mesh.N)).astype(np.complex128)
     else:
         eta = np.zeros((J, mesh.N), dtype=np.complex128)
     inside = np.linalg.norm(min_image(coords - np.asarray(centre)[None, :], mesh.length), axis=1) < radius
@@ -203,16 +214,16 @@ def batch_2d(kvecs, phi_of_dB, count=64, seed=1, sizes=BATCH_SIZES) -> List[Work
     return out
 
 
-def sphere_3d(kvecs, phi_of_dB, n=128, seed=1, dB=0.02) -> Workload:
-    """bcc lattice (unit <110> vectors), 128^3 periodic cube of side 60 cubic constants,
-    spherical grain of radius 20 constants rotated 5 degrees about [001]; dt=1, 20 steps.
-    Smaller n keeps h fixed."""
-    h = 60.0 * BCC_SPACING / 128.0
+def sphere_3d(kvecs, phi_of_dB, n=128, seed=1, dB=0.02, spacing=BCC_SPACING, name="bcc") -> Workload:
+    """Cubic lattice (bcc: unit <110> vectors; fcc with spacing=FCC_SPACING: the <111> and <200>
+    shells), 128^3 periodic cube of side 60 cubic constants, spherical grain of radius 20 constants
+    rotated 5 degrees about [001]; dt=1, 20 steps.  Smaller n keeps h fixed."""
+    h = 60.0 * spacing / 128.0
     mesh = mesh3d(n, n * h)
-    R = 20.0 * BCC_SPACING * (n / 128.0)
+    R = 20.0 * spacing * (n / 128.0)
     eta = single_grain(mesh, kvecs, phi_of_dB(dB), math.radians(5.0), R, seed=seed,
                        axis=(0.0, 0.0, 1.0))
-    return Workload(f"bcc{n}_sphere", mesh, eta, dB, 1.0, 20, 1e-8)
+    return Workload(f"{name}{n}_sphere", mesh, eta, dB, 1.0, 20, 1e-8)
 
 
 def two_grains_2d(kvecs, phi_of_dB, n=256, seed=1, dB=0.02) -> Workload:

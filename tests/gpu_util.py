@@ -37,3 +37,9 @@ def solver_for(meshes, kind, dBs, **kw):
     ms = [apfc.make_mesh(m.dim, m.n, m.length) for m in meshes]
     ps = [apfc.apfc_params_default(a1=0.5 * dB, **kw) for dB in dBs]
     return apfc.Solver(ms, lat, ps)
+
+
+def eq_of(k):
+    """dB -> relaxed amplitude of every amplitude (one value per shell of |k_j|; FCC has two)."""
+    from oracle.apfc_oracle import equilibrium_amplitudes
+    return lambda dB: equilibrium_amplitudes(BulkEnergy(k, Params.from_dB(dB)))

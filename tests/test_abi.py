@@ -142,3 +142,49 @@ def test_noalloc_limit_is_checked_on_the_host():
                                                                diff_iters=3))
     assert L.apfc_workspace_bytes(c) <= L.apfc_noalloc_max_bytes()
     L.apfc_destroy(c)
+
+
+def test_fcc_lattice_and_equilibrium_amplitudes():
+    """APFC_FCC3D: the <111> and <200> shells; apfc_create accepts its resonances; the library's
+    relaxed amplitudes (Newton on the shell values) are the stationary point of the two-mode polynomial
+    of the FCC bulk energy written out by hand (its gradient 16 a1 - 48 a3 phi2 + 288 a2 phi1^2 +
+    384 a2 phi2^2 = 0, 12 a1 phi2 - 24 a3 phi1^2 + 384 a2 phi1^2 phi2 + 120 a2 phi2^3 = 0), and the single
+    value of apfc_uniform_amplitude for the one-shell lattices."""
+    import scipy.optimize
+    L = apfc.apfc_lattice_default(apfc.APFC_FCC3D)
+    assert L.J == 7
+    norms = [math.sqrt(sum(L.k[j][c] ** 2 for c in range(3))) for j in range(7)]
+    assert norms == pytest.approx([1, 1, 1, 1, 2 / math.sqrt(3), 2 / math.sqrt(3), 2 / math.sqrt(3)], rel=1e-15)
+    m = apfc.make_mesh(3, (8, 8, 8), (80.0, 80.0, 80.0))
+    rc, ctx = _create(m, lat=L)
+    assert rc == apfc.APFC_OK
+    apfc.lib().apfc_destroy(ctx)
+    for dB in (0.01, 0.02, 0.04):
+        p = apfc.apfc_params_default(a1=0.5 * dB)
+        a1, a2, a3 = p.a1, p.a2, p.a3
+
+        def g(x):
+            p1, p2 = x
+            return [16 * a1 - 48 * a3 * p2 + 288 * a2 * p1 ** 2 + 384 * a2 * p2 ** 2,
+                    12 * a1 * p2 - 24 * a3 * p1 ** 2 + 384 * a2 * p1 ** 2 * p2 + 120 * a2 * p2 ** 3]
+        ref = scipy.optimize.fsolve(g, [0.12, 0.12], xtol=1e-14)
+        got = apfc.apfc_equilibrium_amplitudes(L, p)
+        assert got == pytest.approx([ref[0]] * 4 + [ref[1]] * 3, rel=1e-12)
+        for kind in (apfc.APFC_TRI2D, apfc.APFC_BCC3D):
+            lk = apfc.apfc_lattice_default(kind)
+            assert apfc.apfc_equilibrium_amplitudes(lk, p) == [apfc.apfc_uniform_amplitude(lk, p)] * lk.J
+
+
+def test_multigrid_hierarchy_limits():
+    """APFC_INNER_MG: meshes that halve to a coarsest level of at most 8192 nodes are accepted (a 1024^2
+    mesh coarsens to 16^2, a 40 x 28 mesh is its own coarsest level, 150^2 halves once to 75^2 = 5625
+    nodes); 101^2 (odd, 10201 nodes) and 182^2 (halves to 91^2 = 8281 nodes) are not."""
+    for n, ok in (((1024, 1024), True), ((40, 28), True), ((150, 150), True), ((101, 101), False),
+                  ((182, 182), False)):
+        m = apfc.make_mesh(2, n, (n[0] * 2.0, n[1] * 2.0))
+        rc, ctx = _create(m, params=apfc.apfc_params_default(inner_kind=apfc.APFC_INNER_MG, diff_iters=2))
+        assert (rc == apfc.APFC_OK) == ok, (n, rc)
+        if ok:
+            apfc.lib().apfc_destroy(ctx)
+        else:
+            assert b"coarsest multigrid level" in apfc.lib().apfc_last_error()

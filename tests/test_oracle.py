@@ -13,7 +13,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle.apfc_oracle import (BulkEnergy, Grid, Oracle, Params, assemble, bcc_k, chebyshev, element_matrices,
-                                fourier_symbols, jacobi_pcg, kappas, kron_matrices, model_spectrum,
+                                equilibrium_amplitudes, fcc_k, fourier_symbols, jacobi_pcg, kappas, kron_matrices, model_spectrum,
                                 plane_wave, tri_bulk_closed_form, tri_k, uniform_amplitude)
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -165,10 +165,13 @@ def test_tri_bulk_reproduces_eq5_eq6():
     np.testing.assert_allclose(b.f(eta), tri_bulk_closed_form(eta, p), rtol=1e-13, atol=1e-15)
 
 
-@pytest.mark.parametrize("lattice", ["tri", "bcc"])
+LATTICES = {"tri": tri_k, "bcc": bcc_k, "fcc": fcc_k}
+
+
+@pytest.mark.parametrize("lattice", ["tri", "bcc", "fcc"])
 def test_force_is_wirtinger_derivative(lattice):
     """F^s_j = d f / d eta_j^* = (df/dx + i df/dy)/2, checked by central differences."""
-    k = tri_k() if lattice == "tri" else bcc_k()
+    k = LATTICES[lattice]()
     b = BulkEnergy(k, Params())
     eta = rand_eta(len(k), 7, seed=5)
     F = b.F(eta)
@@ -182,13 +185,13 @@ def test_force_is_wirtinger_derivative(lattice):
             np.testing.assert_allclose(fd, comp, rtol=1e-7, atol=1e-9)
 
 
-@pytest.mark.parametrize("lattice", ["tri", "bcc"])
+@pytest.mark.parametrize("lattice", ["tri", "bcc", "fcc"])
 def test_newton_jacobian_closed_form(lattice):
-    """For both lattices every resonant cubic/quartic term with eta_j and eta_j^* is a
+    """For the three lattices every resonant cubic/quartic term with eta_j and eta_j^* is a
     pair term, so dF_j = 2 a1/a0 + 4 (a2/a0) A (real, the same for all j), and for the
     triangular lattice h_j = -4 (a2/a0) |eta_j|^2 eta_j - 2 (a3/a0) prod_{l != j} eta_l^*."""
     p = Params()
-    k = tri_k() if lattice == "tri" else bcc_k()
+    k = LATTICES[lattice]()
     b = BulkEnergy(k, p)
     eta = rand_eta(len(k), 20, seed=7)
     A = 2.0 * np.sum(np.abs(eta) ** 2, axis=0)
@@ -263,6 +266,100 @@ def test_bcc_uniform_energy_closed_form():
 # Uniform-crystal equilibrium (P1) and its energy (P5)
 # ----------------------------------------------------------------------------------------
 
+def fcc_bulk_by_hand(eta, p):
+    """The FCC bulk energy written out by hand (reading R16).  With sqrt 3 k = (1,1,1), (1,-1,-1),
+    (-1,1,-1), (-1,-1,1), (2,0,0), (0,2,0), (0,0,2):
+      triads   k1 + k2 = k5, k1 + k3 = k6, k1 + k4 = k7, k2 + k3 + k7 = k2 + k4 + k6 = k3 + k4 + k5 = 0;
+      quartets k1 + k2 + k3 + k4 = 0, k1 - k2 = k6 + k7, k1 - k3 = k5 + k7, k1 - k4 = k5 + k6,
+               k2 - k3 = k5 - k6, k2 - k4 = k5 - k7, k3 - k4 = k6 - k7.
+    Coefficients as for bcc: -(2 a3/a0)(T + T^*) per triad, (8 a2/a0)(Q + Q^*) per quartet, pair terms
+    (a1/a0) A + (a2/a0)(A^2 - 2 sum |eta|^4)."""
+    e = eta
+    c = np.conj
+    A = 2.0 * np.sum(np.abs(e) ** 2, axis=0)
+    triads = (e[0] * e[1] * c(e[4]) + e[0] * e[2] * c(e[5]) + e[0] * e[3] * c(e[6]) + e[1] * e[2] * e[6]
+              + e[1] * e[3] * e[5] + e[2] * e[3] * e[4])
+    quartets = (e[0] * e[1] * e[2] * e[3] + e[0] * c(e[1]) * c(e[5]) * c(e[6]) + e[0] * c(e[2]) * c(e[4]) * c(e[6])
+                + e[0] * c(e[3]) * c(e[4]) * c(e[5]) + e[1] * c(e[2]) * c(e[4]) * e[5]
+                + e[1] * c(e[3]) * c(e[4]) * e[6] + e[2] * c(e[3]) * c(e[5]) * e[6])
+    return (p.a1 / p.a0 * A + p.a2 / p.a0 * (A ** 2 - 2.0 * np.sum(np.abs(e) ** 4, axis=0))
+            - 2.0 * p.a3 / p.a0 * 2.0 * triads.real + 8.0 * p.a2 / p.a0 * 2.0 * quartets.real)
+
+
+def test_fcc_lattice_and_resonances():
+    """|k_<111>| = 1, |k_<200>| = 2/sqrt 3, the <111> vectors sum to zero; 6 triads and 7 distinct-index
+    quartets (each with its conjugate) and no other non-pair product; kappa_j = a0 |k_j|^2."""
+    k = fcc_k()
+    np.testing.assert_allclose(np.linalg.norm(k, axis=1), [1, 1, 1, 1, 2 / math.sqrt(3), 2 / math.sqrt(3),
+                                                          2 / math.sqrt(3)], atol=1e-15)
+    np.testing.assert_allclose(k[:4].sum(axis=0), 0.0, atol=1e-15)
+    np.testing.assert_allclose(kappas(k, Params()), 0.98 * np.array([1, 1, 1, 1, 4 / 3, 4 / 3, 4 / 3]), rtol=1e-15)
+    b = BulkEnergy(k, Params())
+    J = 7
+    cubic = [e for e in b.terms if sum(e) == 3]
+    quart_distinct = [e for e in b.terms if sum(e) == 4 and max(e[j] + e[J + j] for j in range(J)) == 1]
+    other = [e for e in b.terms if sum(e) == 4 and max(e[j] + e[J + j] for j in range(J)) >= 2
+             and any(e[j] != e[J + j] for j in range(J))]
+    assert len(cubic) == 12 and len(quart_distinct) == 14 and not other
+
+
+def test_fcc_bulk_matches_hand_polynomial():
+    p = Params(a0=0.9, a1=0.03, a2=0.3, a3=0.7)
+    b = BulkEnergy(fcc_k(), p)
+    eta = rand_eta(7, 40, seed=13)
+    np.testing.assert_allclose(b.f(eta), fcc_bulk_by_hand(eta, p), rtol=1e-13, atol=1e-15)
+
+
+def fcc_two_mode(phi1, phi2, p):
+    """f^s at eta_1..4 = phi1 (<111>), eta_5..7 = phi2 (<200>), from the hand polynomial: A = 8 phi1^2 +
+    6 phi2^2, pair part A^2 - 2 (4 phi1^4 + 3 phi2^4) = 56 phi1^4 + 96 phi1^2 phi2^2 + 30 phi2^4, every triad
+    = phi1^2 phi2, quartet 1 = phi1^4 and the six others = phi1^2 phi2^2."""
+    return ((8 * phi1 ** 2 + 6 * phi2 ** 2) * p.a1 - 24 * p.a3 * phi1 ** 2 * phi2
+            + p.a2 * (72 * phi1 ** 4 + 192 * phi1 ** 2 * phi2 ** 2 + 30 * phi2 ** 4)) / p.a0
+
+
+def test_fcc_uniform_closed_form():
+    """The two-mode polynomial above equals the oracle's f^s; the oracle's relaxed amplitudes are the
+    stationary point of that polynomial (its hand-written gradient 16 a1 - 48 a3 phi2 + 288 a2 phi1^2 +
+    384 a2 phi2^2 = 0, 12 a1 phi2 - 24 a3 phi1^2 + 384 a2 phi1^2 phi2 + 120 a2 phi2^3 = 0, solved by a
+    library root finder) and a lower energy than the single-amplitude crystal; with phi1 = phi2 = phi the
+    polynomial is (14 a1 phi^2 - 24 a3 phi^3 + 294 a2 phi^4)/a0."""
+    import scipy.optimize
+    p = Params()
+    b = BulkEnergy(fcc_k(), p)
+    for p1, p2 in ((0.04, 0.09), (0.11, 0.11), (0.27, 0.13)):
+        eta = np.array([p1] * 4 + [p2] * 3, dtype=complex)[:, None]
+        assert math.isclose(float(b.f(eta)[0]), fcc_two_mode(p1, p2, p), rel_tol=1e-13)
+    phi = 0.11
+    assert math.isclose(fcc_two_mode(phi, phi, p),
+                        (14 * p.a1 * phi ** 2 - 24 * p.a3 * phi ** 3 + 294 * p.a2 * phi ** 4) / p.a0, rel_tol=1e-14)
+
+    def g(x):
+        p1, p2 = x
+        return [16 * p.a1 - 48 * p.a3 * p2 + 288 * p.a2 * p1 ** 2 + 384 * p.a2 * p2 ** 2,
+                12 * p.a1 * p2 - 24 * p.a3 * p1 ** 2 + 384 * p.a2 * p1 ** 2 * p2 + 120 * p.a2 * p2 ** 3]
+    ref = scipy.optimize.fsolve(g, [0.12, 0.12], xtol=1e-14)
+    got = equilibrium_amplitudes(b)
+    np.testing.assert_allclose(got, [ref[0]] * 4 + [ref[1]] * 3, rtol=1e-12)
+    assert fcc_two_mode(ref[0], ref[1], p) < fcc_two_mode(uniform_amplitude(b), uniform_amplitude(b), p) < 0.0
+    # one shell: the equilibrium is the single amplitude of Eq. (5)-(6)
+    np.testing.assert_allclose(equilibrium_amplitudes(BulkEnergy(tri_k(), p)), uniform_amplitude(BulkEnergy(tri_k(), p)))
+
+
+def test_fcc_translation_invariance():
+    """eta_j -> eta_j e^{i k_j.u} leaves the FCC energy unchanged and commutes with the step (every
+    resonant product's wave vectors sum to zero)."""
+    g = Grid(3, (4, 4, 4), (16.0, 16.0, 16.0))
+    o = Oracle(g, fcc_k(), Params())
+    eta = 0.1 + rand_eta(7, g.N, seed=17, scale=0.03)
+    u = np.array([0.7, -1.3, 2.1])
+    ph = np.exp(1j * (fcc_k() @ u))[:, None]
+    assert math.isclose(o.energy(eta * ph), o.energy(eta), rel_tol=1e-12)
+    _, e1 = o.step(eta, 0.8)
+    _, e2 = o.step(eta * ph, 0.8)
+    np.testing.assert_allclose(e2, e1 * ph, rtol=0, atol=1e-12)
+
+
 def test_uniform_amplitude_closed_form():
     """phi = (a3 + sqrt(a3^2 - 40 a1 a2)) / (20 a2) = 0.177459666924148 (triangular)."""
     p = Params()
@@ -271,26 +368,27 @@ def test_uniform_amplitude_closed_form():
     assert math.isclose(phi, 0.177459666924148, rel_tol=1e-14)
 
 
-@pytest.mark.parametrize("lattice", ["tri", "bcc"])
+@pytest.mark.parametrize("lattice", ["tri", "bcc", "fcc"])
 def test_uniform_state_is_fixed_point(lattice):
     """K 1 = T 1 = 0 on the periodic mesh and F^s_j(phi) = 0, so eta_j = phi is reproduced
     by the discrete step; a perturbed uniform state relaxes towards phi."""
     p = Params()
-    k = tri_k() if lattice == "tri" else bcc_k()
+    k = LATTICES[lattice]()
     g = Grid(2, (8, 8), (20.0, 20.0)) if lattice == "tri" else Grid(3, (4, 4, 4), (16.0, 16.0, 16.0))
     o = Oracle(g, k, p)
-    phi = uniform_amplitude(o.bulk)
-    np.testing.assert_allclose(o.bulk.F(np.full((len(k), 1), phi)), 0.0, atol=1e-15)
-    eta = np.full((len(k), g.N), phi, dtype=complex)
+    phi = equilibrium_amplitudes(o.bulk)[:, None]      # one value per shell of |k_j| (FCC: two)
+    np.testing.assert_allclose(o.bulk.F(phi.astype(complex)), 0.0, atol=1e-15)
+    eta = np.broadcast_to(phi, (len(k), g.N)).astype(complex)
     _, e1 = o.step(eta, 1.0)
-    np.testing.assert_allclose(e1, phi, rtol=0, atol=1e-14)
-    pert = np.full((len(k), g.N), 0.9 * phi, dtype=complex)
+    np.testing.assert_allclose(e1, eta, rtol=0, atol=1e-14)
+    pert = 0.9 * eta
     e = pert
     errs = []
     for _ in range(5):
         _, e = o.step(e, 1.0)
         errs.append(np.max(np.abs(e - phi)))
-    assert errs[-1] < errs[0] < 0.1 * phi
+    assert errs[-1] < errs[0] < np.max(np.abs(pert - phi))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
 
 
 def test_uniform_energy_density():
@@ -671,3 +769,85 @@ def test_refinement_indicator_cases():
     hs = refinement_h(g, tri_k(), e, np.zeros(g.N), 10, 1e-2, 1e-3, 0.5, 40.0)
     xs = np.arange(g.N) % 32
     assert np.all(hs[(xs == 15) | (xs == 16)] == 0.5)
+
+
+# ----------------------------------------------------------------------------------------
+# Multigrid V-cycle for L (R17): Galerkin coarse operators and local Fourier analysis
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n", [(2, (16, 12)), (3, (8, 6, 4))])
+def test_multigrid_coarse_operator_is_galerkin(dim, n):
+    """The rediscretised L on the grid of twice the mesh size equals P^T L P for the Q1 interpolation
+    (nested finite-element spaces), and P reproduces constants."""
+    from oracle.apfc_oracle import MultigridL, coarse_grid, interpolation
+    g = Grid(dim, n, tuple(1.7 * v for v in n))
+    mg = MultigridL(g, 0.98, 3.0, coarse_min=2)
+    Lf, P = mg.levels[0]["L"], mg.levels[0]["P"]
+    Lc = mg.levels[1]["L"]
+    assert abs(P.T @ Lf @ P - Lc).max() < 1e-12 * abs(Lc).max()
+    gc = coarse_grid(g)
+    np.testing.assert_allclose(interpolation(gc) @ np.ones(gc.N), 1.0, atol=1e-15)
+
+
+def _cheb_residual(lam, nu, lo, hi):
+    """Residual polynomial of nu Chebyshev iterations for the spectrum interval [lo, hi]:
+    T_nu((theta - lam)/delta) / T_nu(theta/delta) (the textbook form, Saad Sec. 12.3)."""
+    th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+
+    def T(x):
+        return math.cos(nu * math.acos(x)) if abs(x) <= 1.0 else math.cosh(nu * math.acosh(abs(x))) * (
+            1.0 if x > 0 or nu % 2 == 0 else -1.0)
+    return T((th - lam) / de) / T(th / de)
+
+
+def test_two_grid_cycle_matches_local_fourier_analysis():
+    """On a periodic grid a Fourier mode couples only with its harmonics theta + (pi, 0), (0, pi), (pi, pi).
+    With D = diag(L), lam_a = L^_a / D, the symbols R^_a = prod_d (1 + cos(theta_d + a_d pi)) of P^T,
+    R^_a / 4 of P and L^_c of the coarse L at 2 theta, one two-grid cycle from zero maps b = e^{i theta.x} to
+      x1 = s . b,  s_a = (1 - r(lam_a)) / L^_a   (r: the Chebyshev residual polynomial),
+      x2 = x1 + (R^ . (b - L^ . x1)) / L^_c * R^/4,   x3 = x2 + s . (b - L^ . x2),
+    written out here from the symbols; the oracle's cycle (coarsest level solved by 400 Chebyshev
+    iterations, i.e. exactly) must give x3 on the four harmonics."""
+    from oracle.apfc_oracle import MultigridL, plane_wave, symbols_at
+    n, Lside, kap, dt, nu, alpha = 16, 16 * 2.3, 0.98, 5.0, 2, 4.0
+    g = Grid(2, (n, n), (Lside, Lside))
+    mg = MultigridL(g, kap, dt, nu=nu, alpha=alpha, coarse_min=8, coarse_iters=400)
+    assert len(mg.levels) == 2
+    D = mg.levels[0]["L"].diagonal()[0]
+    lo, hi = mg.levels[0]["lam"]
+    gc = mg.levels[1]["grid"]
+    mode = (3, 2)
+    th = [2 * math.pi * mode[d] / n for d in range(2)]
+    harm = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    Lh, R = [], []
+    for a in harm:
+        t = [th[d] + a[d] * math.pi for d in range(2)]
+        Mh, Kh, _ = symbols_at(g, np.zeros(2), t)
+        Lh.append(Mh / math.sqrt(dt) + math.sqrt(kap) * Kh)
+        R.append(np.prod([1.0 + math.cos(t[d]) for d in range(2)]))
+    Lh, R = np.array(Lh), np.array(R)
+    Mc, Kc, _ = symbols_at(gc, np.zeros(2), [2 * t for t in th])
+    Lc = Mc / math.sqrt(dt) + math.sqrt(kap) * Kc
+    s = np.array([(1.0 - _cheb_residual(l / D, nu, hi / alpha, hi)) / l for l in Lh])
+    b = np.array([1.0, 0.0, 0.0, 0.0], dtype=complex)
+    x1 = s * b
+    x2 = x1 + (R @ (b - Lh * x1)) / Lc * R / 4.0
+    x3 = x2 + s * (b - Lh * x2)
+    got = mg.cycle(plane_wave(g, mode))
+    ref = sum(x3[i] * plane_wave(g, (mode[0] + a[0] * n // 2, mode[1] + a[1] * n // 2)) for i, a in enumerate(harm))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.max(np.abs(ref)))
+
+
+def test_multigrid_cycle_is_symmetric_and_contracts():
+    """The V-cycle B is a symmetric operator (the same smoothing polynomial before and after the coarse
+    correction) and I - B L contracts: spectral radius well below the Chebyshev 3-iteration inner solve's at
+    large dt."""
+    from oracle.apfc_oracle import MultigridL
+    g = Grid(2, (32, 32), (32 * 2.26725,) * 2)
+    mg = MultigridL(g, 0.98, 30.0)
+    N = g.N
+    B = np.column_stack([mg.cycle(np.eye(N)[:, i]) for i in range(N)])
+    np.testing.assert_allclose(B, B.T, atol=1e-12 * np.max(np.abs(B)))
+    L = mg.levels[0]["L"].toarray()
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(N) - B @ L)))
+    assert rho < 0.15, rho
