@@ -10,6 +10,8 @@ Workloads (seeded, synthetic, resident in HBM before the timed region starts):
   batch64  64 independent triangular instances of seeded size n^2, n in {128,...,512}, one rotated grain
            each, Delta B ~ U[0.01, 0.05], all in one batched context, 50 steps
   bcc128   128^3 bcc lattice (6 amplitudes), spherical grain rotated 5 degrees about [001], 20 steps
+  fcc128   the same sphere recipe on the FCC lattice (7 amplitudes: <111> and <200> shells, two-shell
+           relaxed amplitudes), side 60 cubic constants, 20 steps
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tri1024|batch64|bcc128]
                     [--precision mixed|fp64] [--no-compare] [--no-variants] [--probe KERNEL] [--no-cpu-baseline]
@@ -39,7 +41,8 @@ sys.path.insert(0, ROOT)
 METRIC = "amplitude DOF-steps/s at 1e-8 rel. residual + % HBM peak; plain vs mixed/batch"
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1902_09761_amd", "csrc")
-KERNEL_SOURCES = ["apfc_internal.h", "kernels_common.h", "kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip"]
+KERNEL_SOURCES = ["apfc_internal.h", "kernels_common.h", "kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip",
+                  "kernels_mg.hip"]
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel families with a byte model, as the library's probe names them, and the kernels they cover
 FAMILIES = {"cheb": "k_cheb2d (3D: k_cb_*)", "apply": "k_apply_dot2d/3d", "proj_final": "k_proj_final",
@@ -53,14 +56,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's run length, 100 / 50 / 20)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tri1024", choices=["tri1024", "batch64", "bcc128"])
+    ap.add_argument("--workload", default="tri1024", choices=["tri1024", "batch64", "bcc128", "fcc128"])
     ap.add_argument("--n", type=int, default=None, help="override the mesh side (tri1024 / bcc128)")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the run in the other precision (FP64 vs mixed: eta and energy differences)")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the batch64 and bcc128 runs that the default workload's line carries")
-    ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb"])
+    ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb", "mg"])
     ap.add_argument("--restart", type=int, default=4)
     ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
                     help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) / cubic (3) "
@@ -80,26 +83,49 @@ def parse():
     ap.add_argument("--tiles", default=None,
                     help="ROWS[,REGION]: fixed tile rows (and fused-preconditioner region) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--study", default=None, choices=["dt"],
+                    help="dt: the time-step sensitivity study on the chosen workload (one JSON line per time step "
+                         "and inner-solver arm, then a markdown table); --steps and --warmup apply to every run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 256 MiB device-to-device (reference for HBM counters)")
     return ap.parse_args()
 
 
+def default_inner_iters(args):
+    """(mass, diffusion) inner iterations: Chebyshev 5/3, multigrid 5 mass iterations and 2 smoothing
+    iterations per side of each V-cycle, the paper's PCG 3/5."""
+    dm, dd = {"cheb": (5, 3), "mg": (5, 2)}.get(args.inner, (3, 5))
+    return args.mass_iters or dm, args.diff_iters or dd
+
+
+_WORKLOADS = {}
+
+
 def make_workload(args, workload):
-    """Returns (lattice, list of inputs.Workload, dim)."""
+    """Returns (lattice, list of inputs.Workload, dim); generated once per (workload, n) in a process."""
+    key = (workload, args.n)
+    if key not in _WORKLOADS:
+        _WORKLOADS[key] = _make_workload(args, workload)
+    return _WORKLOADS[key]
+
+
+def _make_workload(args, workload):
     import numpy as np
     from paper_1902_09761_amd import apfc, inputs
-    kind = apfc.APFC_BCC3D if workload == "bcc128" else apfc.APFC_TRI2D
+    kind = {"bcc128": apfc.APFC_BCC3D, "fcc128": apfc.APFC_FCC3D}.get(workload, apfc.APFC_TRI2D)
     lat = apfc.apfc_lattice_default(kind)
-    dim = 3 if kind == apfc.APFC_BCC3D else 2
+    dim = 2 if kind == apfc.APFC_TRI2D else 3
     kk = np.array(apfc.lattice_k(lat, dim))
 
     def phi_of(dB):
-        return apfc.apfc_uniform_amplitude(lat, apfc.apfc_params_default(a1=0.5 * dB))
+        # one relaxed amplitude per amplitude (FCC: the <111> and <200> shells differ)
+        return apfc.apfc_equilibrium_amplitudes(lat, apfc.apfc_params_default(a1=0.5 * dB))
     if workload == "tri1024":
         wls = [inputs.voronoi_2d(kk, phi_of, n=args.n or 1024, seed=1)]
     elif workload == "batch64":
         wls = inputs.batch_2d(kk, phi_of, count=64, seed=1)
+    elif workload == "fcc128":
+        wls = [inputs.sphere_3d(kk, phi_of, n=args.n or 128, seed=1, spacing=inputs.FCC_SPACING, name="fcc")]
     else:
         wls = [inputs.sphere_3d(kk, phi_of, n=args.n or 128, seed=1)]
     return lat, wls, dim
@@ -111,9 +137,8 @@ def run_gpu(args, precision, probe=None, workload=None, graphs=None):
     workload = workload or args.workload
     lat, wls, dim = make_workload(args, workload)
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
-    inner = apfc.APFC_INNER_CHEB if args.inner == "cheb" else apfc.APFC_INNER_PCG
-    mi = args.mass_iters or (5 if args.inner == "cheb" else 3)
-    di = args.diff_iters or (3 if args.inner == "cheb" else 5)
+    inner = {"cheb": apfc.APFC_INNER_CHEB, "mg": apfc.APFC_INNER_MG}.get(args.inner, apfc.APFC_INNER_PCG)
+    mi, di = default_inner_iters(args)
     ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=prec, inner_kind=inner,
                                    restart=args.restart, mass_iters=mi, diff_iters=di, x0_order=args.x0)
           for w in wls]
@@ -286,8 +311,8 @@ def measure(args, workload, precision, probe, compare, graphs=None):
                       "amplitude_dofs": res["dofs"], "J": res["J"], "dt": res["dt"], "rtol": 1e-8,
                       "precision": precision, "inner": args.inner, "restart": args.restart,
                       "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
-                      "mass_iters": args.mass_iters or (5 if args.inner == "cheb" else 3),
-                      "diff_iters": args.diff_iters or (3 if args.inner == "cheb" else 5), "x0_order": args.x0,
+                      "mass_iters": default_inner_iters(args)[0], "diff_iters": default_inner_iters(args)[1],
+                      "x0_order": args.x0,
                       "graphs": res["graphs"], "entry": "apfc_step" if args.per_step else "apfc_run"}}
     timed = rooflines(res)
     if timed:
@@ -313,13 +338,54 @@ def measure(args, workload, precision, probe, compare, graphs=None):
     return out
 
 
+STUDY_DT = [0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0]
+# (label, inner solver, mass iterations, diffusion iterations / smoothing iterations, initial-guess order, time steps)
+STUDY_ARMS = [("PCG 3/5 (paper), x0 0", "pcg", 3, 5, 0, STUDY_DT),
+              ("Chebyshev 5/3, x0 0", "cheb", 5, 3, 0, STUDY_DT),
+              ("Chebyshev 5/3, x0 3", "cheb", 5, 3, 3, STUDY_DT),
+              ("Chebyshev 5/6, x0 0", "cheb", 5, 6, 0, STUDY_DT),
+              ("multigrid 5/nu=1, x0 0", "mg", 5, 1, 0, STUDY_DT),
+              ("multigrid 5/nu=2, x0 0", "mg", 5, 2, 0, STUDY_DT),
+              ("PCG 20/20 (inner solves ~exact), x0 0", "pcg", 20, 20, 0, [1.0, 10.0, 100.0])]
+
+
+def dt_study(args):
+    """FGMRES iterations per step (slowest system) and wall time per step against dt for each inner-solver
+    arm: the analogue of the paper's Fig. 4(a).  Prints one JSON line per run, then a markdown table."""
+    import numpy as np
+    rows = {}
+    for label, inner, mi, di, x0, dts in STUDY_ARMS:
+        for dt in dts:
+            args.inner, args.mass_iters, args.diff_iters, args.x0, args.dt = inner, mi, di, x0, dt
+            res = run_gpu(args, args.precision, probe=None)
+            r = {"arm": label, "dt": dt, "ms_per_step": 1e3 * res["sec"] / args.steps,
+                 "fgmres_iters_per_step": float(np.mean(res["iters"])), "final_relres": res["relres"],
+                 "workload": res["workload"], "steps": args.steps, "warmup": args.warmup,
+                 "tiles": res["tile_rows"]}
+            rows[(label, dt)] = r
+            print(json.dumps(r), flush=True)
+    print("| dt | " + " | ".join(a[0] for a in STUDY_ARMS) + " |")
+    print("|---" * (len(STUDY_ARMS) + 1) + "|")
+    for dt in STUDY_DT:
+        cells = []
+        for a in STUDY_ARMS:
+            r = rows.get((a[0], dt))
+            cells.append("—" if r is None else f"{r['fgmres_iters_per_step']:.1f} its, {r['ms_per_step']:.2f} ms")
+        print(f"| {dt:g} | " + " | ".join(cells) + " |", flush=True)
+
+
 def main():
     args = parse()
-    if args.steps is None:
-        args.steps = {"tri1024": 100, "batch64": 50, "bcc128": 20}[args.workload]
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.study == "dt":
+        if args.steps is None:
+            args.steps = 10
+        dt_study(args)
+        return
+    if args.steps is None:
+        args.steps = {"tri1024": 100, "batch64": 50, "bcc128": 20, "fcc128": 20}[args.workload]
     probe = None if args.probe in ("", "none") else args.probe
     K = args.steps
     m = measure(args, args.workload, args.precision, probe, args.compare)
@@ -347,7 +413,7 @@ def main():
     if "other_precision" in m:
         variants.update(m["other_precision"])
     if args.variants and args.workload == "tri1024" and args.n is None:
-        for wl in ("batch64", "bcc128"):
+        for wl in ("batch64", "bcc128", "fcc128"):
             v = measure(args, wl, args.precision, probe, args.compare)
             v.pop("kernels", None)
             variants[wl] = v

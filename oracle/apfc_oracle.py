@@ -39,13 +39,13 @@ R9  Periodic boundary conditions; zeta^0 = M^{-1} G eta^0.
 R10 bcc lattice: k_j = the six unit <110>/sqrt(2) vectors; f^s is the zero-wave-vector
     part of (a1/a0) n^2 - a3/(3 a0) n^3 + a2/(3 a0) n^4 with n from Eq. (1).  For the
     triangular lattice this reproduces Eq. (5)-(6) exactly.
-R17 Multigrid inner solve (the paper uses one algebraic V-cycle from a library): a geometric V-cycle on
-    the structured mesh, coarse operators by rediscretisation (equal to the Galerkin products), symmetric
-    Chebyshev-Jacobi smoothing; see MultigridL.
 R16 FCC lattice (J = 7; the paper takes its vectors and bulk polynomial from another work): the
     first two shells of the fcc reciprocal lattice, four <111>/sqrt 3 vectors (one of each +- pair,
     chosen to sum to zero, |k| = 1) and three <200>/sqrt 3 vectors (|k| = 2/sqrt 3); f^s by the same
     enumeration as R10.
+R17 Multigrid inner solve (the paper uses one algebraic V-cycle from a library): a geometric V-cycle on
+    the structured mesh, coarse operators by rediscretisation (equal to the Galerkin products), symmetric
+    Chebyshev-Jacobi smoothing; see MultigridL.
 """
 from __future__ import annotations
 

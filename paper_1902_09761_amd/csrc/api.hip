@@ -941,6 +941,9 @@ int refresh_dt(apfc_ctx* c, double dt, hipStream_t st) {
     if (dt != c->dt) {
         set_dt_scalars(*c, dt);
         HIPCHK(hipMemcpyAsync(c->d_sys, c->sys.data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
+        // the multigrid levels' dt scalars and smoothing tables as well
+        for (int l = 0; l < c->mg_n; ++l)
+            HIPCHK(hipMemcpyAsync(c->d_mg_sys[l], c->mg_sys[l].data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }
     return APFC_OK;
@@ -1805,6 +1808,11 @@ int attach_scratch(apfc_ctx* c, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(c->d_chunks, c->chunks.data(), sizeof(Chunk) * c->chunks.size(), hipMemcpyHostToDevice, st));
     if (!c->ctiles.empty())
         HIPCHK(hipMemcpyAsync(c->d_ctiles, c->ctiles.data(), sizeof(CTile) * c->ctiles.size(), hipMemcpyHostToDevice, st));
+    for (int l = 0; l < c->mg_n; ++l) {
+        HIPCHK(hipMemcpyAsync(c->d_mg_sys[l], c->mg_sys[l].data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->d_mg_tiles[l], c->mg_tiles[l].data(), sizeof(Tile) * c->mg_tiles[l].size(),
+                              hipMemcpyHostToDevice, st));
+    }
     hipLaunchKernelGGL(k_zero_ints, dim3((c->S + 255) / 256), dim3(256), 0, st, c->kr.tick_c, c->S);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, c->kr.tick_p, 1);
     HIPCHK(hipGetLastError());
