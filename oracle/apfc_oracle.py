@@ -46,6 +46,10 @@ R16 FCC lattice (J = 7; the paper takes its vectors and bulk polynomial from ano
 R17 Multigrid inner solve (the paper uses one algebraic V-cycle from a library): a geometric V-cycle on
     the structured mesh, coarse operators by rediscretisation (equal to the Galerkin products), symmetric
     Chebyshev-Jacobi smoothing; see MultigridL.
+R18 Separable mass inverse (an alternative to the paper's iterative inner solve of step 1 of P^{-1}): on
+    the uniform periodic mesh M is the Kronecker product of 1D mass matrices, so M^{-1} is the Kronecker
+    product of their inverses, whose entries decay geometrically; truncated to R neighbours per
+    direction; see separable_mass_inverse.
 """
 from __future__ import annotations
 
@@ -499,11 +503,14 @@ class Oracle:
             ll.append((Mh / math.sqrt(dt) + math.sqrt(kap) * Kh) / DL)
         return (min(lm), max(lm)), (min(ll), max(ll))
 
-    def precond_apply(self, j, beta1, beta2, dt, inner=None, mass_iters=3, diff_iters=5, mg_options=None):
+    def precond_apply(self, j, beta1, beta2, dt, inner=None, mass_iters=3, diff_iters=5, mg_options=None,
+                      mass="iter"):
         """x = P^{-1} b by the four steps; inner=None uses exact (direct) inner solves,
         inner='pcg' uses fixed-count Jacobi-preconditioned CG from a zero start, inner='cheb'
         fixed-count Chebyshev iteration with the exact Jacobi spectral bounds, inner='mg' one multigrid
-        V-cycle for each L solve (MultigridL with mg_options) and Chebyshev for the mass solve."""
+        V-cycle for each L solve (MultigridL with mg_options) and Chebyshev for the mass solve.
+        mass='sep' replaces the mass solve of step 1 by the separable inverse with R = mass_iters
+        neighbours per direction (R18)."""
         kap = self.kappa[j]
         L = (self.M / math.sqrt(dt) + math.sqrt(kap) * self.K).tocsc()
         if inner is None:
@@ -521,6 +528,9 @@ class Oracle:
             bm, bl = self.jacobi_bounds(j, dt)
             solve_M = lambda b: chebyshev(self.M, b, mass_iters, *bm)
             solve_L = lambda b: chebyshev(L.tocsr(), b, diff_iters, *bl)
+        if mass == "sep":
+            W = separable_mass_inverse(self.grid, mass_iters)
+            solve_M = lambda b: W @ b
         b1p = solve_M(beta1)                                   # step 1
         b2p = solve_L(beta2 - kap * (self.G[j] @ b1p))         # step 2
         chi2 = solve_L(self.M @ b2p)                           # step 3
@@ -540,6 +550,38 @@ class Oracle:
         Minv = np.linalg.inv(M)
         upper = np.block([[np.eye(N), Minv @ K], [np.zeros((N, N)), Minv @ L]])
         return lower @ upper
+
+
+# ---------------------------------------------------------------------------------------
+# Separable approximate inverse of the mass matrix (R18)
+# ---------------------------------------------------------------------------------------
+
+def separable_mass_inverse(grid: Grid, R: int) -> sp.csr_matrix:
+    """W ~ M^{-1} for step 1 of P^{-1} (R18).
+
+    The 1D linear-element mass matrix on a uniform mesh is (h/6) tridiag(1, 4, 1).  On an unbounded
+    line its inverse is the Toeplitz matrix with entries (sqrt(3)/h) rho^|i-l|, where rho = sqrt(3) - 2
+    is the root of modulus below one of rho^2 + 4 rho + 1 = 0 (the recurrence the rows of the inverse
+    satisfy away from the diagonal; the diagonal row fixes the factor: (h/6)(4 + 2 rho) sqrt(3)/h = 1).
+    The Q1 mass matrix of the uniform quad/hex mesh is the Kronecker product of the 1D mass matrices of
+    the directions, so W = kron of the 1D operators, each truncated to |i - l| <= R and wrapped
+    periodically (taps that land on the same node add up)."""
+    rho = math.sqrt(3.0) - 2.0
+    c = math.sqrt(3.0) / grid.h
+
+    def one(n):
+        rows, cols, vals = [], [], []
+        for i in range(n):
+            for k in range(-R, R + 1):
+                rows.append(i)
+                cols.append((i + k) % n)
+                vals.append(c * rho ** abs(k))
+        return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))   # duplicates are summed
+
+    W = one(grid.n[0])
+    for d in range(1, grid.dim):                 # x fastest: kron(z, y, x)
+        W = sp.kron(one(grid.n[d]), W)
+    return W.tocsr()
 
 
 # ---------------------------------------------------------------------------------------

@@ -851,3 +851,56 @@ def test_multigrid_cycle_is_symmetric_and_contracts():
     L = mg.levels[0]["L"].toarray()
     rho = np.max(np.abs(np.linalg.eigvals(np.eye(N) - B @ L)))
     assert rho < 0.15, rho
+
+
+# ----------------------------------------------------------------------------------------
+# Separable mass inverse (R18)
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,R", [(2, (36, 40), 22), (3, (12, 10, 14), 24)])
+def test_separable_mass_inverse_tends_to_the_exact_inverse(dim, n, R):
+    """With R past the half-period of every direction the wrapped taps sum all periodic images up to
+    rho^(R+1): W equals the inverse of the element-assembled mass matrix (a direct solve) to that order."""
+    from oracle.apfc_oracle import separable_mass_inverse
+    h = 0.37
+    g = Grid(dim, n, tuple(h * v for v in n))
+    M = assemble(g, tri_k() if dim == 2 else bcc_k())[0]
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    ref = spla.spsolve(M.tocsc().astype(complex), b)
+    got = separable_mass_inverse(g, R) @ b
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dim,R", [(2, 1), (2, 3), (3, 2)])
+def test_separable_mass_inverse_defect_closed_form(dim, R):
+    """M W - I for the truncated 1D inverse has, per direction, the entries -(sqrt 3/6) rho^(R+1) at
+    offsets +-R and (sqrt 3/6) rho^R at +-(R+1) (rho = sqrt 3 - 2) and nothing else; for the Kronecker
+    product the absolute row sum is (1 + e1)^dim - 1 with e1 = (sqrt 3/3) |rho|^R (1 + |rho|)."""
+    from oracle.apfc_oracle import separable_mass_inverse
+    n = (20, 16, 12)[:dim]
+    g = Grid(dim, n, tuple(0.8 * v for v in n))
+    M = assemble(g, tri_k() if dim == 2 else bcc_k())[0]
+    D = (M @ separable_mass_inverse(g, R)).toarray() - np.eye(g.N)
+    rho = math.sqrt(3.0) - 2.0
+    e1 = math.sqrt(3.0) / 3.0 * abs(rho) ** R * (1.0 + abs(rho))
+    np.testing.assert_allclose(np.abs(D).sum(axis=1), (1.0 + e1) ** dim - 1.0, rtol=1e-11)
+    i = 5 + 5 * n[0]                     # an interior node (x = 5, y = 5)
+    np.testing.assert_allclose(D[i, i + R], -math.sqrt(3.0) / 6.0 * rho ** (R + 1), rtol=1e-11)
+    np.testing.assert_allclose(D[i, i + R + 1], math.sqrt(3.0) / 6.0 * rho ** R, rtol=1e-11)
+    if R >= 2:
+        np.testing.assert_allclose(D[i, i + 1], 0.0, atol=1e-13)
+    np.testing.assert_allclose(D[i, i], 0.0, atol=1e-13)
+
+
+def test_precond_with_separable_mass_reduces_to_exact_inner_solves():
+    """P^{-1} with the separable mass inverse of large R and direct L solves equals P^{-1} with direct
+    inner solves (the four steps of Eq. (12))."""
+    g = Grid(2, (16, 12), (16 * 1.3, 12 * 1.3))
+    o = Oracle(g, tri_k(), Params.from_dB(0.02))
+    rng = np.random.default_rng(4)
+    b1, b2 = (rng.normal(size=g.N) + 1j * rng.normal(size=g.N) for _ in range(2))
+    ref = o.precond_apply(1, b1, b2, 2.0)
+    got = o.precond_apply(1, b1, b2, 2.0, mass="sep", mass_iters=20)
+    for x, y in zip(got, ref):
+        assert np.max(np.abs(x - y)) <= 1e-10 * np.max(np.abs(y))
