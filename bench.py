@@ -42,12 +42,12 @@ METRIC = "amplitude DOF-steps/s at 1e-8 rel. residual + % HBM peak; plain vs mix
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1902_09761_amd", "csrc")
 KERNEL_SOURCES = ["apfc_internal.h", "kernels_common.h", "kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip",
-                  "kernels_mg.hip"]
+                  "kernels_mg.hip", "kernels_mass.hip"]
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel families with a byte model, as the library's probe names them, and the kernels they cover
 FAMILIES = {"cheb": "k_cheb2d (3D: k_cb_*)", "apply": "k_apply_dot2d/3d", "proj_final": "k_proj_final",
             "residual": "k_residual2d/3d", "extrapolate": "k_extrapolate", "rhs": "k_rhs_nonlinear",
-            "pcg_spmv": "k_cg_spmv", "pcg_update": "k_cg_update"}
+            "pcg_spmv": "k_cg_spmv", "pcg_update": "k_cg_update", "mass": "k_mass_sep"}
 
 
 def parse():
@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the batch64 and bcc128 runs that the default workload's line carries")
     ap.add_argument("--inner", default="cheb", choices=["pcg", "cheb", "mg"])
+    ap.add_argument("--mass", default="sep", choices=["iter", "sep"],
+                    help="step 1 of the preconditioner: inner iterations (iter) or the separable mass inverse "
+                         "with --mass-iters taps per side (sep)")
     ap.add_argument("--restart", type=int, default=4)
     ap.add_argument("--x0", type=int, default=3, choices=[0, 1, 2, 3],
                     help="FGMRES initial guess: state of the last step (0) or its linear (1) / quadratic (2) / cubic (3) "
@@ -93,8 +96,11 @@ def parse():
 
 def default_inner_iters(args):
     """(mass, diffusion) inner iterations: Chebyshev 5/3, multigrid 5 mass iterations and 2 smoothing
-    iterations per side of each V-cycle, the paper's PCG 3/5."""
+    iterations per side of each V-cycle, the paper's PCG 3/5; with the separable mass inverse the mass
+    count is its taps per side (3)."""
     dm, dd = {"cheb": (5, 3), "mg": (5, 2)}.get(args.inner, (3, 5))
+    if args.mass == "sep":
+        dm = 3
     return args.mass_iters or dm, args.diff_iters or dd
 
 
@@ -139,8 +145,10 @@ def run_gpu(args, precision, probe=None, workload=None, graphs=None):
     prec = apfc.APFC_MIXED if precision == "mixed" else apfc.APFC_FP64
     inner = {"cheb": apfc.APFC_INNER_CHEB, "mg": apfc.APFC_INNER_MG}.get(args.inner, apfc.APFC_INNER_PCG)
     mi, di = default_inner_iters(args)
+    mk = apfc.APFC_MASS_SEPARABLE if args.mass == "sep" else apfc.APFC_MASS_ITER
     ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=prec, inner_kind=inner,
-                                   restart=args.restart, mass_iters=mi, diff_iters=di, x0_order=args.x0)
+                                   restart=args.restart, mass_iters=mi, diff_iters=di, x0_order=args.x0,
+                                   mass_kind=mk)
           for w in wls]
     ms = [apfc.make_mesh(dim, w.mesh.n, w.mesh.length) for w in wls]
     s = apfc.Solver(ms, lat, ps)
@@ -311,7 +319,8 @@ def measure(args, workload, precision, probe, compare, graphs=None):
                       "amplitude_dofs": res["dofs"], "J": res["J"], "dt": res["dt"], "rtol": 1e-8,
                       "precision": precision, "inner": args.inner, "restart": args.restart,
                       "tile_rows": res["tile_rows"][0], "precond_region": res["tile_rows"][1],
-                      "mass_iters": default_inner_iters(args)[0], "diff_iters": default_inner_iters(args)[1],
+                      "mass": args.mass, "mass_iters": default_inner_iters(args)[0],
+                      "diff_iters": default_inner_iters(args)[1],
                       "x0_order": args.x0,
                       "graphs": res["graphs"], "entry": "apfc_step" if args.per_step else "apfc_run"}}
     timed = rooflines(res)

@@ -26,6 +26,7 @@ APFC_ERR_NONFINITE = -4
 APFC_TRI2D, APFC_BCC3D, APFC_CUSTOM, APFC_FCC3D = 0, 1, 2, 3
 APFC_FP64, APFC_MIXED = 0, 1
 APFC_INNER_PCG, APFC_INNER_CHEB, APFC_INNER_MG = 0, 1, 2
+APFC_MASS_ITER, APFC_MASS_SEPARABLE = 0, 1
 APFC_OP_A, APFC_OP_PINV = 0, 1
 
 EXPORTS = ["apfc_params_default", "apfc_lattice_default", "apfc_uniform_amplitude", "apfc_equilibrium_amplitudes",
@@ -49,7 +50,7 @@ class apfc_params(ctypes.Structure):
     _fields_ = [("a0", c_double), ("a1", c_double), ("a2", c_double), ("a3", c_double),
                 ("picard_iters", c_int), ("rtol", c_double), ("restart", c_int), ("max_iters", c_int),
                 ("precision", c_int), ("mass_iters", c_int), ("diff_iters", c_int), ("inner_kind", c_int),
-                ("x0_order", c_int)]
+                ("x0_order", c_int), ("mass_kind", c_int)]
 
 
 class apfc_state(ctypes.Structure):

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip", "kernels_mg.hip", "api.hip"]
+SOURCES = ["kernels.hip", "kernels_apply.hip", "kernels_cheb2d.hip", "kernels_mg.hip", "kernels_mass.hip", "api.hip"]
 LIB = os.path.join(HERE, "libapfc.so")
 ARCH = "gfx950"
 

@@ -15,6 +15,9 @@ constexpr int kMaxJ = 8;
 constexpr int kMaxTerms = 24;
 constexpr int kMaxRestart = 32;
 constexpr int kMaxCheb = 64;     // Chebyshev iterations per inner solve
+constexpr int kMassRMax = 4;     // taps per side of the separable mass inverse
+// bricks of the separable mass inverse: 64 x kMassBY nodes per plane, kMassBZ planes (3D), 512 threads
+constexpr int kMassBY = 8, kMassBZ = 16, kMassThreads = 512;
 
 // Complex value stored as two reals (re, im), 2*sizeof(R)-aligned for vector loads.
 template <typename R>
@@ -45,6 +48,8 @@ struct Sys {
     // with rho_0 = delta/theta, rho_j = 1/(2 theta/delta - rho_{j-1}).  Indexed dynamically, so kernels
     // read it through the Sys pointer, not from a local copy.
     double cb[2][kMaxCheb][2];
+    // 1D taps of the separable mass inverse, wsep[k] = (sqrt(3)/h) rho^k, rho = sqrt(3) - 2 (k <= kMassRMax)
+    double wsep[kMassRMax + 1];
 };
 
 struct Tile { int sys, x0, y0, z; };
@@ -76,7 +81,7 @@ enum Slot { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kBB = 4, kE0 = 5, kE1 = 6, k
 enum KernelId {
     KID_ALL = -2, KID_NONE = -1, KID_PCG_SPMV = 0, KID_PCG_UPDATE, KID_PCG_INIT, KID_PC_FINAL, KID_APPLY,
     KID_RESIDUAL, KID_GS, KID_PROJ_FINAL, KID_XUPDATE, KID_REDUCE, KID_SMALL, KID_OTHER, KID_CHEB, KID_EXTRAP,
-    KID_RHS, KID_MG, KID_COUNT
+    KID_RHS, KID_MG, KID_MASS, KID_COUNT
 };
 const char* kernel_name(int kid);
 int kernel_id(const char* name);
@@ -99,6 +104,8 @@ struct Dev {
     const Sys* sys = nullptr;        // device [S]
     const Tile* tiles = nullptr;     // device [ntiles]
     const Chunk* chunks = nullptr;   // device [nchunks]
+    const Tile* mtiles = nullptr;    // device [nmtiles]: bricks of the separable mass inverse
+    int nmtiles = 0;
     int ntiles = 0, nchunks = 0, S = 0, TY = 16, J = 0, count = 0, dim = 2;
     long long NT = 0;                // half-vector length (complex values)
     Terms terms{};
@@ -176,18 +183,26 @@ void launch_apply(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, cons
 
 template <typename T>
 void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
-                    cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+                    cx<T>* q, double* part, int mass_iters, int diff_iters, int mass_sep, const int* mask,
+                    hipStream_t st);
 
+// mass_sep > 0 (every preconditioner launcher): step 1 by the separable mass inverse with mass_sep taps per
+// side (launch_mass_sep) instead of mass_iters inner iterations.
 // vscale (may be null): the input is vscale[sys] * rv instead of v, and that scaled vector is also
 // stored to vout
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
-                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st);
+                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep,
+                         const double* vscale, const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st);
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
-                                 cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st);
+                                 cx<T>* d1, int mass_iters, int diff_iters, int mass_sep, const int* mask,
+                                 hipStream_t st);
+// x1 = W beta1 (beta1 = the zeta part of v): the separable approximate inverse of the mass matrix, taps
+// Sys::wsep[0..R] in every direction, on the bricks d.mtiles (kernels_mass.hip).
+template <typename T>
+void launch_mass_sep(const Dev& d, int R, const cx<T>* v, cx<T>* x1, const int* mask, hipStream_t st);
 
 void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool chunk_ranges, double* out, int ld,
                    const int* mask, hipStream_t st);
@@ -221,11 +236,12 @@ void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd*
 template <typename T>
 void launch_mg_vcycle(const Dev& fine, const MgLevels& mg, const cx<T>* b, cx<T>* x, cx<T>* r, cx<T>* d0, cx<T>* d1,
                       const int* mask, hipStream_t st);
-// The block preconditioner with the multigrid L solves: step 1 by mass_iters Chebyshev iterations, steps 2
-// and 3 by one V-cycle each, step 4.
+// The block preconditioner with the multigrid L solves: step 1 by mass_iters Chebyshev iterations (or the
+// separable mass inverse), steps 2 and 3 by one V-cycle each, step 4.
 template <typename T>
 void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r,
-                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, const int* mask, hipStream_t st);
+                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, int mass_sep, const int* mask,
+                       hipStream_t st);
 void launch_energy_parts(const Dev& d, const zd* eta, const zd* zeta, double* part, hipStream_t st);
 void launch_energy_grad(const Dev& d, const zd* eta, const zd* zeta, double* const* grad_tab, double* part,
                         hipStream_t st);

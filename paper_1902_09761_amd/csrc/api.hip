@@ -126,6 +126,8 @@ struct apfc_ctx {
     std::vector<Chunk> chunks;
     std::vector<CTile> ctiles;
     CTile* d_ctiles = nullptr;
+    std::vector<Tile> mtiles;          // bricks of the separable mass inverse (APFC_MASS_SEPARABLE)
+    Tile* d_mtiles = nullptr;
     int cheb_shape = 0;
     size_t max_ctiles = 0;
     long long NT = 0, NI = 0;
@@ -203,6 +205,8 @@ struct apfc_ctx {
         d.sys = d_sys;
         d.tiles = d_tiles;
         d.chunks = d_chunks;
+        d.mtiles = d_mtiles;
+        d.nmtiles = (int)mtiles.size();
         d.ntiles = (int)tiles.size();
         d.nchunks = (int)chunks.size();
         d.S = S;
@@ -327,6 +331,15 @@ void set_dt_scalars(apfc_ctx& c, double dt) {
     c.dt = dt;
 }
 
+// 1D taps of the separable mass inverse: the inverse of (h/6) tridiag(1, 4, 1) on an unbounded uniform
+// mesh has the entries (sqrt(3)/h) rho^|k| with rho = sqrt(3) - 2 (the root of modulus below one of
+// rho^2 + 4 rho + 1 = 0).
+void set_wsep(Sys& y) {
+    const double rho = std::sqrt(3.0) - 2.0;
+    double t = std::sqrt(3.0) / y.h;
+    for (int k = 0; k <= kMassRMax; ++k, t *= rho) y.wsep[k] = t;
+}
+
 // The multigrid levels (APFC_INNER_MG): coarsen all systems together while every direction of every
 // system is even and its half at least kMgCoarseMin nodes (16 in 2D, 8 in 3D); a coarse level is the
 // same periodic domain with twice the mesh size.  The coarsest level of each system must hold at most
@@ -356,6 +369,7 @@ int build_mg_levels(apfc_ctx& c) {
             off += y.N;
             y.h *= 2.0;
             y.w = std::pow(y.h, y.dim);
+            set_wsep(y);
             y.diagM = std::pow(2.0 * y.h / 3.0, y.dim);
             y.diagK = y.dim * (2.0 / y.h) * std::pow(2.0 * y.h / 3.0, y.dim - 1);
             y.tbeg = (int)c.mg_tiles[l].size();
@@ -382,7 +396,23 @@ int build_mg_levels(apfc_ctx& c) {
     return APFC_OK;
 }
 
-int cheb_halo(const apfc_params& p) { return std::max(p.mass_iters - 1, p.diff_iters); }
+// Halo of the fused 2D Chebyshev regions: stage 0 needs mass_iters - 1 stencil layers (or mass_iters taps of
+// the separable mass inverse), stages 1 and 2 one layer for G x1 or M x2 plus diff_iters - 1.
+int cheb_halo(const apfc_params& p) {
+    return std::max(p.mass_kind == APFC_MASS_SEPARABLE ? p.mass_iters : p.mass_iters - 1, p.diff_iters);
+}
+
+// Bricks of the separable mass inverse: 64 x kMassBY nodes per plane, kMassBZ planes (3D).
+void build_mtiles(apfc_ctx& c) {
+    c.mtiles.clear();
+    if (c.solver.mass_kind != APFC_MASS_SEPARABLE) return;
+    for (int s = 0; s < c.S; ++s) {
+        const Sys& y = c.sys[s];
+        for (int z0 = 0; z0 < y.nz; z0 += (y.dim == 3 ? kMassBZ : 1))
+            for (int y0 = 0; y0 < y.ny; y0 += kMassBY)
+                for (int x0 = 0; x0 < y.nx; x0 += kTX) c.mtiles.push_back(Tile{s, x0, y0, z0});
+    }
+}
 
 void build_ctiles(apfc_ctx& c) {
     c.ctiles.clear();
@@ -407,6 +437,8 @@ int upload_tables(apfc_ctx& c) {
     HIPCHK(hipMemcpy(c.d_chunks, c.chunks.data(), sizeof(Chunk) * c.chunks.size(), hipMemcpyHostToDevice));
     if (!c.ctiles.empty())
         HIPCHK(hipMemcpy(c.d_ctiles, c.ctiles.data(), sizeof(CTile) * c.ctiles.size(), hipMemcpyHostToDevice));
+    if (!c.mtiles.empty())
+        HIPCHK(hipMemcpy(c.d_mtiles, c.mtiles.data(), sizeof(Tile) * c.mtiles.size(), hipMemcpyHostToDevice));
     return APFC_OK;
 }
 
@@ -433,6 +465,7 @@ size_t carve(apfc_ctx& c, char* base) {
     c.d_tiles = (Tile*)take(sizeof(Tile) * c.max_tiles);
     c.d_chunks = (Chunk*)take(sizeof(Chunk) * c.chunks.size());
     c.d_ctiles = (CTile*)take(sizeof(CTile) * std::max<size_t>(1, c.max_ctiles));
+    c.d_mtiles = (Tile*)take(sizeof(Tile) * std::max<size_t>(1, c.mtiles.size()));
     c.d_tab = (double**)take(sizeof(double*) * 4 * c.count);
     c.X = (zd*)take(sizeof(zd) * 2 * NT);
     c.B = (zd*)take(sizeof(zd) * 2 * NT);
@@ -548,6 +581,10 @@ int check_params(const apfc_params& p) {
     if (p.inner_kind != APFC_INNER_PCG && p.inner_kind != APFC_INNER_CHEB && p.inner_kind != APFC_INNER_MG)
         return fail(APFC_ERR_INVALID, "params.inner_kind");
     if (p.x0_order < 0 || p.x0_order > 3) return fail(APFC_ERR_INVALID, "params.x0_order must be in [0,3]");
+    if (p.mass_kind != APFC_MASS_ITER && p.mass_kind != APFC_MASS_SEPARABLE)
+        return fail(APFC_ERR_INVALID, "params.mass_kind");
+    if (p.mass_kind == APFC_MASS_SEPARABLE && p.mass_iters > kMassRMax)
+        return fail(APFC_ERR_INVALID, "params: APFC_MASS_SEPARABLE takes mass_iters in [1,4] (taps per side)");
     return APFC_OK;
 }
 
@@ -601,6 +638,7 @@ void apfc_params_default(apfc_params* p) {
     p->diff_iters = 5;
     p->inner_kind = APFC_INNER_PCG;
     p->x0_order = 0;
+    p->mass_kind = APFC_MASS_ITER;
 }
 
 int apfc_lattice_default(int kind, apfc_lattice* L) {
@@ -803,6 +841,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
             y.doff = doff;
             y.h = h;
             y.w = std::pow(h, dim);
+            set_wsep(y);
             double k2 = 0.0;
             for (int q = 0; q < 3; ++q) {
                 y.kv[q] = lattice->k[j][q];
@@ -835,6 +874,7 @@ int apfc_create_batch(int count, const apfc_mesh* meshes, const apfc_lattice* la
             return rc;
         }
     }
+    build_mtiles(*c);
     std::vector<Tile> t4;
     build_tiles(*c, 4, t4);
     c->max_tiles = (int)t4.size();
@@ -1011,19 +1051,20 @@ template <typename T>
 void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mask, hipStream_t st,
              const double* vscale = nullptr, const cx<T>* rv = nullptr, cx<T>* vout = nullptr) {
     cx<T>** pc = (cx<T>**)c->pc;
+    const int sep = c->solver.mass_kind == APFC_MASS_SEPARABLE ? c->solver.mass_iters : 0;
     if (c->solver.inner_kind == APFC_INNER_MG)
         launch_precond_mg<T>(d, mg_levels(c, d), v, z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5],
-                             c->solver.mass_iters, mask, st);
+                             c->solver.mass_iters, sep, mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
-                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, vscale, rv, vout, mask,
-                               st);
+                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, sep, vscale, rv, vout,
+                               mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB)
         launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
-                                       c->solver.diff_iters, mask, st);
+                                       c->solver.diff_iters, sep, mask, st);
     else
         launch_precond<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], pc[5], c->tpart, c->solver.mass_iters,
-                          c->solver.diff_iters, mask, st);
+                          c->solver.diff_iters, sep, mask, st);
 }
 
 // The fused 2D Chebyshev preconditioner normalises the first basis vector of a cycle itself (reading
@@ -1808,6 +1849,8 @@ int attach_scratch(apfc_ctx* c, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(c->d_chunks, c->chunks.data(), sizeof(Chunk) * c->chunks.size(), hipMemcpyHostToDevice, st));
     if (!c->ctiles.empty())
         HIPCHK(hipMemcpyAsync(c->d_ctiles, c->ctiles.data(), sizeof(CTile) * c->ctiles.size(), hipMemcpyHostToDevice, st));
+    if (!c->mtiles.empty())
+        HIPCHK(hipMemcpyAsync(c->d_mtiles, c->mtiles.data(), sizeof(Tile) * c->mtiles.size(), hipMemcpyHostToDevice, st));
     for (int l = 0; l < c->mg_n; ++l) {
         HIPCHK(hipMemcpyAsync(c->d_mg_sys[l], c->mg_sys[l].data(), sizeof(Sys) * c->S, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(c->d_mg_tiles[l], c->mg_tiles[l].data(), sizeof(Tile) * c->mg_tiles[l].size(),

@@ -1290,7 +1290,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(const Sys* sys, const Ti
 // ------------------------------------------------------------------------------------------
 static const char* kNames[KID_COUNT] = {"pcg_spmv", "pcg_update", "pcg_init", "pc_final", "apply", "residual",
                                         "gs",       "proj_final", "xupdate",  "reduce",   "small", "other",
-                                        "cheb",     "extrapolate", "rhs",  "mg"};
+                                        "cheb",     "extrapolate", "rhs",  "mg",    "mass"};
 const char* kernel_name(int kid) { return (kid >= 0 && kid < KID_COUNT) ? kNames[kid] : (kid == KID_ALL ? "all" : "none"); }
 int kernel_id(const char* name) {
     if (!name) return KID_NONE;
@@ -1477,16 +1477,21 @@ static void cg_iterations(const Dev& d, cx<T>* xv, cx<T>* r, cx<T>* p0, cx<T>* p
 
 template <typename T>
 void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* p0, cx<T>* p1,
-                    cx<T>* q, double* part, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+                    cx<T>* q, double* part, int mass_iters, int diff_iters, int mass_sep, const int* mask,
+                    hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
         // step 1: beta1' ~ M^{-1} beta1
-        {
-            ProbeScope ps(d, KID_PCG_INIT, st);
-            hipLaunchKernelGGL((k_cg_init_copy<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, v, r, p0, part,
-                               d.ntiles);
+        if (mass_sep > 0) {
+            launch_mass_sep<T>(d, mass_sep, v, x1, mask, st);
+        } else {
+            {
+                ProbeScope ps(d, KID_PCG_INIT, st);
+                hipLaunchKernelGGL((k_cg_init_copy<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, v, r, p0, part,
+                                   d.ntiles);
+            }
+            cg_iterations<DIM, TYv, T, 0>(d, x1, r, p0, p1, q, part, mass_iters, mask, st);
         }
-        cg_iterations<DIM, TYv, T, 0>(d, x1, r, p0, p1, q, part, mass_iters, mask, st);
         // step 2: beta2' ~ L^{-1} (beta2 - kappa G beta1')
         {
             ProbeScope ps(d, KID_PCG_INIT, st);
@@ -1507,9 +1512,9 @@ void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2
     });
 }
 template void launch_precond<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, zd*, double*, int, int,
-                                     const int*, hipStream_t);
+                                     int, const int*, hipStream_t);
 template void launch_precond<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, double*, int, int,
-                                    const int*, hipStream_t);
+                                    int, const int*, hipStream_t);
 
 // stage launch of the Chebyshev inner solves: z-marching kernels for the stencil stages in 3D
 template <int DIM, int TY, typename T, int STAGE>
@@ -1568,12 +1573,15 @@ static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1,
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
-                                 cx<T>* d1, int mass_iters, int diff_iters, const int* mask, hipStream_t st) {
+                                 cx<T>* d1, int mass_iters, int diff_iters, int mass_sep, const int* mask,
+                                 hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
         if constexpr (DIM == 3) {
-            // step 1: initialisation fused with the first iteration
-            if (mass_iters >= 2) {
+            // step 1: the separable mass inverse, or the initialisation fused with the first iteration
+            if (mass_sep > 0) {
+                launch_mass_sep<T>(d, mass_sep, v, x1, mask, st);
+            } else if (mass_iters >= 2) {
                 ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (mass_iters == 2 ? 2.0 : 4.0) * sizeof(cx<T>), mask);
                 if (mass_iters == 2)
                     hipLaunchKernelGGL((k_cb_first3d<TYv, T, true>), TILE_GRID, d.sys, d.tiles, mask, v, d1, r, x1);
@@ -1583,7 +1591,8 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
                 cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
             }
             // d1 holds d_1: iterations j >= 2 read D[(j - 1) & 1] = d1 first
-            cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
+            if (mass_sep == 0)
+                cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
             {
                 ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
                 cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
@@ -1601,11 +1610,15 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             }
             return;
         }
-        {
-            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
-            cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+        if (mass_sep > 0) {
+            launch_mass_sep<T>(d, mass_sep, v, x1, mask, st);
+        } else {
+            {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
+                cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+            }
+            cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         }
-        cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
             cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
@@ -1620,22 +1633,28 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
         hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);
     });
 }
-template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, int, int,
+template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, int, int, int,
                                                   const int*, hipStream_t);
-template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, int, int,
+template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, int, int, int,
                                                  const int*, hipStream_t);
 
 template <typename T>
 void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r,
-                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, const int* mask, hipStream_t st) {
+                       cx<T>* d0, cx<T>* d1, cx<T>* b, int mass_iters, int mass_sep, const int* mask,
+                       hipStream_t st) {
     dispatch(d, [&](auto D, auto TY) {
         constexpr int DIM = D(), TYv = TY();
-        // step 1: beta1' ~ M^{-1} beta1 by Chebyshev iterations (as the Chebyshev inner solver)
-        {
-            ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
-            cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+        // step 1: beta1' ~ M^{-1} beta1 by the separable inverse or by Chebyshev iterations (as the Chebyshev
+        // inner solver)
+        if (mass_sep > 0) {
+            launch_mass_sep<T>(d, mass_sep, v, x1, mask, st);
+        } else {
+            {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
+                cb_init_launch<DIM, TYv, T, 0>(d, mask, v, x1, r, d0, x1, st);
+            }
+            cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         }
-        cb_iterations<DIM, TYv, T, 0>(d, mass_iters, d0, d1, r, x1, mask, st);
         // step 2: b = beta2 - kappa G beta1' (the stage-1 start writes it to its residual argument), one V-cycle
         {
             ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
@@ -1654,9 +1673,9 @@ void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* 
     });
 }
 template void launch_precond_mg<double>(const Dev&, const MgLevels&, const zd*, zd*, zd*, zd*, zd*, zd*, zd*, zd*, int,
-                                        const int*, hipStream_t);
+                                        int, const int*, hipStream_t);
 template void launch_precond_mg<float>(const Dev&, const MgLevels&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, zf*, int,
-                                       const int*, hipStream_t);
+                                       int, const int*, hipStream_t);
 
 void launch_mass_solve(const Dev& d, const zd* eta, zd* zeta, zd* r, zd* p0, zd* p1, zd* q, double* part, int iters,
                        hipStream_t st) {

@@ -94,7 +94,10 @@ struct RegionRows {
 template <typename T>
 constexpr int cheb_buffers() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <typename T, int STAGE, int RX, int RY, int NTH>
+// MR > 0 (stage 0 only): x1 = W beta1 with the separable mass inverse of MR taps per side (Sys::wsep; the
+// operator of launch_mass_sep) instead of the Chebyshev mass iterations: an x filter of the region's rows,
+// then a y filter at the thread's rows.
+template <typename T, int STAGE, int RX, int RY, int NTH, int MR = 0>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v, cx<T>* x1, cx<T>* x2, cx<T>* z, int sM,
     int sL, int halo, long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
@@ -165,6 +168,44 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
                                               cx<T>, cx<T>) { R[i] = ma * (pA + pC) + mb * pB; });
         }
     }
+    static_assert(MR == 0 || (STAGE == 0 && MR <= kMassRMax), "the separable mass inverse is step 1");
+    if constexpr (MR > 0) {
+        // x filter of the thread's rows from LDS into X, written back over the region (one buffer), then the
+        // y filter; region rows q in [MR, RY - MR) and columns in [MR, RX - MR) come out exact, and the
+        // interior lies inside them (halo >= MR)
+        T w[MR + 1];
+#pragma unroll
+        for (int k = 0; k <= MR; ++k) w[k] = T(s.wsep[k]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) lrow(bufs[0], i) = R[i];
+        __syncthreads();
+        const bool xin = px >= MR && px < RX - MR;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const cx<T>* row = &lrow(bufs[0], i);
+            cx<T> acc = cx<T>{T(0), T(0)};
+            if (xin) {
+                acc = w[0] * row[0];
+#pragma unroll
+                for (int k = 1; k <= MR; ++k) acc = acc + w[k] * (row[-k] + row[k]);
+            }
+            X[i] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) lrow(bufs[0], i) = X[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int q = r0 + i;
+            if (q < MR || q >= RY - MR) continue;
+            const cx<T>* col = &lrow(bufs[0], i);
+            cx<T> acc = w[0] * col[0];
+#pragma unroll
+            for (int k = 1; k <= MR; ++k) acc = acc + w[k] * (col[-k * RX] + col[k * RX]);
+            X[i] = acc;
+        }
+    } else {
     // Chebyshev iterations on OP = M (stage 0) or L (stages 1, 2)
     constexpr bool isM = STAGE == 0;
     const int its = isM ? sM : sL;
@@ -226,6 +267,7 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
                                           });
         }
     }
+    }
     // interior output (no wrap: each mesh node is written by exactly one tile)
     const int ix = px - halo;
     if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
@@ -251,15 +293,25 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
 
 template <typename T, int RX, int RY, int NTH>
 static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
-                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
+                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep, const double* vscale,
                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
     // input half read (residual or basis vector) and, with vscale, the basis vector written
     const double pts = (double)d.NT, vin = (double)sizeof(cx<T>), vb = vscale ? (double)sizeof(cx<T>) : 0.0;
     {
         ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
-        hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z,
-                           mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+        auto stage0 = [&](auto mr) {
+            hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH, decltype(mr)::value>), g, b, 0, st, d.sys, ctiles, mask,
+                               v, x1, x2, z, mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+        };
+        static_assert(kMassRMax == 4, "one case per tap count");
+        switch (mass_sep) {
+            case 0: stage0(std::integral_constant<int, 0>{}); break;
+            case 1: stage0(std::integral_constant<int, 1>{}); break;
+            case 2: stage0(std::integral_constant<int, 2>{}); break;
+            case 3: stage0(std::integral_constant<int, 3>{}); break;
+            default: stage0(std::integral_constant<int, 4>{}); break;
+        }
     }
     {
         ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb), mask);
@@ -273,12 +325,12 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
 
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
-                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, const double* vscale,
-                         const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+                         cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep,
+                         const double* vscale, const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
 #define APFC_CHEB_SHAPE(I)                                                                                       \
     case I:                                                                                                      \
         cheb_stages<T, kChebShape[I][0], kChebShape[I][1], kChebShape[I][2]>(                                    \
-            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st);          \
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vscale, rv, vout, mask, st); \
         break;
     static_assert(kChebShapes == 6, "one case per region shape");
     switch (shape) {
@@ -288,13 +340,13 @@ void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctil
         APFC_CHEB_SHAPE(4)
         APFC_CHEB_SHAPE(5)
         default: cheb_stages<T, kChebShape[0][0], kChebShape[0][1], kChebShape[0][2]>(
-            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, vscale, rv, vout, mask, st);
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vscale, rv, vout, mask, st);
     }
 #undef APFC_CHEB_SHAPE
 }
 template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
-                                          const double*, const zd*, zd*, const int*, hipStream_t);
+                                          int, const double*, const zd*, zd*, const int*, hipStream_t);
 template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
-                                         const double*, const zf*, zf*, const int*, hipStream_t);
+                                         int, const double*, const zf*, zf*, const int*, hipStream_t);
 
 }  // namespace apfc

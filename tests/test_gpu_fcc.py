@@ -125,11 +125,13 @@ def test_fcc_relaxed_crystal_is_a_fixed_point_at_full_size():
 
 def test_fcc128_full_size_steps_solve_the_oracle_system():
     """The 128^3 FCC sphere (7 amplitudes, 14.7 M amplitude DOF) in the benchmark's launch configuration
-    (mixed precision, Chebyshev 5/3, restart 4, cubic extrapolated guess, autotuned bricks): three steps,
+    (mixed precision, separable mass inverse of 3 taps and 3 Chebyshev diffusion iterations, restart 4,
+    cubic extrapolated guess, autotuned bricks): three steps,
     the third certified against the oracle's block systems (Kronecker assembly)."""
     wl = inputs.sphere_3d(fcc_k(), eq_of(fcc_k()), n=128, seed=1, spacing=inputs.FCC_SPACING, name="fcc")
     p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=1e-8, precision=apfc.APFC_MIXED,
-                                 inner_kind=apfc.APFC_INNER_CHEB, restart=4, mass_iters=5, diff_iters=3, x0_order=3)
+                                 inner_kind=apfc.APFC_INNER_CHEB, restart=4,
+                                 mass_kind=apfc.APFC_MASS_SEPARABLE, mass_iters=3, diff_iters=3, x0_order=3)
     s = apfc.Solver([apfc.make_mesh(3, wl.mesh.n, wl.mesh.length)], apfc.apfc_lattice_default(apfc.APFC_FCC3D), [p])
     s.autotune()
     et = to_dev(wl.eta0)

@@ -1,5 +1,6 @@
-"""The benchmark workloads at full size, in the launch configuration bench.py times (Chebyshev 5/3 inner
-solves, restart 4, cubic extrapolated initial guess, autotuned tiles): the 1024^2 triangular
+"""The benchmark workloads at full size, in the launch configuration bench.py times (separable mass
+inverse of 3 taps and 3 Chebyshev diffusion iterations as inner solves, restart 4, cubic extrapolated
+initial guess, autotuned tiles): the 1024^2 triangular
 polycrystal, the 128^3 bcc sphere and the 64-instance batch.  The oracle cannot factor these systems in
 reasonable time, so it checks a property that holds at any size: with its own assembly and its own
 nodal linearisation it forms every amplitude's block system Eq. (11) and verifies that the GPU's step
@@ -32,7 +33,8 @@ def test_full_size_step_solves_the_oracle_system(precision):
     last step are certified."""
     o, wl = _oracle_and_workload()
     p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=wl.rtol, precision=precision, inner_kind=apfc.APFC_INNER_CHEB,
-                                 restart=4, mass_iters=5, diff_iters=3, x0_order=3)
+                                 restart=4, mass_kind=apfc.APFC_MASS_SEPARABLE, mass_iters=3,
+                                 diff_iters=3, x0_order=3)
     s = apfc.Solver([apfc.make_mesh(2, wl.mesh.n, wl.mesh.length)], apfc.apfc_lattice_default(apfc.APFC_TRI2D), [p])
     s.autotune()
     et = to_dev(wl.eta0)
@@ -71,13 +73,15 @@ def _certify(o, dt, eta_in, eta1, zeta1):
 
 def test_bcc128_full_size_steps_solve_the_oracle_system():
     """The 128^3 bcc sphere (6 amplitudes) in the benchmark's launch configuration (mixed precision,
-    Chebyshev 5/3, restart 4, cubic extrapolated guess, autotuned bricks): three steps, the third
+    separable mass inverse (3 taps) and 3 Chebyshev
+    diffusion iterations, restart 4, cubic extrapolated guess, autotuned bricks): three steps, the third
     certified against the oracle's block systems (Kronecker assembly, equal to the element loop)."""
     from oracle.apfc_oracle import bcc_k
     wl = inputs.sphere_3d(bcc_k(), lambda dB: uniform_amplitude(BulkEnergy(bcc_k(), Params.from_dB(dB))), n=128,
                           seed=1)
     p = apfc.apfc_params_default(a1=0.5 * wl.dB, rtol=1e-8, precision=apfc.APFC_MIXED,
-                                 inner_kind=apfc.APFC_INNER_CHEB, restart=4, mass_iters=5, diff_iters=3, x0_order=3)
+                                 inner_kind=apfc.APFC_INNER_CHEB, restart=4,
+                                 mass_kind=apfc.APFC_MASS_SEPARABLE, mass_iters=3, diff_iters=3, x0_order=3)
     s = apfc.Solver([apfc.make_mesh(3, wl.mesh.n, wl.mesh.length)], apfc.apfc_lattice_default(apfc.APFC_BCC3D), [p])
     s.autotune()
     et = to_dev(wl.eta0)
@@ -100,7 +104,8 @@ def test_batch64_full_size_every_instance():
     k = tri_k()
     wls = inputs.batch_2d(k, lambda dB: uniform_amplitude(BulkEnergy(k, Params.from_dB(dB))), count=64, seed=1)
     ps = [apfc.apfc_params_default(a1=0.5 * w.dB, rtol=1e-8, precision=apfc.APFC_MIXED,
-                                   inner_kind=apfc.APFC_INNER_CHEB, restart=4, mass_iters=5, diff_iters=3, x0_order=3)
+                                   inner_kind=apfc.APFC_INNER_CHEB, restart=4,
+                                   mass_kind=apfc.APFC_MASS_SEPARABLE, mass_iters=3, diff_iters=3, x0_order=3)
           for w in wls]
     s = apfc.Solver([apfc.make_mesh(2, w.mesh.n, w.mesh.length) for w in wls],
                     apfc.apfc_lattice_default(apfc.APFC_TRI2D), ps)
