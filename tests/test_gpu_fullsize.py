@@ -73,8 +73,8 @@ def _certify(o, dt, eta_in, eta1, zeta1):
 
 def test_bcc128_full_size_steps_solve_the_oracle_system():
     """The 128^3 bcc sphere (6 amplitudes) in the benchmark's launch configuration (mixed precision,
-    separable mass inverse (3 taps) and 3 Chebyshev
-    diffusion iterations, restart 4, cubic extrapolated guess, autotuned bricks): three steps, the third
+    separable mass inverse of 3 taps and 3 Chebyshev diffusion iterations, restart 4, cubic extrapolated
+    guess, autotuned bricks): three steps, the third
     certified against the oracle's block systems (Kronecker assembly, equal to the element loop)."""
     from oracle.apfc_oracle import bcc_k
     wl = inputs.sphere_3d(bcc_k(), lambda dB: uniform_amplitude(BulkEnergy(bcc_k(), Params.from_dB(dB))), n=128,
