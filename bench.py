@@ -348,14 +348,16 @@ def measure(args, workload, precision, probe, compare, graphs=None):
 
 
 STUDY_DT = [0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0]
-# (label, inner solver, mass iterations, diffusion iterations / smoothing iterations, initial-guess order, time steps)
-STUDY_ARMS = [("PCG 3/5 (paper), x0 0", "pcg", 3, 5, 0, STUDY_DT),
-              ("Chebyshev 5/3, x0 0", "cheb", 5, 3, 0, STUDY_DT),
-              ("Chebyshev 5/3, x0 3", "cheb", 5, 3, 3, STUDY_DT),
-              ("Chebyshev 5/6, x0 0", "cheb", 5, 6, 0, STUDY_DT),
-              ("multigrid 5/nu=1, x0 0", "mg", 5, 1, 0, STUDY_DT),
-              ("multigrid 5/nu=2, x0 0", "mg", 5, 2, 0, STUDY_DT),
-              ("PCG 20/20 (inner solves ~exact), x0 0", "pcg", 20, 20, 0, [1.0, 10.0, 100.0])]
+# (label, inner solver, mass step, mass iterations or taps, diffusion iterations or smoothing iterations,
+#  initial-guess order, time steps)
+STUDY_ARMS = [("PCG 3/5 (paper), x0 0", "pcg", "iter", 3, 5, 0, STUDY_DT),
+              ("Chebyshev 5/3, x0 0", "cheb", "iter", 5, 3, 0, STUDY_DT),
+              ("separable 3 + Chebyshev 3, x0 0", "cheb", "sep", 3, 3, 0, STUDY_DT),
+              ("separable 3 + Chebyshev 3, x0 3", "cheb", "sep", 3, 3, 3, STUDY_DT),
+              ("separable 3 + Chebyshev 6, x0 0", "cheb", "sep", 3, 6, 0, STUDY_DT),
+              ("separable 3 + multigrid nu=1, x0 0", "mg", "sep", 3, 1, 0, STUDY_DT),
+              ("separable 3 + multigrid nu=2, x0 0", "mg", "sep", 3, 2, 0, STUDY_DT),
+              ("PCG 20/20 (inner solves ~exact), x0 0", "pcg", "iter", 20, 20, 0, [1.0, 10.0, 100.0])]
 
 
 def dt_study(args):
@@ -363,10 +365,14 @@ def dt_study(args):
     arm: the analogue of the paper's Fig. 4(a).  Prints one JSON line per run, then a markdown table."""
     import numpy as np
     rows = {}
-    for label, inner, mi, di, x0, dts in STUDY_ARMS:
+    for label, inner, mass, mi, di, x0, dts in STUDY_ARMS:
         for dt in dts:
-            args.inner, args.mass_iters, args.diff_iters, args.x0, args.dt = inner, mi, di, x0, dt
-            res = run_gpu(args, args.precision, probe=None)
+            args.inner, args.mass, args.mass_iters, args.diff_iters, args.x0, args.dt = inner, mass, mi, di, x0, dt
+            try:
+                res = run_gpu(args, args.precision, probe=None)
+            except Exception as e:      # e.g. FGMRES reached max_iters on this arm
+                print(json.dumps({"arm": label, "dt": dt, "error": str(e)}), flush=True)
+                continue
             r = {"arm": label, "dt": dt, "ms_per_step": 1e3 * res["sec"] / args.steps,
                  "fgmres_iters_per_step": float(np.mean(res["iters"])), "final_relres": res["relres"],
                  "workload": res["workload"], "steps": args.steps, "warmup": args.warmup,

@@ -101,7 +101,8 @@ template <typename T, int STAGE, int RX, int RY, int NTH, int MR = 0>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v, cx<T>* x1, cx<T>* x2, cx<T>* z, int sM,
     int sL, int halo, long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
-    constexpr int NB = cheb_buffers<T>();
+    // the separable stage 0 needs one region buffer: half the LDS, twice the workgroups per CU
+    constexpr int NB = MR > 0 ? 1 : cheb_buffers<T>();
     constexpr int RL = RY + 2, RP = RX * RL, NP = RX * RY / NTH;
     static_assert((RX * RY) % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
     __shared__ cx<T> bufs[NB][RP];
