@@ -1255,7 +1255,11 @@ namespace {
 // nodal linearisation, FGMRES.  *max_iters receives the largest per-system iteration count.
 int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st, int* max_iters) {
     const int K = c->solver.picard_iters;
-    if (K == 1)
+    // 2D with one linearisation: the RHS and the nonlinearity in one pass; 3D: the mass term by the plane
+    // march into BB, then the nodal pass (a 27-point stencil per amplitude from global loads costs more
+    // than the extra pass over BB)
+    const bool fused_rhs = K == 1 && c->dim == 2;
+    if (fused_rhs)
         launch_rhs_nonlinear(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->dnode, c->B, st);
     else
         launch_rhs_base(d, c->X + c->NT, source ? tab(c, 2) : nullptr, c->BB, st);
@@ -1263,7 +1267,7 @@ int step_body(apfc_ctx* c, const Dev& d, double dt, bool source, hipStream_t st,
     if (order > 0 && c->hist_n > 0 && dt != c->hist_dt) c->hist_n = 0;
     for (int k = 0; k < K; ++k) {
         // all amplitudes linearised at the previous iterate (Jacobi splitting)
-        if (K > 1) launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
+        if (!fused_rhs) launch_nonlinear(d, c->X + c->NT, c->BB, c->dnode, c->B, st);
         if (k == 0 && order > 0) {
             // initial guess extrapolated from the kept states; the state passed in becomes the newest
             // kept state and the oldest one is dropped

@@ -196,29 +196,63 @@ __global__ __launch_bounds__(kBlock) void k_rhs_base(const Sys* sys, const Tile*
     }
 }
 
-// d (per instance node) and B = [0 ; BB - kappa_j w h_j(eta_it)] for every amplitude of the instance.
+// 3D k_rhs_base on z-marching bricks: the x/y passes of each plane of eta_j (and s_j) from LDS, the z pass in
+// registers (the arithmetic of the plane-marching stencil kernels).
+template <int TY, bool SRC>
+__global__ __launch_bounds__(kBlock) void k_rhs_base3d(const Sys* sys, const Tile* tiles, const zd* Xeta,
+                                                      double* const* src_tab, zd* BB) {
+    const int* mask = nullptr;
+    TILE_PROLOGUE();
+    constexpr int NF = SRC ? 2 : 1;
+    const double* src = SRC ? src_tab[s.inst] + (long long)s.j * 2 * s.N : nullptr;
+    const int y = tile.y0 + ty;
+    const double h = s.h, m0 = h / 6.0, m1 = 4.0 * h / 6.0, ih = 1.0 / h;
+    __shared__ zd buf[2][NF][kPP];
+    zmarch_lds<TY / 4, NF, false, false, double, double>(
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih,
+        [&](int f, long long i) { return f == 0 ? Xeta[s.off + i] : zd{src[i], src[s.N + i]}; },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            zd Mu, Ku, Tu;
+            zcombine<false, false, double>(P[0][0], P[0][1], P[0][2], m0, m1, ih, 0.0, 0.0, 0.0, Mu, Ku, Tu);
+            zd out = s.inv_dt * Mu;
+            if constexpr (SRC) {
+                zd Ms;
+                zcombine<false, false, double>(P[NF - 1][0], P[NF - 1][1], P[NF - 1][2], m0, m1, ih, 0.0, 0.0, 0.0, Ms,
+                                               Ku, Tu);
+                out = out + Ms;
+            }
+            BB[s.off + ((long long)z * s.ny + y) * s.nx + x] = out;
+        });
+}
+
+// d (per instance node) and B = [0 ; BB - kappa_j w h_j(eta_it)] for every amplitude of the instance.  The
+// J tiles of an instance that cover the same nodes share the rows (amplitude j's tile takes the row steps
+// rr with rr % J == j), as in k_rhs_nonlinear.
 template <int DIM, int TY, int JM>
 __global__ __launch_bounds__(kBlock) void k_nonlinear(const Sys* sys, const Tile* tiles, const Terms T,
                                                      const zd* eta_half, const zd* BB, double* dnode, zd* B,
                                                      long long NT) {
     const int* mask = nullptr;
     TILE_PROLOGUE();
-    if (s.j != 0) return;
+    const int s0 = tile.sys - s.j;   // amplitude 0 of the instance
+    const Sys b = sys[s0];
     FOR_ROWS(TY) {
+        if (rr_ % T.J != s.j) continue;
         const long long i = ((long long)pz * s.ny + y) * s.nx + x;
         zd eta[JM], h[JM];
 #pragma unroll
-        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[s.off + l * s.N + i] : zd{0.0, 0.0};
+        for (int l = 0; l < JM; ++l) eta[l] = l < T.J ? eta_half[b.off + l * b.N + i] : zd{0.0, 0.0};
         double d;
-        bulk_h_reg<JM>(T, s, eta, d, h);
+        bulk_h_reg<JM>(T, b, eta, d, h);
         dnode[s.doff + i] = d;
 #pragma unroll
         for (int l = 0; l < JM; ++l) {
             if (l >= T.J) break;
-            const double kap = sys[tile.sys + l].kappa;
-            const long long o = s.off + l * s.N + i;
+            const double kap = sys[s0 + l].kappa;
+            const long long o = b.off + l * b.N + i;
             B[o] = zd{0.0, 0.0};
-            B[NT + o] = BB[o] - (kap * s.w) * h[l];
+            B[NT + o] = BB[o] - (kap * b.w) * h[l];
         }
     }
 }
@@ -538,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile
                 rv = Mu;
             const cx<T> dv = scale * rv;
             r[i] = rv;
-            d[i] = dv;
+            if (d) d[i] = dv;   // not kept by the three-term form (k_cx_iter3d)
             xv[i] = dv;
         });
 }
@@ -604,6 +638,38 @@ __global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Til
                 r[i] = rv;
                 dout[i] = dv;
             }
+        });
+}
+
+// Iteration j >= 1 of the Chebyshev solve for L in three-term form on the iterates (3D):
+//   x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 (b - L x_j),   x_0 = 0 (FIRST: j = 1),
+// with the scalars (c1, c2) of iteration j of the correction form (k_cb_iter3d: d_j = c1 d_{j-1} + c2 r_j,
+// x_{j+1} = x_j + d_j, where d_{j-1} = x_j - x_{j-1} and r_j = b - L x_j), so the iterates are the same in
+// exact arithmetic; per node it reads x_j (stencil), x_{j-1} and b and writes x_{j+1}, two vectors fewer
+// than the correction form.  xout may be xkm1 (each node is read, then written, by one thread).  FINAL:
+// also step 4, z_zeta = x1 - (x2 - chi2 / sqrt(dt)) / sqrt(kappa) with chi2 = x_{j+1}.
+template <int TY, typename T, bool FIRST, bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_cx_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
+                                                     const cx<T>* xk, const cx<T>* xkm1, const cx<T>* b, cx<T>* xout,
+                                                     const cx<T>* x1, const cx<T>* x2, cx<T>* zz) {
+    TILE_PROLOGUE();
+    const T c1 = T(sys[tile.sys].cb[1][j][0]), c2 = T(sys[tile.sys].cb[1][j][1]);
+    const T cM = T(s.isq_dt), cK = T(s.sq_kap);
+    const int y = tile.y0 + ty;
+    const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
+    __shared__ cx<T> buf[2][1][kPP];
+    zmarch_lds<TY / 4, 1, true, false, T, T>(
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return xk[s.off + i]; },
+        [&](int z, const auto& P) {
+            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+            const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
+            cx<T> Mu, Ku, Tu;
+            zcombine<true, false, T>(P[0][0], P[0][1], P[0][2], m0, m1, ih, T(0), T(0), T(0), Mu, Ku, Tu);
+            const cx<T> xc = P[0][1].c;
+            const cx<T> dprev = FIRST ? xc : xc - ld<T>(xkm1, i);
+            const cx<T> xn = xc + c1 * dprev + c2 * (ld<T>(b, i) - (cM * Mu + cK * Ku));
+            xout[i] = xn;
+            if constexpr (FINAL) zz[i] = ld<T>(x1, i) - T(s.isq_kap) * (ld<T>(x2, i) - T(s.isq_dt) * xn);
         });
 }
 
@@ -1408,8 +1474,17 @@ void launch_narrow(const zd* in, zf* out, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_narrow, dim3((unsigned)blocks), dim3(kBlock), 0, st, in, out, n);
 }
 void launch_rhs_base(const Dev& d, const zd* Xeta, double* const* src_tab, zd* BB, hipStream_t st) {
+    // reads eta (and s), writes BB
+    ProbeScope ps(d, KID_RHS, st, (double)d.NT * sizeof(zd) * (2.0 + (src_tab ? 1.0 : 0.0)));
     dispatch(d, [&](auto D, auto TY) {
-        hipLaunchKernelGGL((k_rhs_base<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, Xeta, src_tab, BB);
+        if constexpr (D() == 3) {
+            if (src_tab)
+                hipLaunchKernelGGL((k_rhs_base3d<TY(), true>), TILE_GRID, d.sys, d.tiles, Xeta, src_tab, BB);
+            else
+                hipLaunchKernelGGL((k_rhs_base3d<TY(), false>), TILE_GRID, d.sys, d.tiles, Xeta, src_tab, BB);
+        } else {
+            hipLaunchKernelGGL((k_rhs_base<D(), TY()>), TILE_GRID, d.sys, d.tiles, nullptr, Xeta, src_tab, BB);
+        }
     });
 }
 // amplitude slots of the register-resident nonlinearity: 3 (triangular), 6 (bcc), else 8
@@ -1420,6 +1495,8 @@ static void dispatch_jm(int J, F&& f) {
     else f(std::integral_constant<int, kMaxJ>{});
 }
 void launch_nonlinear(const Dev& d, const zd* eta_half, const zd* BB, double* dnode, zd* B, hipStream_t st) {
+    // reads eta and BB, writes B (both halves) and d
+    ProbeScope ps(d, KID_RHS, st, (double)d.NT * sizeof(zd) * 4.0 + (double)d.NT * 8.0 / d.J);
     dispatch(d, [&](auto D, auto TY) {
         dispatch_jm(d.J, [&](auto JM) {
             hipLaunchKernelGGL((k_nonlinear<D(), TY(), JM()>), TILE_GRID, d.sys, d.tiles, d.terms, eta_half, BB,
@@ -1571,6 +1648,34 @@ static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1,
     }
 }
 
+// Iterations 1 .. its - 1 of a three-term Chebyshev solve for L (3D) after the start wrote x_1 to A: x_j
+// in A or B by the parity of j, the last iterate into out (with x1, x2, zz: step 4 as well).
+template <int TYv, typename T>
+static void cx_iterations3d(const Dev& d, int its, cx<T>* A, cx<T>* B, const cx<T>* b, cx<T>* out, const cx<T>* x1,
+                            const cx<T>* x2, cx<T>* zz, const int* mask, hipStream_t st) {
+    for (int j = 1; j < its; ++j) {
+        const bool last = j == its - 1, first = j == 1;
+        cx<T>* xk = ((j - 1) & 1) ? B : A;
+        cx<T>* xkm1 = (j & 1) ? B : A;
+        cx<T>* xo = last ? out : xkm1;
+        const double vecs = (first ? 3.0 : 4.0) + (last && zz ? 3.0 : 0.0);
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * vecs, mask);
+        auto go = [&](auto f, auto fin) {
+            hipLaunchKernelGGL((k_cx_iter3d<TYv, T, decltype(f)::value, decltype(fin)::value>), TILE_GRID, d.sys,
+                               d.tiles, mask, j, xk, xkm1, b, xo, x1, x2, zz);
+        };
+        using TT = std::true_type;
+        using FF = std::false_type;
+        if (last && zz) {
+            if (first) go(TT{}, TT{});
+            else go(FF{}, TT{});
+        } else {
+            if (first) go(TT{}, FF{});
+            else go(FF{}, FF{});
+        }
+    }
+}
+
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
                                  cx<T>* d1, int mass_iters, int diff_iters, int mass_sep, const int* mask,
@@ -1593,17 +1698,18 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             // d1 holds d_1: iterations j >= 2 read D[(j - 1) & 1] = d1 first
             if (mass_sep == 0)
                 cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
-            {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 5.0 * sizeof(cx<T>), mask);
-                cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, d0, x2, st);
-            }
-            cb_iterations3d<TYv, T, 1>(d, 1, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
+            // steps 2 and 3 in three-term form: the start writes b (into r) and x_1
             {
                 ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
-                cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, d0, z + d.NT, st);
+                cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, nullptr, diff_iters == 1 ? x2 : d0, st);
+            }
+            cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
+            {
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 3.0 * sizeof(cx<T>), mask);
+                cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, nullptr, diff_iters == 1 ? z + d.NT : d0, st);
             }
             // steps 3 and 4: the last iteration also forms z_zeta
-            cb_iterations3d<TYv, T, 1>(d, 1, diff_iters, d0, d1, r, z + d.NT, x1, x2, z, mask, st);
+            cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, z + d.NT, x1, x2, z, mask, st);
             if (diff_iters < 2) {
                 ProbeScope ps(d, KID_PC_FINAL, st);
                 hipLaunchKernelGGL((k_pc_final<DIM, TYv, T>), TILE_GRID, d.sys, d.tiles, mask, x1, x2, z, d.NT);

@@ -28,6 +28,25 @@ __device__ __forceinline__ int wrapi(int g, int n) {
     return g < 0 ? g + n : g;
 }
 
+// Whole-wave lane shifts by one lane (DPP wave_shr:1 / wave_shl:1): after lane_shift<kDppWaveShr1>, lane i
+// holds lane i - 1's value (lane 0 gets 0); after kDppWaveShl1, lane i + 1's (lane 63 gets 0).
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cx<T> lane_shift(cx<T> v) {
+    return cx<T>{lane_shift<CTRL>(v.x), lane_shift<CTRL>(v.y)};
+}
+
 // The operators of the inner solves in split form.  With P = [1 4 1], Q = [-1 2 -1] = 6 delta - P and
 // E = [-1 0 1], the bilinear element stencils are M = (h/6)^2 P(x)P,
 // K = (1/6)(Q(x)P + P(x)Q) = (delta(x)P + P(x)delta) - P(x)P/3 and T_j = (h/6)(k0 E(x)P + k1 P(x)E).
@@ -170,7 +189,45 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
         }
     }
     static_assert(MR == 0 || (STAGE == 0 && MR <= kMassRMax), "the separable mass inverse is step 1");
-    if constexpr (MR > 0) {
+    if constexpr (MR > 0 && RX == kTX) {
+        // a region row is one wave: the x filter by lane shifts (DPP) in registers; the y filter from the
+        // thread's own rows, and from LDS for the MR rows beyond either end of its block, which the waves
+        // above and below store.  Rows q in [MR, RY - MR) and columns in [MR, RX - MR) come out exact.
+        static_assert(2 * MR <= NP, "a thread's block holds the rows its neighbours need");
+        T w[MR + 1];
+#pragma unroll
+        for (int k = 0; k <= MR; ++k) w[k] = T(s.wsep[k]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            cx<T> lo = R[i], hi = R[i];
+            cx<T> acc = w[0] * R[i];
+#pragma unroll
+            for (int k = 1; k <= MR; ++k) {
+                lo = lane_shift<kDppWaveShr1>(lo);   // column px - k
+                hi = lane_shift<kDppWaveShl1>(hi);   // column px + k
+                acc = acc + w[k] * (lo + hi);
+            }
+            X[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            if (i < MR || i >= NP - MR) lrow(bufs[0], i) = X[i];
+        __syncthreads();
+        // (R, no longer needed, takes the y-filtered rows)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            cx<T> acc = w[0] * X[i];
+#pragma unroll
+            for (int k = 1; k <= MR; ++k) {
+                const cx<T> a = i - k >= 0 ? X[i - k] : lrow(bufs[0], i - k);
+                const cx<T> b = i + k < NP ? X[i + k] : lrow(bufs[0], i + k);
+                acc = acc + w[k] * (a + b);
+            }
+            R[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) X[i] = R[i];
+    } else if constexpr (MR > 0) {
         // x filter of the thread's rows from LDS into X, written back over the region (one buffer), then the
         // y filter; region rows q in [MR, RY - MR) and columns in [MR, RX - MR) come out exact, and the
         // interior lies inside them (halo >= MR)
