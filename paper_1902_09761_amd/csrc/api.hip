@@ -228,15 +228,26 @@ void noalloc_forget(const apfc_ctx* c);
 
 namespace {
 
+// Workgroups go to the 8 XCDs of the chip in turn (workgroup b to XCD b mod 8), each XCD with its own L2.
+constexpr int kXcds = 8;
+
 void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
     tiles.clear();
     for (int s = 0; s < c.S; ++s) {
         Sys& y = c.sys[s];
         y.tbeg = (int)tiles.size();
         if (y.dim == 3) {   // 64 x 4 x TY/4 bricks
+            std::vector<Tile> nat;
             for (int z0 = 0; z0 < y.nz; z0 += TY / 4)
                 for (int y0 = 0; y0 < y.ny; y0 += 4)
-                    for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, z0});
+                    for (int x0 = 0; x0 < y.nx; x0 += kTX) nat.push_back(Tile{s, x0, y0, z0});
+            // XCD-contiguous order: the workgroups of one XCD take consecutive bricks of the natural order,
+            // so a brick's neighbours in y (whose planes its halo re-reads) sit in the same L2
+            const int T = (int)nat.size(), per = T / kXcds, rem = T % kXcds;
+            for (int l = 0; l < T; ++l) {
+                const int x = l % kXcds, q = l / kXcds;
+                tiles.push_back(nat[x * per + std::min(x, rem) + q]);
+            }
         } else {
             for (int y0 = 0; y0 < y.ny; y0 += TY)
                 for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, 0});
