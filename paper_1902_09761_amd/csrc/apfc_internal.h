@@ -210,12 +210,12 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
 // part1, the second (only for the systems that need it) into part2; then the Hessenberg column.
 template <typename VT>
 void launch_gs(const Dev& d, const Krylov& kr, int k, const double* part1, const VT* V, long long vstride,
-               const zd* w, double* part2, hipStream_t st);
+               const VT* w, double* part2, hipStream_t st);
 template <typename T>
-void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, cx<T>* W, const cx<T>* V, long long vstride, int nv,
                       double* part, const int* mask, hipStream_t st);
 template <typename VT>
-void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
+void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const VT* w, const double* hcoef,
                        const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st);
 template <typename VT>
 void launch_scale(const Dev& d, const VT* r, const double* inv_beta, VT* v0, const int* mask, hipStream_t st);

@@ -1119,10 +1119,12 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
         precond<T>(c, d, V + k * vs, Z + k * vs, act, st);
     const int nv = k + 1;
     // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
-    launch_apply_dot<T>(d, Z + k * vs, c->dnode, c->W, V, vs, nv, c->apart, act, st);
+    // w is kept in the basis precision (the front of the W buffer)
+    cx<T>* Wk = (cx<T>*)c->W;
+    launch_apply_dot<T>(d, Z + k * vs, c->dnode, Wk, V, vs, nv, c->apart, act, st);
     // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
-    launch_gs<cx<T>>(d, kr, k, c->apart, V, vs, c->W, c->cpart, st);
-    launch_proj_final<cx<T>>(d, V, vs, nv, c->W, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
+    launch_gs<cx<T>>(d, kr, k, c->apart, V, vs, Wk, c->cpart, st);
+    launch_proj_final<cx<T>>(d, V, vs, nv, Wk, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
 }
 
 void run_iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
@@ -1722,7 +1724,7 @@ int apfc_autotune(apfc_ctx* c, void* stream, int* chosen) {
             auto body = [&]() {
                 if (c->mixed) {
                     precond<float>(c, d, basis<float>(c), (zf*)c->Z, nullptr, st);
-                    launch_apply_dot<float>(d, (const zf*)c->Z, c->dnode, c->W, basis<float>(c), vs, 2, c->apart,
+                    launch_apply_dot<float>(d, (const zf*)c->Z, c->dnode, (zf*)c->W, basis<float>(c), vs, 2, c->apart,
                                             nullptr, st);
                 } else {
                     precond<double>(c, d, c->V, (zd*)c->Z, nullptr, st);

@@ -693,7 +693,7 @@ __device__ __forceinline__ long long elem_index(const Sys& s, long long NT, long
 // out = (w - sum_l hcoef_l V_l) * hinv, formed in FP64 and stored in the basis precision
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chunk* chunks, const int* mask,
-                                                      const VT* V, long long vstride, int nv, const zd* w,
+                                                      const VT* V, long long vstride, int nv, const VT* w,
                                                       const double* hcoef, int hld, const double* hinv, VT* out,
                                                       long long NT) {
     __shared__ zd cf[kMaxRestart + 1];
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chu
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             gi[u] = elem_index(s, NT, (long long)ch.e0 + threadIdx.x + (long long)u * kBlock);
-            wv[u] = w[gi[u]];
+            wv[u] = ld<double>(w, gi[u]);
         }
         for (int l = 0; l < nv; ++l) {
             const zd c = cf[l];
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_final(const Sys* sys, const Chu
     }
     FOR_ELEMS() {
         const long long gi = elem_index(s, NT, e);
-        zd wv = w[gi];
+        zd wv = ld<double>(w, gi);
         for (int l = 0; l < nv; ++l) wv = wv - cmul(cf[l], ld<double>(V, l * vstride + gi));
         stv(out, gi, sc * wv);
     }
@@ -991,7 +991,7 @@ constexpr int kGsGrid = 128;   // workgroups of k_gs (at least one per system)
 template <int NV, typename VT>
 __global__ __launch_bounds__(kBlock) void k_gs(const Sys* sys, const Chunk* chunks, Krylov kr, int S, int k,
                                               const double* part1, long long P1, const VT* V, long long vstride,
-                                              const zd* w, double* part2, int nchunks, long long NT) {
+                                              const VT* w, double* part2, int nchunks, long long NT) {
     constexpr int NH = 2 * (kMaxRestart + 1) + 1;
     constexpr int EPT = kChunk / kBlock;
     __shared__ double hh[2][NH], rot[3 * kMaxRestart + 2], col[2 * (kMaxRestart + 1)];
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_gs(const Sys* sys, const Chunk* chun
             zd vv[NV];
 #pragma unroll
             for (int l = 0; l < NV; ++l) vv[l] = l < nv ? ld<double>(V, l * vstride + gi) : zd{0.0, 0.0};
-            zd wv = w[gi];
+            zd wv = ld<double>(w, gi);
 #pragma unroll
             for (int l = 0; l < NV; ++l) wv = wv - cmul(cf[l], vv[l]);
 #pragma unroll
@@ -1808,9 +1808,9 @@ void launch_reduce(const Dev& d, const double* part, int slot0, int nvals, bool 
 
 template <typename VT>
 void launch_gs(const Dev& d, const Krylov& kr, int k, const double* part1, const VT* V, long long vstride,
-               const zd* w, double* part2, hipStream_t st) {
-    // the second pass, where it runs, reads w and nv basis vectors
-    ProbeScope ps(d, KID_GS, st, 2.0 * d.NT * (sizeof(zd) + (k + 1) * sizeof(VT)), kr.reorth);
+               const VT* w, double* part2, hipStream_t st) {
+    // the second pass, where it runs, reads w and nv basis vectors (all stored in the basis precision)
+    ProbeScope ps(d, KID_GS, st, 2.0 * d.NT * (k + 2) * sizeof(VT), kr.reorth);
     const int per = d.S >= kGsGrid ? 1 : (kGsGrid + d.S - 1) / d.S;
     const dim3 grid(d.S * per);
     const int nv = k + 1;
@@ -1825,14 +1825,14 @@ void launch_gs(const Dev& d, const Krylov& kr, int k, const double* part1, const
 }
 template void launch_gs<zd>(const Dev&, const Krylov&, int, const double*, const zd*, long long, const zd*, double*,
                             hipStream_t);
-template void launch_gs<zf>(const Dev&, const Krylov&, int, const double*, const zf*, long long, const zd*, double*,
+template void launch_gs<zf>(const Dev&, const Krylov&, int, const double*, const zf*, long long, const zf*, double*,
                             hipStream_t);
 
 
 template <typename VT>
-void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const zd* w, const double* hcoef,
+void launch_proj_final(const Dev& d, const VT* V, long long vstride, int nv, const VT* w, const double* hcoef,
                        const double* hinv, int hstride, VT* out, const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_PROJ_FINAL, st, 2.0 * d.NT * (sizeof(zd) + (nv + 1) * sizeof(VT)), mask);
+    ProbeScope ps(d, KID_PROJ_FINAL, st, 2.0 * d.NT * (nv + 2) * sizeof(VT), mask);
     hipLaunchKernelGGL(k_proj_final<VT>, CHUNK_GRID, d.sys, d.chunks, mask, V, vstride, nv, w, hcoef, hstride, hinv, out,
                        d.NT);
 }
@@ -1842,7 +1842,7 @@ void launch_scale(const Dev& d, const VT* r, const double* inv_beta, VT* v0, con
 }
 template void launch_proj_final<zd>(const Dev&, const zd*, long long, int, const zd*, const double*, const double*,
                                     int, zd*, const int*, hipStream_t);
-template void launch_proj_final<zf>(const Dev&, const zf*, long long, int, const zd*, const double*, const double*,
+template void launch_proj_final<zf>(const Dev&, const zf*, long long, int, const zf*, const double*, const double*,
                                     int, zf*, const int*, hipStream_t);
 template void launch_scale<zd>(const Dev&, const zd*, const double*, zd*, const int*, hipStream_t);
 template void launch_scale<zf>(const Dev&, const zf*, const double*, zf*, const int*, hipStream_t);

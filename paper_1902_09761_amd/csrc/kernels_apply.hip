@@ -101,7 +101,7 @@ __device__ __forceinline__ void colmarch_A(const Sys& s, int x, int y0, const LO
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Tile* tiles, const int* mask,
                                                        const cx<T>* __restrict__ Z, const double* __restrict__ dnode,
-                                                       zd* __restrict__ W, const cx<T>* __restrict__ V,
+                                                       cx<T>* __restrict__ W, const cx<T>* __restrict__ V,
                                                        long long vstride, int nv, double* part, long long NT,
                                                        int ntiles) {
     constexpr int RR = TY / 4;
@@ -114,9 +114,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot2d(const Sys* sys, const Ti
     const cx<T>* zz = Z + s.off;
     const cx<T>* ze = Z + NT + s.off;
     auto load = [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); };
-    auto emit = [&](long long il, const zd& y1, const zd& y2) {
-        W[s.off + il] = y1;
-        W[NT + s.off + il] = y2;
+    auto emit = [&](long long il, const zd& a1, const zd& a2) {
+        // w is stored in the basis precision; the first pass takes the stored (rounded) w, so that the
+        // projection of k_proj_final and the coefficients belong to the same vector
+        const zd y1 = rounded<T>(a1), y2 = rounded<T>(a2);
+        stv(W, s.off + il, y1);
+        stv(W, NT + s.off + il, y2);
         acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
         for (int l = 0; l < NV; ++l)
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_residual2d(const Sys* sys, const Til
 
 template <int TY, typename T, int NV>
 __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Tile* tiles, const int* mask,
-                                                       const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V,
+                                                       const cx<T>* Z, const double* dnode, cx<T>* W, const cx<T>* V,
                                                        long long vstride, int nv, double* part, long long NT,
                                                        int ntiles) {
     __shared__ double lds[4 * (2 * NV + 1)];
@@ -202,10 +205,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
             const long long il = ((long long)z * s.ny + y) * s.nx + x;
-            zd y1, y2;
-            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], y1, y2);
-            W[s.off + il] = y1;
-            W[NT + s.off + il] = y2;
+            zd a1, a2;
+            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], a1, a2);
+            const zd y1 = rounded<T>(a1), y2 = rounded<T>(a2);
+            stv(W, s.off + il, y1);
+            stv(W, NT + s.off + il, y2);
             acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
             for (int l = 0; l < NV; ++l)
@@ -287,11 +291,10 @@ template void launch_apply<double>(const Dev&, const zd*, const double*, zd*, co
 template void launch_apply<float>(const Dev&, const zf*, const double*, zd*, const int*, hipStream_t);
 
 template <typename T>
-void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, const cx<T>* V, long long vstride, int nv,
-                      double* part, const int* mask, hipStream_t st) {
-    // reads z, d, nv basis vectors (stored like z); writes w
-    ProbeScope ps(d, KID_APPLY, st,
-                  (double)d.NT * (2.0 * sizeof(cx<T>) * (1 + nv) + 2.0 * sizeof(zd) + 8.0 / d.J), mask, true);
+void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, cx<T>* W, const cx<T>* V, long long vstride,
+                      int nv, double* part, const int* mask, hipStream_t st) {
+    // reads z, d, nv basis vectors (stored like z); writes w (stored like z)
+    ProbeScope ps(d, KID_APPLY, st, (double)d.NT * (2.0 * sizeof(cx<T>) * (2 + nv) + 8.0 / d.J), mask, true);
     dispatch(d, [&](auto D, auto TY) {
         auto go = [&](auto nvc) {
             if constexpr (D() == 2)
@@ -318,7 +321,7 @@ void launch_apply_dot(const Dev& d, const cx<T>* Z, const double* dnode, zd* W, 
 }
 template void launch_apply_dot<double>(const Dev&, const zd*, const double*, zd*, const zd*, long long, int, double*,
                                        const int*, hipStream_t);
-template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zd*, const zf*, long long, int, double*,
+template void launch_apply_dot<float>(const Dev&, const zf*, const double*, zf*, const zf*, long long, int, double*,
                                       const int*, hipStream_t);
 
 }  // namespace apfc

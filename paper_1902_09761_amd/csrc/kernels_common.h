@@ -47,6 +47,11 @@ __device__ __forceinline__ cx<R> ld(const cx<S>* p, long long i) {
     const cx<S> v = p[i];
     return {R(v.x), R(v.y)};
 }
+// v rounded to precision S (and back): the value a store to cx<S> keeps
+template <typename S>
+__device__ __forceinline__ zd rounded(zd v) {
+    return zd{double(S(v.x)), double(S(v.y))};
+}
 template <typename S, typename R>
 __device__ __forceinline__ void stv(cx<S>* p, long long i, cx<R> v) {
     p[i] = cx<S>{S(v.x), S(v.y)};
