@@ -286,10 +286,12 @@ int apfc_probe_read_kernel(apfc_ctx* ctx, const char* name, int* launches, doubl
 int apfc_autotune(apfc_ctx* ctx, void* stream, int* chosen_tile_rows);
 
 /* Set the tiling by hand instead of apfc_autotune: tile_rows in {4, 8, 16, 32} (rows of the 64-wide
- * stencil tiles) and precond_region in 0..5 (LDS region of the fused 2D Chebyshev preconditioner, nodes /
- * threads / FP32 region buffers: 128x32 / 512 / 2, 64x32 / 256 / 1, 64x64 / 512 / 1, 128x36 / 512 / 2,
- * 128x36 / 512 / 1, 128x72 / 1024 / 1; taller regions recompute less halo, one buffer leaves room for more
- * workgroups per CU).  Needs the workspace. */
+ * stencil tiles) and precond_region in 0..5 (LDS region of the fused 2D Chebyshev preconditioner, nodes x
+ * rows / threads: 0: 128x32 / 512, 1: 64x32 / 256, 2: 64x64 / 512, 3: 128x36 / 512, 4: 128x64 / 1024,
+ * 5: 256x32 / 1024; a Chebyshev stage keeps two LDS copies of its region in FP32 and one in FP64, the
+ * separable mass stage one; taller regions recompute less halo, smaller ones leave room for more
+ * workgroups per CU).  Needs the workspace.  The 3D bricks of the separable mass inverse and of the
+ * Chebyshev L solves (64 x 8 nodes per plane, 8 or 16 planes) are chosen at creation, not here. */
 int apfc_set_tiles(apfc_ctx* ctx, int tile_rows, int precond_region);
 int apfc_get_tiles(const apfc_ctx* ctx, int* tile_rows, int* precond_region);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <type_traits>
 
 namespace apfc {
 
@@ -16,8 +17,10 @@ constexpr int kMaxTerms = 24;
 constexpr int kMaxRestart = 32;
 constexpr int kMaxCheb = 64;     // Chebyshev iterations per inner solve
 constexpr int kMassRMax = 4;     // taps per side of the separable mass inverse
-// bricks of the separable mass inverse: 64 x kMassBY nodes per plane, kMassBZ planes (3D), 512 threads
-constexpr int kMassBY = 8, kMassBZ = 16, kMassThreads = 512;
+// bricks of the separable mass inverse and of the 3D Chebyshev L solves: 64 x kMassBY nodes per plane,
+// 512 threads; in 3D kBrickZShallow or kBrickZDeep planes (Dev::mbz)
+constexpr int kMassBY = 8, kMassThreads = 512;
+constexpr int kBrickZShallow = 8, kBrickZDeep = 16;
 
 // Complex value stored as two reals (re, im), 2*sizeof(R)-aligned for vector loads.
 template <typename R>
@@ -105,12 +108,21 @@ struct Dev {
     const Tile* tiles = nullptr;     // device [ntiles]
     const Chunk* chunks = nullptr;   // device [nchunks]
     const Tile* mtiles = nullptr;    // device [nmtiles]: bricks of the separable mass inverse
-    int nmtiles = 0;
+    int nmtiles = 0, mbz = kBrickZShallow;   // brick depth in planes (3D)
     int ntiles = 0, nchunks = 0, S = 0, TY = 16, J = 0, count = 0, dim = 2;
     long long NT = 0;                // half-vector length (complex values)
     Terms terms{};
     Probe* probe = nullptr;
 };
+
+// Calls f(std::integral_constant<int, depth>{}) with the brick depth of d.
+template <typename F>
+void brick_depth(const Dev& d, const F& f) {
+    if (d.mbz == kBrickZDeep)
+        f(std::integral_constant<int, kBrickZDeep>{});
+    else
+        f(std::integral_constant<int, kBrickZShallow>{});
+}
 
 // Levels of the multigrid inner solve below the fine one (APFC_INNER_MG): level l + 1 of the V-cycle is
 // lev[l] (its own Sys and tile tables, 16-row tiles) with its buffers in the storage precision.
@@ -199,6 +211,9 @@ template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,
                                  cx<T>* d1, int mass_iters, int diff_iters, int mass_sep, const int* mask,
                                  hipStream_t st);
+// Workgroups of the 3D brick Chebyshev iteration (bricks of bz planes, FP32 when single) that one compute
+// unit holds at once; 0 if the runtime cannot tell.
+int brick_occupancy(int bz, bool single);
 // x1 = W beta1 (beta1 = the zeta part of v): the separable approximate inverse of the mass matrix, taps
 // Sys::wsep[0..R] in every direction, on the bricks d.mtiles (kernels_mass.hip).
 template <typename T>

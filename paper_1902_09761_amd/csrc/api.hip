@@ -126,7 +126,8 @@ struct apfc_ctx {
     std::vector<Chunk> chunks;
     std::vector<CTile> ctiles;
     CTile* d_ctiles = nullptr;
-    std::vector<Tile> mtiles;          // bricks of the separable mass inverse (APFC_MASS_SEPARABLE)
+    std::vector<Tile> mtiles;          // bricks of the separable mass inverse and the 3D Chebyshev L solves
+    int mbz = kBrickZShallow;          // their depth in planes (3D)
     Tile* d_mtiles = nullptr;
     int cheb_shape = 0;
     size_t max_ctiles = 0;
@@ -207,6 +208,7 @@ struct apfc_ctx {
         d.chunks = d_chunks;
         d.mtiles = d_mtiles;
         d.nmtiles = (int)mtiles.size();
+        d.mbz = mbz;
         d.ntiles = (int)tiles.size();
         d.nchunks = (int)chunks.size();
         d.S = S;
@@ -231,6 +233,16 @@ namespace {
 // Workgroups go to the 8 XCDs of the chip in turn (workgroup b to XCD b mod 8), each XCD with its own L2.
 constexpr int kXcds = 8;
 
+// Appends bricks in XCD-contiguous order: the workgroups of one XCD take consecutive bricks of the natural
+// order, so a brick's neighbours in y (whose planes its halo re-reads) sit in the same L2.
+void append_xcd_order(const std::vector<Tile>& nat, std::vector<Tile>& out) {
+    const int T = (int)nat.size(), per = T / kXcds, rem = T % kXcds;
+    for (int l = 0; l < T; ++l) {
+        const int x = l % kXcds, q = l / kXcds;
+        out.push_back(nat[x * per + std::min(x, rem) + q]);
+    }
+}
+
 void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
     tiles.clear();
     for (int s = 0; s < c.S; ++s) {
@@ -241,13 +253,7 @@ void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
             for (int z0 = 0; z0 < y.nz; z0 += TY / 4)
                 for (int y0 = 0; y0 < y.ny; y0 += 4)
                     for (int x0 = 0; x0 < y.nx; x0 += kTX) nat.push_back(Tile{s, x0, y0, z0});
-            // XCD-contiguous order: the workgroups of one XCD take consecutive bricks of the natural order,
-            // so a brick's neighbours in y (whose planes its halo re-reads) sit in the same L2
-            const int T = (int)nat.size(), per = T / kXcds, rem = T % kXcds;
-            for (int l = 0; l < T; ++l) {
-                const int x = l % kXcds, q = l / kXcds;
-                tiles.push_back(nat[x * per + std::min(x, rem) + q]);
-            }
+            append_xcd_order(nat, tiles);
         } else {
             for (int y0 = 0; y0 < y.ny; y0 += TY)
                 for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, 0});
@@ -413,15 +419,36 @@ int cheb_halo(const apfc_params& p) {
     return std::max(p.mass_kind == APFC_MASS_SEPARABLE ? p.mass_iters : p.mass_iters - 1, p.diff_iters);
 }
 
-// Bricks of the separable mass inverse: 64 x kMassBY nodes per plane, kMassBZ planes (3D).
+// Bricks of the separable mass inverse and of the 3D Chebyshev L solves: 64 x kMassBY nodes per plane;
+// in 3D, bz = kBrickZShallow or kBrickZDeep planes, whichever gives the smaller (workgroup rounds) x (bz + 2
+// planes marched per brick), a round being as many bricks as the chip holds at once: deeper bricks re-read
+// fewer halo planes, but a partly filled last round costs as much as a full one.
 void build_mtiles(apfc_ctx& c) {
     c.mtiles.clear();
-    if (c.solver.mass_kind != APFC_MASS_SEPARABLE) return;
+    if (c.solver.mass_kind != APFC_MASS_SEPARABLE && c.dim != 3) return;
+    auto count = [&](int bz) {
+        long long n = 0;
+        for (int s = 0; s < c.S; ++s) {
+            const Sys& y = c.sys[s];
+            n += (long long)((y.nx + kTX - 1) / kTX) * ((y.ny + kMassBY - 1) / kMassBY) * ((y.nz + bz - 1) / bz);
+        }
+        return n;
+    };
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    auto cost = [&](int bz) {
+        const long long slots = (long long)std::max(1, cus) * std::max(1, brick_occupancy(bz, c.mixed));
+        return (count(bz) + slots - 1) / slots * (bz + 2);
+    };
+    c.mbz = c.dim == 3 && cost(kBrickZDeep) < cost(kBrickZShallow) ? kBrickZDeep : kBrickZShallow;
     for (int s = 0; s < c.S; ++s) {
         const Sys& y = c.sys[s];
-        for (int z0 = 0; z0 < y.nz; z0 += (y.dim == 3 ? kMassBZ : 1))
+        std::vector<Tile> nat;
+        for (int z0 = 0; z0 < y.nz; z0 += (y.dim == 3 ? c.mbz : 1))
             for (int y0 = 0; y0 < y.ny; y0 += kMassBY)
-                for (int x0 = 0; x0 < y.nx; x0 += kTX) c.mtiles.push_back(Tile{s, x0, y0, z0});
+                for (int x0 = 0; x0 < y.nx; x0 += kTX) nat.push_back(Tile{s, x0, y0, z0});
+        append_xcd_order(nat, c.mtiles);
     }
 }
 

@@ -544,9 +544,11 @@ __global__ __launch_bounds__(kBlock) void k_cb_iter(const Sys* sys, const Tile* 
 
 // 3D versions of k_cb_init (STAGE 1..3, the stages with a stencil) and k_cb_iter on z-marching
 // bricks; same arithmetic per node.
-template <int TY, typename T, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile* tiles, const int* mask, const cx<T>* v,
-                                                     const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv, long long NT) {
+// RR planes per thread on bricks of 64 x BY columns (64 x BY threads).
+template <int RR, int BY, typename T, int STAGE>
+__global__ __launch_bounds__(64 * BY) void k_cb_init3d(const Sys* sys, const Tile* tiles, const int* mask,
+                                                      const cx<T>* v, const cx<T>* src, cx<T>* r, cx<T>* d, cx<T>* xv,
+                                                      long long NT) {
     static_assert(STAGE >= 1 && STAGE <= 3, "stage 0 has no stencil");
     TILE_PROLOGUE();
     constexpr bool isM = STAGE == 3;
@@ -555,8 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_cb_init3d(const Sys* sys, const Tile
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
     const T k0 = T(s.kv[0]), k1 = T(s.kv[1]), k2 = T(s.kv[2]);
-    __shared__ cx<T> buf[2][1][kPP];
-    zmarch_lds<TY / 4, 1, WG, WG, T, T>(
+    __shared__ cx<T> buf[2][1][kPPb<BY>];
+    zmarch_lds<RR, 1, WG, WG, T, T, BY>(
         s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return src[s.off + i]; },
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
@@ -648,17 +650,17 @@ __global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Til
 // exact arithmetic; per node it reads x_j (stencil), x_{j-1} and b and writes x_{j+1}, two vectors fewer
 // than the correction form.  xout may be xkm1 (each node is read, then written, by one thread).  FINAL:
 // also step 4, z_zeta = x1 - (x2 - chi2 / sqrt(dt)) / sqrt(kappa) with chi2 = x_{j+1}.
-template <int TY, typename T, bool FIRST, bool FINAL>
-__global__ __launch_bounds__(kBlock) void k_cx_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
-                                                     const cx<T>* xk, const cx<T>* xkm1, const cx<T>* b, cx<T>* xout,
-                                                     const cx<T>* x1, const cx<T>* x2, cx<T>* zz) {
+template <int RR, int BY, typename T, bool FIRST, bool FINAL>
+__global__ __launch_bounds__(64 * BY) void k_cx_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
+                                                      const cx<T>* xk, const cx<T>* xkm1, const cx<T>* b,
+                                                      cx<T>* xout, const cx<T>* x1, const cx<T>* x2, cx<T>* zz) {
     TILE_PROLOGUE();
     const T c1 = T(sys[tile.sys].cb[1][j][0]), c2 = T(sys[tile.sys].cb[1][j][1]);
     const T cM = T(s.isq_dt), cK = T(s.sq_kap);
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
-    __shared__ cx<T> buf[2][1][kPP];
-    zmarch_lds<TY / 4, 1, true, false, T, T>(
+    __shared__ cx<T> buf[2][1][kPPb<BY>];
+    zmarch_lds<RR, 1, true, false, T, T, BY>(
         s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return xk[s.off + i]; },
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
@@ -1598,7 +1600,8 @@ template <int DIM, int TY, typename T, int STAGE>
 static void cb_init_launch(const Dev& d, const int* mask, const cx<T>* v, const cx<T>* src, cx<T>* r, cx<T>* dd,
                            cx<T>* xv, hipStream_t st) {
     if constexpr (DIM == 3 && STAGE != 0)
-        hipLaunchKernelGGL((k_cb_init3d<TY, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv, d.NT);
+        hipLaunchKernelGGL((k_cb_init3d<TY / 4, 4, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv,
+                           d.NT);
     else
         hipLaunchKernelGGL((k_cb_init<DIM, TY, T, STAGE>), TILE_GRID, d.sys, d.tiles, mask, v, src, r, dd, xv, d.NT);
 }
@@ -1661,8 +1664,12 @@ static void cx_iterations3d(const Dev& d, int its, cx<T>* A, cx<T>* B, const cx<
         const double vecs = (first ? 3.0 : 4.0) + (last && zz ? 3.0 : 0.0);
         ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * vecs, mask);
         auto go = [&](auto f, auto fin) {
-            hipLaunchKernelGGL((k_cx_iter3d<TYv, T, decltype(f)::value, decltype(fin)::value>), TILE_GRID, d.sys,
-                               d.tiles, mask, j, xk, xkm1, b, xo, x1, x2, zz);
+            brick_depth(d, [&](auto bz) {
+                hipLaunchKernelGGL((k_cx_iter3d<decltype(bz)::value, kMassBY, T, decltype(f)::value,
+                                                decltype(fin)::value>),
+                                   dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, j, xk, xkm1, b,
+                                   xo, x1, x2, zz);
+            });
         };
         using TT = std::true_type;
         using FF = std::false_type;
@@ -1698,15 +1705,24 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             // d1 holds d_1: iterations j >= 2 read D[(j - 1) & 1] = d1 first
             if (mass_sep == 0)
                 cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
-            // steps 2 and 3 in three-term form: the start writes b (into r) and x_1
+            // steps 2 and 3 in three-term form on the 64 x 8 x mbz bricks (shorter halos than the 64 x 4
+            // tiles): the start writes b (into r) and x_1
             {
                 ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
-                cb_init_launch<DIM, TYv, T, 1>(d, mask, v, x1, r, nullptr, diff_iters == 1 ? x2 : d0, st);
+                brick_depth(d, [&](auto bz) {
+                    hipLaunchKernelGGL((k_cb_init3d<decltype(bz)::value, kMassBY, T, 1>), dim3(d.nmtiles),
+                                       dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, v, x1, r, nullptr,
+                                       diff_iters == 1 ? x2 : d0, d.NT);
+                });
             }
             cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
             {
                 ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 3.0 * sizeof(cx<T>), mask);
-                cb_init_launch<DIM, TYv, T, 2>(d, mask, v, x2, r, nullptr, diff_iters == 1 ? z + d.NT : d0, st);
+                brick_depth(d, [&](auto bz) {
+                    hipLaunchKernelGGL((k_cb_init3d<decltype(bz)::value, kMassBY, T, 2>), dim3(d.nmtiles),
+                                       dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, v, x2, r, nullptr,
+                                       diff_iters == 1 ? z + d.NT : d0, d.NT);
+                });
             }
             // steps 3 and 4: the last iteration also forms z_zeta
             cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, z + d.NT, x1, x2, z, mask, st);
@@ -1743,6 +1759,20 @@ template void launch_precond_cheb_unfused<double>(const Dev&, const zd*, zd*, zd
                                                   const int*, hipStream_t);
 template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*, zf*, zf*, zf*, zf*, int, int, int,
                                                  const int*, hipStream_t);
+
+int brick_occupancy(int bz, bool single) {
+    const void* f =
+        single ? (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, float, false, false>
+                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, float, false, false>)
+               : (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, double, false, false>
+                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, double, false, false>);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kMassThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
 
 template <typename T>
 void launch_precond_mg(const Dev& d, const MgLevels& mg, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r,

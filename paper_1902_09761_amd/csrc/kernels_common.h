@@ -316,23 +316,30 @@ __device__ __forceinline__ Plane<R> plane_pass_lds(const cx<S>* b, int lane, int
     return p;
 }
 
-template <int RR, int NF, bool WK, bool WT, typename R, typename S, typename LOADG, typename EMIT>
-__device__ __forceinline__ void zmarch_lds(const Sys& s, const Tile& tile, int lane, int ty, cx<S> (*buf)[NF][kPP],
-                                           R m0, R m1, R ih, const LOADG& loadg, const EMIT& emit) {
-    const int e0 = (int)threadIdx.x, e1 = (int)threadIdx.x + kBlock;
+// BY: rows of the brick (the workgroup is 64 x BY threads; planes of (64 + 2) x (BY + 2) nodes in LDS).
+template <int BY>
+constexpr int kPPb = kPX * (BY + 2);
+
+template <int RR, int NF, bool WK, bool WT, typename R, typename S, int BY = 4, typename LOADG, typename EMIT>
+__device__ __forceinline__ void zmarch_lds(const Sys& s, const Tile& tile, int lane, int ty,
+                                           cx<S> (*buf)[NF][kPPb<BY>], R m0, R m1, R ih, const LOADG& loadg,
+                                           const EMIT& emit) {
+    constexpr int NTH = 64 * BY, PP = kPPb<BY>;
+    static_assert(PP <= 2 * NTH, "two staged nodes per thread and plane");
+    const int e0 = (int)threadIdx.x, e1 = (int)threadIdx.x + NTH;
     auto goff = [&](int e) {
         int gx = (tile.x0 - 1 + e % kPX) % s.nx, gy = (tile.y0 - 1 + e / kPX) % s.ny;
         gx = gx < 0 ? gx + s.nx : gx;
         gy = gy < 0 ? gy + s.ny : gy;
         return (long long)gy * s.nx + gx;
     };
-    const long long o0 = goff(e0), o1 = e1 < kPP ? goff(e1) : 0;
+    const long long o0 = goff(e0), o1 = e1 < PP ? goff(e1) : 0;
     const long long plane = (long long)s.nx * s.ny;
     auto fetch = [&](int b, long long base) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             buf[b][f][e0] = loadg(f, base + o0);
-            if (e1 < kPP) buf[b][f][e1] = loadg(f, base + o1);
+            if (e1 < PP) buf[b][f][e1] = loadg(f, base + o1);
         }
     };
     Plane<R> P[NF][3];

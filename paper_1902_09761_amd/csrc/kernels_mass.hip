@@ -11,8 +11,8 @@ namespace apfc {
 // direction (Sys::wsep holds (sqrt(3)/h) rho^k).  Taps that wrap onto the same node of a short periodic
 // direction add up.
 //
-// A workgroup of 512 threads owns a brick of 64 x kMassBY nodes per plane and kMassBZ planes (one plane
-// in 2D).  For each plane, from R planes before the brick to R planes after it (periodic), it stages the
+// A workgroup of 512 threads owns a brick of 64 x kMassBY nodes per plane and BZ planes (one plane in
+// 2D).  For each plane, from R planes before the brick to R planes after it (periodic), it stages the
 // plane's region of (64 + 2R) x (kMassBY + 2R) nodes in LDS (the next plane's loads in flight meanwhile),
 // filters the region's rows in x into a second LDS array, filters that in y at the thread's node and keeps
 // the last 2R + 1 such values of its column in registers for the z filter.  HBM traffic: beta1 read once
@@ -22,11 +22,11 @@ __device__ __forceinline__ int wrapm(int g, int n) {
     return g < 0 ? g + n : g;
 }
 
-template <int DIM, typename T, int R>
+template <int DIM, int BZ, typename T, int R>
 __global__ __launch_bounds__(kMassThreads) void k_mass_sep(const Sys* sys, const Tile* tiles, const int* mask,
                                                           const cx<T>* __restrict__ v, cx<T>* __restrict__ x1) {
     constexpr int PX = kTX + 2 * R, PY = kMassBY + 2 * R, PP = PX * PY;
-    constexpr int NZ = DIM == 3 ? kMassBZ + 2 * R : 1;   // planes marched
+    constexpr int NZ = DIM == 3 ? BZ + 2 * R : 1;   // planes marched
     static_assert(kMassThreads == kTX * kMassBY, "one thread per node of a brick plane");
     constexpr int NS = (PP + kMassThreads - 1) / kMassThreads;   // staged nodes per thread and plane
     __shared__ cx<T> A[PP];
@@ -110,11 +110,13 @@ void launch_mass_sep(const Dev& d, int R, const cx<T>* v, cx<T>* x1, const int* 
     auto go = [&](auto rc) {
         constexpr int RR = decltype(rc)::value;
         if (d.dim == 3)
-            hipLaunchKernelGGL((k_mass_sep<3, T, RR>), dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys, d.mtiles,
-                               mask, v, x1);
+            brick_depth(d, [&](auto bz) {
+                hipLaunchKernelGGL((k_mass_sep<3, decltype(bz)::value, T, RR>), dim3(d.nmtiles), dim3(kMassThreads),
+                                   0, st, d.sys, d.mtiles, mask, v, x1);
+            });
         else
-            hipLaunchKernelGGL((k_mass_sep<2, T, RR>), dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys, d.mtiles,
-                               mask, v, x1);
+            hipLaunchKernelGGL((k_mass_sep<2, 1, T, RR>), dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys,
+                               d.mtiles, mask, v, x1);
     };
     static_assert(kMassRMax == 4, "one case per tap count");
     switch (R) {

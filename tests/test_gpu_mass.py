@@ -88,6 +88,34 @@ def test_3d_bricks_match_oracle(n, R, precision, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [(apfc.APFC_FP64, 1e-12), (apfc.APFC_MIXED, 2e-5)])
+def test_deep_bricks_in_a_large_batch(precision, tol):
+    """128 bcc systems of 16 x 16 x 32 (768 amplitude systems: 3072 bricks of 16 planes, which fill three
+    rounds of the chip, so the 3D L solves and the mass inverse take the deep bricks): P^{-1} of systems 0,
+    77 and 127, each with its own input, against the oracle's."""
+    S, n, dt = 128, (16, 16, 32), 0.8
+    mesh = inputs.Mesh(3, n, tuple(v * H_BCC for v in n))
+    k = bcc_k()
+    J = len(k)
+    pairs = [_rand_pair(J, mesh.N, 100 + q) for q in range(S)]
+    s = solver_for([mesh] * S, apfc.APFC_BCC3D, [0.02] * S, inner_kind=apfc.APFC_INNER_CHEB, precision=precision,
+                   mass_kind=apfc.APFC_MASS_SEPARABLE, mass_iters=3, diff_iters=3)
+    zo = [torch.zeros((J, 2, mesh.N), dtype=torch.float64, device="cuda") for _ in range(S)]
+    eo = [torch.zeros_like(t) for t in zo]
+    s.apply(apfc.APFC_OP_PINV, [to_dev(z) for z, _ in pairs], [to_dev(e) for _, e in pairs], zo, eo, dt)
+    o = oracle_for(mesh, k, 0.02)
+    worst = 0.0
+    for q in (0, 77, 127):
+        gz, ge = from_dev(zo[q]), from_dev(eo[q])
+        zin, ein = pairs[q]
+        for j in range(J):
+            c1, c2 = o.precond_apply(j, zin[j], ein[j], dt, inner="cheb", mass_iters=3, diff_iters=3, mass="sep")
+            ref = np.concatenate([c1, c2])
+            worst = max(worst, float(np.max(np.abs(np.concatenate([gz[j], ge[j]]) - ref)) / np.max(np.abs(ref))))
+    print("deep bricks", precision, worst)
+    assert worst <= tol
+
+
 @pytest.mark.parametrize("precision", [apfc.APFC_FP64, apfc.APFC_MIXED])
 def test_steps_with_separable_mass_match_oracle(precision):
     """Three steps of the 64^2 grain (fused 2D path) and two of a bcc 12 x 10 x 8 grain (3D bricks) with
