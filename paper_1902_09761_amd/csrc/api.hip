@@ -233,9 +233,10 @@ namespace {
 // Workgroups go to the 8 XCDs of the chip in turn (workgroup b to XCD b mod 8), each XCD with its own L2.
 constexpr int kXcds = 8;
 
-// Appends bricks in XCD-contiguous order: the workgroups of one XCD take consecutive bricks of the natural
-// order, so a brick's neighbours in y (whose planes its halo re-reads) sit in the same L2.
-void append_xcd_order(const std::vector<Tile>& nat, std::vector<Tile>& out) {
+// Appends tiles in XCD-contiguous order: the workgroups of one XCD take consecutive tiles of the natural
+// order, so a tile's neighbours (whose nodes its halo re-reads) sit in the same L2.
+template <typename TL>
+void append_xcd_order(const std::vector<TL>& nat, std::vector<TL>& out) {
     const int T = (int)nat.size(), per = T / kXcds, rem = T % kXcds;
     for (int l = 0; l < T; ++l) {
         const int x = l % kXcds, q = l / kXcds;
@@ -255,8 +256,10 @@ void build_tiles(apfc_ctx& c, int TY, std::vector<Tile>& tiles) {
                     for (int x0 = 0; x0 < y.nx; x0 += kTX) nat.push_back(Tile{s, x0, y0, z0});
             append_xcd_order(nat, tiles);
         } else {
+            std::vector<Tile> nat;
             for (int y0 = 0; y0 < y.ny; y0 += TY)
-                for (int x0 = 0; x0 < y.nx; x0 += kTX) tiles.push_back(Tile{s, x0, y0, 0});
+                for (int x0 = 0; x0 < y.nx; x0 += kTX) nat.push_back(Tile{s, x0, y0, 0});
+            append_xcd_order(nat, tiles);
         }
         y.tend = (int)tiles.size();
     }
@@ -458,9 +461,11 @@ void build_ctiles(apfc_ctx& c) {
     const int IX = kChebShape[c.cheb_shape][0] - 2 * H, IY = kChebShape[c.cheb_shape][1] - 2 * H;
     for (int s = 0; s < c.S; ++s) {
         const Sys& y = c.sys[s];
+        std::vector<CTile> nat;
         for (int z = 0; z < y.nz; ++z)
             for (int y0 = 0; y0 < y.ny; y0 += IY)
-                for (int x0 = 0; x0 < y.nx; x0 += IX) c.ctiles.push_back(CTile{s, x0, y0, z});
+                for (int x0 = 0; x0 < y.nx; x0 += IX) nat.push_back(CTile{s, x0, y0, z});
+        append_xcd_order(nat, c.ctiles);
     }
 }
 
