@@ -202,10 +202,25 @@ void launch_precond(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2
 // side (launch_mass_sep) instead of mass_iters inner iterations.
 // vscale (may be null): the input is vscale[sys] * rv instead of v, and that scaled vector is also
 // stored to vout
+// Input of the fused 2D preconditioner formed as it is loaded (a basis vector of FGMRES) instead of read:
+// v = (src - sum_{l < nv} c_l V_l) * scale[sys] with c_l = hcoef[sys * hld + 2l] + i hcoef[sys * hld + 2l + 1],
+// in FP64 from the stored values, and stored to vout at the nodes each region owns.  src = null: v is read.
+template <typename T>
+struct VIn {
+    const cx<T>* src = nullptr;
+    const cx<T>* V = nullptr;   // V_l at V + l * vs
+    long long vs = 0;
+    int nv = 0;
+    const double* hcoef = nullptr;
+    int hld = 0;
+    const double* scale = nullptr;
+    cx<T>* vout = nullptr;
+};
+
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
                          cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep,
-                         const double* vscale, const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st);
+                         const VIn<T>& vin, const int* mask, hipStream_t st);
 
 template <typename T>
 void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* x1, cx<T>* x2, cx<T>* r, cx<T>* d0,

@@ -1063,10 +1063,6 @@ int upload_ptrs_na(apfc_ctx* c, int n, hipStream_t st) {
 // device slot copied to the host after the cycle.
 int* pub_target(apfc_ctx* c) { return c->noalloc ? c->pub_dev : c->d_pub; }
 
-// P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
-// Chebyshev (3D), or the paper's Jacobi-PCG.
-// With vscale set (fused 2D Chebyshev only), the input is vscale[sys] * rv instead of v and is also
-// stored to vout.
 // The multigrid levels' device view (tables and buffers of the attached workspace).
 MgLevels mg_levels(apfc_ctx* c, const Dev& fine) {
     MgLevels m;
@@ -1090,9 +1086,12 @@ MgLevels mg_levels(apfc_ctx* c, const Dev& fine) {
     return m;
 }
 
+// P^{-1} v -> z with the context's inner solver: fused 2D Chebyshev tiles, one-launch-per-iteration
+// Chebyshev (3D), or the paper's Jacobi-PCG.  With vin.src set (fused 2D Chebyshev only), v is formed
+// from vin and stored to vin.vout.
 template <typename T>
 void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mask, hipStream_t st,
-             const double* vscale = nullptr, const cx<T>* rv = nullptr, cx<T>* vout = nullptr) {
+             const VIn<T>& vin = VIn<T>{}) {
     cx<T>** pc = (cx<T>**)c->pc;
     const int sep = c->solver.mass_kind == APFC_MASS_SEPARABLE ? c->solver.mass_iters : 0;
     if (c->solver.inner_kind == APFC_INNER_MG)
@@ -1100,8 +1099,7 @@ void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mas
                              c->solver.mass_iters, sep, mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2)
         launch_precond_cheb<T>(d, c->cheb_shape, c->d_ctiles, (int)c->ctiles.size(), cheb_halo(c->solver), v, z,
-                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, sep, vscale, rv, vout,
-                               mask, st);
+                               pc[0], pc[1], c->solver.mass_iters, c->solver.diff_iters, sep, vin, mask, st);
     else if (c->solver.inner_kind == APFC_INNER_CHEB)
         launch_precond_cheb_unfused<T>(d, v, z, pc[0], pc[1], pc[2], pc[3], pc[4], c->solver.mass_iters,
                                        c->solver.diff_iters, sep, mask, st);
@@ -1110,8 +1108,8 @@ void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mas
                           c->solver.diff_iters, sep, mask, st);
 }
 
-// The fused 2D Chebyshev preconditioner normalises the first basis vector of a cycle itself (reading
-// the residual), so no separate scaling pass runs.
+// The fused 2D Chebyshev preconditioner forms the basis vectors itself: the first of a cycle from the
+// residual (no separate scaling pass), the others from w and the earlier ones (no projection pass).
 bool scale_in_precond(const apfc_ctx* c) { return c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2; }
 
 // The Krylov basis V is stored in the preconditioner's precision T: FP32 in mixed precision (inner
@@ -1145,18 +1143,39 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     cx<T>* Z = (cx<T>*)c->Z;
     cx<T>* V = basis<T>(c);
     const int* act = kr.iter_active;
-    if (k == 0 && scale_in_precond(c))   // v_0 = r / beta formed by the preconditioner's first stages
-        precond<T>(c, d, nullptr, Z, act, st, kr.inv_beta, residual<T>(c), V);
-    else
-        precond<T>(c, d, V + k * vs, Z + k * vs, act, st);
-    const int nv = k + 1;
-    // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     // w is kept in the basis precision (the front of the W buffer)
     cx<T>* Wk = (cx<T>*)c->W;
+    const bool form_v = scale_in_precond(c);
+    if (form_v) {
+        // the preconditioner's first stages form v_k and store it: v_0 = r / beta, or
+        // v_k = (w_{k-1} - sum_{l < k} h_{l,k-1} v_l) / h_{k,k-1} with the previous iteration's column
+        VIn<T> vin;
+        vin.vout = V + k * vs;
+        if (k == 0) {
+            vin.src = residual<T>(c);
+            vin.scale = kr.inv_beta;
+        } else {
+            vin.src = Wk;
+            vin.V = V;
+            vin.vs = vs;
+            vin.nv = k;
+            vin.hcoef = kr.hsum;
+            vin.hld = 2 * (c->m + 1);
+            vin.scale = kr.hinv;
+        }
+        precond<T>(c, d, nullptr, Z + k * vs, act, st, vin);
+    } else {
+        precond<T>(c, d, V + k * vs, Z + k * vs, act, st);
+    }
+    const int nv = k + 1;
+    // W = A z_k with the first Gram-Schmidt pass fused (V^H w and |w|^2 per tile)
     launch_apply_dot<T>(d, Z + k * vs, c->dnode, Wk, V, vs, nv, c->apart, act, st);
     // reduce the first pass; skip or run the second; Hessenberg column, Givens, convergence test
     launch_gs<cx<T>>(d, kr, k, c->apart, V, vs, Wk, c->cpart, st);
-    launch_proj_final<cx<T>>(d, V, vs, nv, Wk, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
+    // v_{k+1}, unless the next preconditioner forms it; the cycle's last one, v_m, is not needed: the
+    // solution update reads Z, and the next cycle starts from the recomputed residual
+    if (k + 1 < c->m && !form_v)
+        launch_proj_final<cx<T>>(d, V, vs, nv, Wk, kr.hsum, kr.hinv, 2 * (c->m + 1), V + (k + 1) * vs, act, st);
 }
 
 void run_iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {

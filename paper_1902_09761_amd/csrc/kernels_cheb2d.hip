@@ -119,7 +119,7 @@ constexpr int cheb_buffers() { return sizeof(T) == 4 ? 2 : 1; }
 template <typename T, int STAGE, int RX, int RY, int NTH, int MR = 0>
 __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     const Sys* sys, const CTile* tiles, const int* mask, const cx<T>* v, cx<T>* x1, cx<T>* x2, cx<T>* z, int sM,
-    int sL, int halo, long long NT, const double* vscale, const cx<T>* rv, cx<T>* vout) {
+    int sL, int halo, long long NT, VIn<T> vin) {
     // the separable stage 0 needs one region buffer: half the LDS, twice the workgroups per CU
     constexpr int NB = MR > 0 ? 1 : cheb_buffers<T>();
     constexpr int RL = RY + 2, RP = RX * RL, NP = RX * RY / NTH;
@@ -143,31 +143,59 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
             bufs[q][(RL - 1) * RX + e] = cx<T>{T(0), T(0)};
         }
     cx<T> X[NP], R[NP];
-    // The input is v, or, when vscale is set, vscale[sys] * rv (the restart residual): the first basis
-    // vector of a cycle, normalised here instead of in a pass of its own (stages 0 and 1 also store it to
-    // vout)
-    const double vs = vscale ? vscale[tile.sys] : 1.0;
-    auto ldv = [&](long long i) {
-        if (!vscale) return v[i];
-        const zd u = ld<double>(rv, i);
-        return cx<T>{T(vs * u.x), T(vs * u.y)};
+    constexpr int PC = NP % 4 == 0 ? 4 : NP % 3 == 0 ? 3 : NP % 2 == 0 ? 2 : 1;
+    // nodes the region owns (its interior; no wrap: each mesh node is owned by exactly one region)
+    const int ix = px - halo;
+    const bool own_x = ix >= 0 && ix < IX && tile.x0 + ix < s.nx;
+    auto own_row = [&](int i) {
+        const int iy = r0 + i - halo;
+        return iy >= 0 && iy < IY && tile.y0 + iy < s.ny;
+    };
+    // The input half at offset hoff into R: v, or the basis vector formed from vin (normalised, and projected
+    // against the earlier basis vectors, here instead of in a pass of its own), whose owned nodes are also
+    // stored to vin.vout
+    auto load_in = [&](long long hoff) {
+        RegionRows g = rows0;
+        if (!vin.src) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i, g.next()) R[i] = v[hoff + g.at()];
+            return;
+        }
+        const double* hc = vin.hcoef + (long long)tile.sys * vin.hld;
+        const double sc = vin.scale[tile.sys];
+        // PC rows at a time: FP64 accumulators for all NP rows would cost a third of the workgroups per CU
+#pragma unroll
+        for (int i0 = 0; i0 < NP; i0 += PC) {
+            zd u[PC];
+            long long gi[PC];
+#pragma unroll
+            for (int i = 0; i < PC; ++i, g.next()) {
+                gi[i] = hoff + g.at();
+                u[i] = ld<double>(vin.src, gi[i]);
+            }
+            for (int l = 0; l < vin.nv; ++l) {
+                const zd c{hc[2 * l], hc[2 * l + 1]};
+                const cx<T>* Vl = vin.V + l * vin.vs;
+#pragma unroll
+                for (int i = 0; i < PC; ++i) u[i] = u[i] - cmul(c, ld<double>(Vl, gi[i]));
+            }
+#pragma unroll
+            for (int i = 0; i < PC; ++i) {
+                R[i0 + i] = cx<T>{T(sc * u[i].x), T(sc * u[i].y)};
+                if (own_x && own_row(i0 + i)) vin.vout[gi[i]] = R[i0 + i];
+            }
+        }
     };
     // right-hand side of the inner solve
     if constexpr (STAGE == 0) {
-        RegionRows g = rows0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i, g.next()) R[i] = ldv(g.at());
+        load_in(0);
     } else {
         {
             RegionRows g = rows0;
 #pragma unroll
             for (int i = 0; i < NP; ++i, g.next()) lrow(bufs[0], i) = STAGE == 1 ? x1[g.at()] : x2[g.at()];
         }
-        if constexpr (STAGE == 1) {
-            RegionRows g = rows0;
-#pragma unroll
-            for (int i = 0; i < NP; ++i, g.next()) R[i] = ldv(NT + g.at());
-        }
+        if constexpr (STAGE == 1) load_in(NT);
         __syncthreads();
         if constexpr (STAGE == 1) {
             // r = beta2 - kappa G x1 with G = -K + i T_j: r += kappa K x1 - i kappa T_j x1
@@ -326,21 +354,17 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
         }
     }
     }
-    // interior output (no wrap: each mesh node is written by exactly one tile)
-    const int ix = px - halo;
-    if (ix < 0 || ix >= IX || tile.x0 + ix >= s.nx) return;
+    // output at the owned nodes
+    if (!own_x) return;
     RegionRows g = rows0;
 #pragma unroll
     for (int i = 0; i < NP; ++i, g.next()) {
-        const int iy = r0 + i - halo;
-        if (iy < 0 || iy >= IY || tile.y0 + iy >= s.ny) continue;
+        if (!own_row(i)) continue;
         const long long gi = g.at();
         if constexpr (STAGE == 0) {
             x1[gi] = X[i];
-            if (vscale) stv(vout, gi, vs * ld<double>(rv, gi));
         } else if constexpr (STAGE == 1) {
             x2[gi] = X[i];
-            if (vscale) stv(vout, NT + gi, vs * ld<double>(rv, NT + gi));
         } else {
             const cx<T> chi2 = X[i];
             z[gi] = x1[gi] - T(s.isq_kap) * (x2[gi] - T(s.isq_dt) * chi2);
@@ -351,16 +375,17 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
 
 template <typename T, int RX, int RY, int NTH>
 static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo, const cx<T>* v, cx<T>* z,
-                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep, const double* vscale,
-                        const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+                        cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep, const VIn<T>& vin,
+                        const int* mask, hipStream_t st) {
     const dim3 g(nctiles), b(NTH);
-    // input half read (residual or basis vector) and, with vscale, the basis vector written
-    const double pts = (double)d.NT, vin = (double)sizeof(cx<T>), vb = vscale ? (double)sizeof(cx<T>) : 0.0;
+    // input half read (v, or the vectors the basis vector is formed from) and then the basis vector written
+    const double pts = (double)d.NT, in = (double)sizeof(cx<T>) * (vin.src ? 1 + vin.nv : 1),
+                 vb = vin.src ? (double)sizeof(cx<T>) : 0.0;
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + sizeof(cx<T>) + vb), mask);
+        ProbeScope ps(d, KID_CHEB, st, pts * (in + sizeof(cx<T>) + vb), mask);
         auto stage0 = [&](auto mr) {
             hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH, decltype(mr)::value>), g, b, 0, st, d.sys, ctiles, mask,
-                               v, x1, x2, z, mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+                               v, x1, x2, z, mass_iters, diff_iters, halo, d.NT, vin);
         };
         static_assert(kMassRMax == 4, "one case per tap count");
         switch (mass_sep) {
@@ -372,23 +397,23 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
         }
     }
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (vin + 2 * sizeof(cx<T>) + vb), mask);
+        ProbeScope ps(d, KID_CHEB, st, pts * (in + 2 * sizeof(cx<T>) + vb), mask);
         hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z,
-                           mass_iters, diff_iters, halo, d.NT, vscale, rv, vout);
+                           mass_iters, diff_iters, halo, d.NT, vin);
     }
     ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask);
     hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                       diff_iters, halo, d.NT, nullptr, nullptr, nullptr);
+                       diff_iters, halo, d.NT, VIn<T>{});
 }
 
 template <typename T>
 void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctiles, int halo, const cx<T>* v,
                          cx<T>* z, cx<T>* x1, cx<T>* x2, int mass_iters, int diff_iters, int mass_sep,
-                         const double* vscale, const cx<T>* rv, cx<T>* vout, const int* mask, hipStream_t st) {
+                         const VIn<T>& vin, const int* mask, hipStream_t st) {
 #define APFC_CHEB_SHAPE(I)                                                                                       \
     case I:                                                                                                      \
         cheb_stages<T, kChebShape[I][0], kChebShape[I][1], kChebShape[I][2]>(                                    \
-            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vscale, rv, vout, mask, st); \
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vin, mask, st);               \
         break;
     static_assert(kChebShapes == 6, "one case per region shape");
     switch (shape) {
@@ -398,13 +423,13 @@ void launch_precond_cheb(const Dev& d, int shape, const CTile* ctiles, int nctil
         APFC_CHEB_SHAPE(4)
         APFC_CHEB_SHAPE(5)
         default: cheb_stages<T, kChebShape[0][0], kChebShape[0][1], kChebShape[0][2]>(
-            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vscale, rv, vout, mask, st);
+            d, ctiles, nctiles, halo, v, z, x1, x2, mass_iters, diff_iters, mass_sep, vin, mask, st);
     }
 #undef APFC_CHEB_SHAPE
 }
 template void launch_precond_cheb<double>(const Dev&, int, const CTile*, int, int, const zd*, zd*, zd*, zd*, int, int,
-                                          int, const double*, const zd*, zd*, const int*, hipStream_t);
+                                          int, const VIn<double>&, const int*, hipStream_t);
 template void launch_precond_cheb<float>(const Dev&, int, const CTile*, int, int, const zf*, zf*, zf*, zf*, int, int,
-                                         int, const double*, const zf*, zf*, const int*, hipStream_t);
+                                         int, const VIn<float>&, const int*, hipStream_t);
 
 }  // namespace apfc
