@@ -106,8 +106,13 @@ template <int JM>
 __device__ __forceinline__ zd pick(const zd (&e)[JM], int k) {
     zd r = e[0];
 #pragma unroll
-    for (int q = 1; q < JM; ++q)
-        if (k == q) r = e[q];
+    for (int q = 1; q < JM; ++q) {
+        // k is the same in every lane (a term-table entry); the comparison goes through readfirstlane so
+        // that the chain stays a chain of selects instead of an indexed load from a stack copy of e
+        const bool sel = __builtin_amdgcn_readfirstlane(k) == q;
+        r.x = sel ? e[q].x : r.x;
+        r.y = sel ? e[q].y : r.y;
+    }
     return r;
 }
 
