@@ -89,6 +89,44 @@ __device__ __forceinline__ void split_sweep(const cx<T>* b, int xm, int xc, int 
     }
 }
 
+// split_sweep for regions one wave wide (RX = 64, the thread's lane is its column) with the thread's NP
+// rows u[] in registers: the x neighbours come by lane shifts (0 beyond the region's outer columns, whose
+// values only reach the halo), the rows above and below the thread's block from the neighbouring waves
+// through edge[w][0] and edge[w][1] (first and last row of the block of wave w; 0 above the first block and
+// below the last, as the pad rows of the LDS region).  One barrier, after the edge rows are stored.
+// f(i, ...) is called as by split_sweep, in row order, and may overwrite u[i] (read by then).
+template <typename T, int NP, int NW, bool WE, typename F>
+__device__ __forceinline__ void reg_sweep(cx<T> (&u)[NP], cx<T> (*edge)[2][kTX], int w, F&& f) {
+    const int lane = (int)threadIdx.x & (kTX - 1);
+    edge[w][0][lane] = u[0];
+    edge[w][1][lane] = u[NP - 1];
+    __syncthreads();
+    const cx<T> zero{T(0), T(0)};
+    const cx<T> above = w > 0 ? edge[w - 1][1][lane] : zero;
+    const cx<T> below = w + 1 < NW ? edge[w + 1][0][lane] : zero;
+    auto xpass = [&](cx<T> c, cx<T>& p, cx<T>& e) {
+        const cx<T> l = lane_shift<kDppWaveShr1>(c), r = lane_shift<kDppWaveShl1>(c);
+        p = T(4) * c + (l + r);
+        e = WE ? r - l : zero;
+    };
+    cx<T> uA = above, uB = u[0], pA, pB, eA, eB;
+    xpass(uA, pA, eA);
+    xpass(uB, pB, eB);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const cx<T> uC = i + 1 < NP ? u[i + 1] : below;
+        cx<T> pC, eC;
+        xpass(uC, pC, eC);
+        f(i, pA, pB, pC, uA, uB, uC, eA, eB, eC);
+        uA = uB;
+        uB = uC;
+        pA = pB;
+        pB = pC;
+        eA = eB;
+        eB = eC;
+    }
+}
+
 struct SplitCoef {
     double a, b, c, d;
 };
@@ -124,7 +162,14 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     constexpr int NB = MR > 0 ? 1 : cheb_buffers<T>();
     constexpr int RL = RY + 2, RP = RX * RL, NP = RX * RY / NTH;
     static_assert((RX * RY) % NTH == 0 && NTH % RX == 0, "region rows must map onto whole workgroup rows");
-    __shared__ cx<T> bufs[NB][RP];
+    // RG: the Chebyshev stages of FP32 regions one wave wide keep the thread's rows in registers
+    // (reg_sweep); the region is not staged in LDS, only the edge rows of the waves' blocks (two sets, used
+    // in turn by consecutive sweeps, so each sweep needs one barrier)
+    constexpr bool RG = MR == 0 && RX == kTX && sizeof(T) == 4;
+    constexpr int NW = NTH / RX;
+    __shared__ cx<T> bufs[RG ? 1 : NB][RG ? 1 : RP];
+    __shared__ cx<T> edges[RG ? 2 : 1][RG ? NW : 1][2][kTX];
+    const int wv = (int)threadIdx.x / RX;
     const CTile tile = tiles[blockIdx.x];
     if (mask && !mask[tile.sys]) return;
     const Sys s = sys[tile.sys];
@@ -136,12 +181,13 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
                            s.ny};
     auto lrow = [&](cx<T>* b, int i) -> cx<T>& { return b[(r0 + 1 + i) * RX + px]; };
     // the pad rows only feed the outermost halo rows; zero them so that no stale value is ever read
-    for (int e = threadIdx.x; e < RX; e += NTH)
+    if constexpr (!RG)
+        for (int e = threadIdx.x; e < RX; e += NTH)
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            bufs[q][e] = cx<T>{T(0), T(0)};
-            bufs[q][(RL - 1) * RX + e] = cx<T>{T(0), T(0)};
-        }
+            for (int q = 0; q < NB; ++q) {
+                bufs[q][e] = cx<T>{T(0), T(0)};
+                bufs[q][(RL - 1) * RX + e] = cx<T>{T(0), T(0)};
+            }
     cx<T> X[NP], R[NP];
     constexpr int PC = NP % 4 == 0 ? 4 : NP % 3 == 0 ? 3 : NP % 2 == 0 ? 2 : 1;
     // nodes the region owns (its interior; no wrap: each mesh node is owned by exactly one region)
@@ -190,30 +236,37 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     if constexpr (STAGE == 0) {
         load_in(0);
     } else {
-        {
+        // stage 1: r = beta2 - kappa G x1 with G = -K + i T_j (r += kappa K x1 - i kappa T_j x1); stage 2: r = M x2
+        const T k3 = T(s.kappa / 3.0), k4 = T(4.0 * s.kappa), kap = T(s.kappa);
+        const T g0 = T(s.kappa * s.h / 6.0 * s.kv[0]), g1 = T(s.kappa * s.h / 6.0 * s.kv[1]);
+        const SplitCoef m = split_coef(s.h, 1.0, 0.0);
+        const T ma = T(m.a), mb = T(m.b);
+        auto rhs = [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC, cx<T> eA, cx<T> eB,
+                       cx<T> eC) {
+            if constexpr (STAGE == 1) {
+                const cx<T> kk = kap * (uA + uC) + k4 * uB - k3 * ((pA + pC) + pB);
+                const cx<T> tt = g0 * (T(4) * eB + (eA + eC)) + g1 * (pC - pA);
+                R[i] = R[i] + cx<T>{kk.x + tt.y, kk.y - tt.x};
+            } else {
+                R[i] = ma * (pA + pC) + mb * pB;
+            }
+        };
+        if constexpr (RG) {
+            cx<T> U[NP];
             RegionRows g = rows0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i, g.next()) lrow(bufs[0], i) = STAGE == 1 ? x1[g.at()] : x2[g.at()];
-        }
-        if constexpr (STAGE == 1) load_in(NT);
-        __syncthreads();
-        if constexpr (STAGE == 1) {
-            // r = beta2 - kappa G x1 with G = -K + i T_j: r += kappa K x1 - i kappa T_j x1
-            const T k3 = T(s.kappa / 3.0), k4 = T(4.0 * s.kappa), kap = T(s.kappa);
-            const T g0 = T(s.kappa * s.h / 6.0 * s.kv[0]), g1 = T(s.kappa * s.h / 6.0 * s.kv[1]);
-            split_sweep<T, NP, RX, true>(bufs[0] + r0 * RX, xm, px, xp,
-                                         [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA, cx<T> uB, cx<T> uC,
-                                             cx<T> eA, cx<T> eB, cx<T> eC) {
-                                             const cx<T> kk = kap * (uA + uC) + k4 * uB - k3 * ((pA + pC) + pB);
-                                             const cx<T> tt = g0 * (T(4) * eB + (eA + eC)) + g1 * (pC - pA);
-                                             R[i] = R[i] + cx<T>{kk.x + tt.y, kk.y - tt.x};
-                                         });
+            for (int i = 0; i < NP; ++i, g.next()) U[i] = STAGE == 1 ? x1[g.at()] : x2[g.at()];
+            if constexpr (STAGE == 1) load_in(NT);
+            reg_sweep<T, NP, NW, STAGE == 1>(U, edges[0], wv, rhs);
         } else {
-            const SplitCoef m = split_coef(s.h, 1.0, 0.0);
-            const T ma = T(m.a), mb = T(m.b);
-            split_sweep<T, NP, RX, false>(bufs[0] + r0 * RX, xm, px, xp,
-                                          [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T>, cx<T>, cx<T>, cx<T>,
-                                              cx<T>, cx<T>) { R[i] = ma * (pA + pC) + mb * pB; });
+            {
+                RegionRows g = rows0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i, g.next()) lrow(bufs[0], i) = STAGE == 1 ? x1[g.at()] : x2[g.at()];
+            }
+            if constexpr (STAGE == 1) load_in(NT);
+            __syncthreads();
+            split_sweep<T, NP, RX, STAGE == 1>(bufs[0] + r0 * RX, xm, px, xp, rhs);
         }
     }
     static_assert(MR == 0 || (STAGE == 0 && MR <= kMassRMax), "the separable mass inverse is step 1");
@@ -299,7 +352,31 @@ __global__ __launch_bounds__(NTH, sizeof(T) == 4 ? 4 : 2) void k_cheb2d(
     const SplitCoef oc = split_coef(s.h, isM ? 1.0 : s.isq_dt, isM ? 0.0 : s.sq_kap);
     const T oa = T(oc.a), ob = T(oc.b), occ = T(oc.c), od = T(oc.d);
     const T d0 = T(cb[0][0]);
-    if constexpr (NB == 2) {
+    if constexpr (RG) {
+        // d_{k-1} of the thread's rows in D; iteration k sweeps them with edge set k & 1 (set 0 also served
+        // the right-hand side sweep of stages 1 and 2, whose reads finished before iteration 1's barrier) and
+        // replaces each row's d once the sweep has read it
+        cx<T> D[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            D[i] = d0 * R[i];
+            X[i] = D[i];
+        }
+        auto iteration = [&](int k, auto store) {
+            const T c1 = T(cb[k][0]), c2 = T(cb[k][1]);
+            reg_sweep<T, NP, NW, false>(D, edges[k & 1], wv, [&](int i, cx<T> pA, cx<T> pB, cx<T> pC, cx<T> uA,
+                                                                  cx<T> uB, cx<T> uC, cx<T>, cx<T>, cx<T>) {
+                cx<T> q = R[i] - oa * (pA + pC) - ob * pB;
+                if constexpr (!isM) q = q - occ * (uA + uC) - od * uB;
+                R[i] = q;
+                const cx<T> dv = c1 * uB + c2 * q;
+                X[i] = X[i] + dv;
+                if constexpr (decltype(store)::value) D[i] = dv;
+            });
+        };
+        for (int k = 1; k + 1 < its; ++k) iteration(k, std::true_type{});
+        if (its > 1) iteration(its - 1, std::false_type{});
+    } else if constexpr (NB == 2) {
         // d_0 into bufs[1]; iteration k reads d_{k-1} from bufs[k & 1] (the barrier at its start orders it
         // after every write of d_{k-1} and after every read of the buffer it writes, bufs[(k + 1) & 1], by
         // iteration k - 1 or by the prologue of stages 1 and 2)
