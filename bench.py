@@ -226,20 +226,20 @@ def kernel_sources_sha256():
 
 def traffic_from_profile(family, workload, tiles):
     """HBM bytes per working launch of one kernel family from the committed counter summary
-    profiles/<family>_<workload>_hbm_counters.md, if it was taken with the current kernel source and the
-    same tiling (null otherwise)."""
+    profiles/<family>_<workload>_hbm_counters.md (one `traffic_bytes_per_launch[ROWS,REGION]` line per tiling
+    measured), if it was taken with the current kernel source and the tiling the run used (null otherwise)."""
     path = os.path.join(PROFILES, f"{family}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None, None
     text = open(path).read()
-    m1 = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
     m2 = re.search(r"kernel_sources_sha256:\s*([0-9a-f]+)", text)
-    m3 = re.search(r"tiles:\s*([0-9]+),([0-9]+)", text)
-    sha = kernel_sources_sha256()
     rel = os.path.relpath(path, ROOT)
-    if not (m1 and m2 and m3) or m2.group(1) != sha or (int(m3.group(1)), int(m3.group(2))) != tuple(tiles):
+    if not m2 or m2.group(1) != kernel_sources_sha256():
         return None, rel
-    return float(m1.group(1)), rel
+    for m in re.finditer(r"traffic_bytes_per_launch\[([0-9]+),([0-9]+)\]:\s*([0-9.]+)", text):
+        if (int(m.group(1)), int(m.group(2))) == tuple(tiles):
+            return float(m.group(3)), rel
+    return None, rel
 
 
 def rooflines(res):
