@@ -1667,13 +1667,12 @@ static void cx_iterations3d(const Dev& d, int its, cx<T>* A, cx<T>* B, const cx<
         cx<T>* xkm1 = (j & 1) ? B : A;
         cx<T>* xo = last ? out : xkm1;
         const double vecs = (first ? 3.0 : 4.0) + (last && zz ? 3.0 : 0.0);
-        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * vecs, mask);
+        ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * vecs, mask, true);
         auto go = [&](auto f, auto fin) {
             brick_depth(d, [&](auto bz) {
-                hipLaunchKernelGGL((k_cx_iter3d<decltype(bz)::value, kMassBY, T, decltype(f)::value,
-                                                decltype(fin)::value>),
-                                   dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, j, xk, xkm1, b,
-                                   xo, x1, x2, zz);
+                ps.launch(k_cx_iter3d<decltype(bz)::value, kMassBY, T, decltype(f)::value, decltype(fin)::value>,
+                          dim3(d.nmtiles), dim3(kMassThreads), d.sys, d.mtiles, mask, j, (const cx<T>*)xk,
+                          (const cx<T>*)xkm1, b, xo, x1, x2, zz);
             });
         };
         using TT = std::true_type;
@@ -1713,20 +1712,20 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             // steps 2 and 3 in three-term form on the 64 x 8 x mbz bricks (shorter halos than the 64 x 4
             // tiles): the start writes b (into r) and x_1
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask);
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask, true);
                 brick_depth(d, [&](auto bz) {
-                    hipLaunchKernelGGL((k_cb_init3d<decltype(bz)::value, kMassBY, T, 1>), dim3(d.nmtiles),
-                                       dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, v, x1, r, nullptr,
-                                       diff_iters == 1 ? x2 : d0, d.NT);
+                    ps.launch(k_cb_init3d<decltype(bz)::value, kMassBY, T, 1>, dim3(d.nmtiles), dim3(kMassThreads),
+                              d.sys, d.mtiles, mask, v, (const cx<T>*)x1, r, (cx<T>*)nullptr,
+                              diff_iters == 1 ? x2 : d0, d.NT);
                 });
             }
             cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 3.0 * sizeof(cx<T>), mask);
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 3.0 * sizeof(cx<T>), mask, true);
                 brick_depth(d, [&](auto bz) {
-                    hipLaunchKernelGGL((k_cb_init3d<decltype(bz)::value, kMassBY, T, 2>), dim3(d.nmtiles),
-                                       dim3(kMassThreads), 0, st, d.sys, d.mtiles, mask, v, x2, r, nullptr,
-                                       diff_iters == 1 ? z + d.NT : d0, d.NT);
+                    ps.launch(k_cb_init3d<decltype(bz)::value, kMassBY, T, 2>, dim3(d.nmtiles), dim3(kMassThreads),
+                              d.sys, d.mtiles, mask, v, (const cx<T>*)x2, r, (cx<T>*)nullptr,
+                              diff_iters == 1 ? z + d.NT : d0, d.NT);
                 });
             }
             // steps 3 and 4: the last iteration also forms z_zeta

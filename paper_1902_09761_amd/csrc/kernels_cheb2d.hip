@@ -459,10 +459,10 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
     const double pts = (double)d.NT, in = (double)sizeof(cx<T>) * (vin.src ? 1 + vin.nv : 1),
                  vb = vin.src ? (double)sizeof(cx<T>) : 0.0;
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (in + sizeof(cx<T>) + vb), mask);
+        ProbeScope ps(d, KID_CHEB, st, pts * (in + sizeof(cx<T>) + vb), mask, true);
         auto stage0 = [&](auto mr) {
-            hipLaunchKernelGGL((k_cheb2d<T, 0, RX, RY, NTH, decltype(mr)::value>), g, b, 0, st, d.sys, ctiles, mask,
-                               v, x1, x2, z, mass_iters, diff_iters, halo, d.NT, vin);
+            ps.launch(k_cheb2d<T, 0, RX, RY, NTH, decltype(mr)::value>, g, b, d.sys, ctiles, mask, v, x1, x2, z,
+                      mass_iters, diff_iters, halo, d.NT, vin);
         };
         static_assert(kMassRMax == 4, "one case per tap count");
         switch (mass_sep) {
@@ -474,13 +474,13 @@ static void cheb_stages(const Dev& d, const CTile* ctiles, int nctiles, int halo
         }
     }
     {
-        ProbeScope ps(d, KID_CHEB, st, pts * (in + 2 * sizeof(cx<T>) + vb), mask);
-        hipLaunchKernelGGL((k_cheb2d<T, 1, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z,
-                           mass_iters, diff_iters, halo, d.NT, vin);
+        ProbeScope ps(d, KID_CHEB, st, pts * (in + 2 * sizeof(cx<T>) + vb), mask, true);
+        ps.launch(k_cheb2d<T, 1, RX, RY, NTH>, g, b, d.sys, ctiles, mask, v, x1, x2, z, mass_iters, diff_iters, halo,
+                  d.NT, vin);
     }
-    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask);
-    hipLaunchKernelGGL((k_cheb2d<T, 2, RX, RY, NTH>), g, b, 0, st, d.sys, ctiles, mask, v, x1, x2, z, mass_iters,
-                       diff_iters, halo, d.NT, VIn<T>{});
+    ProbeScope ps(d, KID_CHEB, st, pts * 4 * sizeof(cx<T>), mask, true);
+    ps.launch(k_cheb2d<T, 2, RX, RY, NTH>, g, b, d.sys, ctiles, mask, v, x1, x2, z, mass_iters, diff_iters, halo,
+              d.NT, VIn<T>{});
 }
 
 template <typename T>

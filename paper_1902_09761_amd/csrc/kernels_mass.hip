@@ -106,17 +106,16 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_sep(const Sys* sys, const
 
 template <typename T>
 void launch_mass_sep(const Dev& d, int R, const cx<T>* v, cx<T>* x1, const int* mask, hipStream_t st) {
-    ProbeScope ps(d, KID_MASS, st, (double)d.NT * 2.0 * sizeof(cx<T>), mask);
+    ProbeScope ps(d, KID_MASS, st, (double)d.NT * 2.0 * sizeof(cx<T>), mask, true);
     auto go = [&](auto rc) {
         constexpr int RR = decltype(rc)::value;
         if (d.dim == 3)
             brick_depth(d, [&](auto bz) {
-                hipLaunchKernelGGL((k_mass_sep<3, decltype(bz)::value, T, RR>), dim3(d.nmtiles), dim3(kMassThreads),
-                                   0, st, d.sys, d.mtiles, mask, v, x1);
+                ps.launch(k_mass_sep<3, decltype(bz)::value, T, RR>, dim3(d.nmtiles), dim3(kMassThreads), d.sys,
+                          d.mtiles, mask, v, x1);
             });
         else
-            hipLaunchKernelGGL((k_mass_sep<2, 1, T, RR>), dim3(d.nmtiles), dim3(kMassThreads), 0, st, d.sys,
-                               d.mtiles, mask, v, x1);
+            ps.launch(k_mass_sep<2, 1, T, RR>, dim3(d.nmtiles), dim3(kMassThreads), d.sys, d.mtiles, mask, v, x1);
     };
     static_assert(kMassRMax == 4, "one case per tap count");
     switch (R) {
