@@ -274,8 +274,10 @@ int apfc_probe_read(apfc_ctx* ctx, int* launches, double* total_ms, double* byte
  * since the last apfc_probe_read (it does not reset them): sampled working launches, their summed
  * duration, their mean algorithmic bytes (0 for families without a byte model: xupdate, gs's first
  * pass, the small kernels) and, in issued, every launch of the family so far, sampled or not.  Family
- * names: "cheb" (fused and per-iteration Chebyshev preconditioner stages), "apply" (operator apply with
- * the first Gram-Schmidt pass), "residual", "proj_final", "xupdate", "gs", "extrapolate", "rhs",
+ * names: "cheb" (fused and per-iteration Chebyshev preconditioner stages; stages 0 and 1 of the fused 2D
+ * preconditioner also form the next basis vector), "apply" (operator apply with
+ * the first Gram-Schmidt pass), "residual", "proj_final" (the basis vector where the preconditioner does
+ * not form it), "xupdate", "gs", "extrapolate", "rhs",
  * "mass" (the separable mass inverse on bricks), "mg" (multigrid V-cycle kernels), "pcg_spmv",
  * "pcg_update", "pcg_init", "pc_final", "reduce", "small", "other". */
 int apfc_probe_read_kernel(apfc_ctx* ctx, const char* name, int* launches, double* total_ms,
