@@ -200,26 +200,32 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot3d(const Sys* sys, const Ti
     double acc[2 * NV + 1];
 #pragma unroll
     for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0.0;
-    zmarch<TY / 4, 2, true, true, double>(
-        s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); },
-        [&](int z, const auto& P) {
-            if (x >= s.nx || y >= s.ny || z >= s.nz) return;
-            const long long il = ((long long)z * s.ny + y) * s.nx + x;
-            zd a1, a2;
-            apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], a1, a2);
-            const zd y1 = rounded<T>(a1), y2 = rounded<T>(a2);
-            stv(W, s.off + il, y1);
-            stv(W, NT + s.off + il, y2);
-            acc[2 * NV] += abs2(y1) + abs2(y2);
+    auto emit = [&](int z, const auto& P) {
+        if (x >= s.nx || y >= s.ny || z >= s.nz) return;
+        const long long il = ((long long)z * s.ny + y) * s.nx + x;
+        zd a1, a2;
+        apply_A_planes(s, P, m0, m1, ih, dnode[s.doff + il], a1, a2);
+        const zd y1 = rounded<T>(a1), y2 = rounded<T>(a2);
+        stv(W, s.off + il, y1);
+        stv(W, NT + s.off + il, y2);
+        acc[2 * NV] += abs2(y1) + abs2(y2);
 #pragma unroll
-            for (int l = 0; l < NV; ++l)
-                if (NV <= 8 || l < nv) {
-                    const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
-                         q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
-                    acc[2 * l] += p.x + q.x;
-                    acc[2 * l + 1] += p.y + q.y;
-                }
-        });
+        for (int l = 0; l < NV; ++l)
+            if (NV <= 8 || l < nv) {
+                const zd p = cdot(ld<double>(V, l * vstride + s.off + il), y1),
+                     q = cdot(ld<double>(V, l * vstride + NT + s.off + il), y2);
+                acc[2 * l] += p.x + q.x;
+                acc[2 * l + 1] += p.y + q.y;
+            }
+    };
+    // FP32 storage: the next plane's values are loaded while the current one is used (two waves per SIMD
+    // either way); FP64 storage keeps the plain march, whose look-ahead would halve its waves
+    if constexpr (sizeof(T) == 4)
+        zmarch_prefetch<TY / 4, 2, true, true, double, T>(s, xc, yc, tile.z, m0, m1, ih,
+                                                          [&](int f) { return f == 0 ? zz : ze; }, emit);
+    else
+        zmarch<TY / 4, 2, true, true, double>(
+            s, xc, yc, tile.z, m0, m1, ih, [&](int f, long long i) { return ld<double>(f == 0 ? zz : ze, i); }, emit);
     block_sum<2 * NV + 1>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll

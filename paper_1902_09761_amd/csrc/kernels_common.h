@@ -287,6 +287,72 @@ __device__ __forceinline__ void zmarch(const Sys& s, int xc, int yc, int z0, R m
     }
 }
 
+// zmarch with the next plane loaded while the current one is used: the 9 stored values per field of plane
+// z + 1 (ptr(f)[node], type cx<S>) are in flight while the passes of plane z are formed, so a wave has
+// arithmetic to issue while its loads are outstanding.  The same operations and emit as zmarch (the
+// compiler may contract a few multiply-adds differently).
+template <bool WK, bool WT, typename R, typename S>
+__device__ __forceinline__ Plane<R> plane_pass_regs(const cx<S> (&u)[9], R m0, R m1, R ih) {
+    const R half = R(0.5);
+    cx<R> mx[3], kx[3], dx[3];
+    Plane<R> p{};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const cx<R> l{R(u[3 * b].x), R(u[3 * b].y)}, c{R(u[3 * b + 1].x), R(u[3 * b + 1].y)},
+            r{R(u[3 * b + 2].x), R(u[3 * b + 2].y)};
+        mx[b] = m0 * (l + r) + m1 * c;
+        if (WK) kx[b] = ih * ((c + c) - (l + r));
+        if (WT) dx[b] = half * (r - l);
+        if (b == 1) p.c = c;
+    }
+    p.m = m0 * (mx[0] + mx[2]) + m1 * mx[1];
+    if (WK) p.k = (m0 * (kx[0] + kx[2]) + m1 * kx[1]) + ih * ((mx[1] + mx[1]) - (mx[0] + mx[2]));
+    if (WT) {
+        p.dx = m0 * (dx[0] + dx[2]) + m1 * dx[1];
+        p.dy = half * (mx[2] - mx[0]);
+    }
+    return p;
+}
+
+template <int RR, int NF, bool WK, bool WT, typename R, typename S, typename PTR, typename EMIT>
+__device__ __forceinline__ void zmarch_prefetch(const Sys& s, int xc, int yc, int z0, R m0, R m1, R ih,
+                                                const PTR& ptr, const EMIT& emit) {
+    const int xs[3] = {xc == 0 ? s.nx - 1 : xc - 1, xc, xc == s.nx - 1 ? 0 : xc + 1};
+    const long long rs[3] = {(long long)(yc == 0 ? s.ny - 1 : yc - 1) * s.nx, (long long)yc * s.nx,
+                             (long long)(yc == s.ny - 1 ? 0 : yc + 1) * s.nx};
+    const long long plane = (long long)s.nx * s.ny;
+    cx<S> cur[NF][9], nxt[NF][9];
+    auto fetch = [&](long long base, cx<S> (&dst)[NF][9]) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) dst[f][3 * b + q] = ptr(f)[base + rs[b] + xs[q]];
+    };
+    Plane<R> P[NF][3];
+    int zz = z0 == 0 ? s.nz - 1 : z0 - 1;
+    fetch(zz * plane, cur);
+#pragma unroll
+    for (int a = 0; a < RR + 2; ++a) {
+        const int zn = zz + 1 == s.nz ? 0 : zz + 1;
+        if (a + 1 < RR + 2) fetch(zn * plane, nxt);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) P[f][2] = plane_pass_regs<WK, WT, R, S>(cur[f], m0, m1, ih);
+        if (a >= 2) emit(z0 + a - 2, P);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            P[f][0] = P[f][1];
+            P[f][1] = P[f][2];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) cur[f][e] = nxt[f][e];
+        }
+        zz = zn;
+        // one plane of look-ahead, no more: later planes' loads would hold registers the waves need
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // 3D plane march with the planes of the workgroup's 64 x 4 columns plus a one-node halo (66 x 6) staged in
 // LDS: the workgroup loads a plane with two coalesced loads per thread and field, the next plane while
 // the current one is in use, and every thread takes its x/y pass from LDS (9 LDS reads instead of 9
