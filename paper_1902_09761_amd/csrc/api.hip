@@ -1110,7 +1110,7 @@ void precond(apfc_ctx* c, const Dev& d, const cx<T>* v, cx<T>* z, const int* mas
 
 // The fused 2D Chebyshev preconditioner forms the basis vectors itself: the first of a cycle from the
 // residual (no separate scaling pass), the others from w and the earlier ones (no projection pass).
-bool scale_in_precond(const apfc_ctx* c) { return c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2; }
+bool precond_forms_basis(const apfc_ctx* c) { return c->solver.inner_kind == APFC_INNER_CHEB && c->dim == 2; }
 
 // The Krylov basis V is stored in the preconditioner's precision T: FP32 in mixed precision (inner
 // products and projections still accumulate in FP64), FP64 otherwise.
@@ -1129,7 +1129,7 @@ void launch_restart_residual(apfc_ctx* c, const Dev& d, const int* mask, hipStre
 
 // v_0 = r / beta where the preconditioner does not form it
 void scale_start(apfc_ctx* c, const Dev& d, hipStream_t st) {
-    if (scale_in_precond(c)) return;
+    if (precond_forms_basis(c)) return;
     if (c->mixed)
         launch_scale<zf>(d, residual<float>(c), c->kr.inv_beta, basis<float>(c), c->kr.iter_active, st);
     else
@@ -1145,7 +1145,7 @@ void iteration(apfc_ctx* c, const Dev& d, int k, hipStream_t st) {
     const int* act = kr.iter_active;
     // w is kept in the basis precision (the front of the W buffer)
     cx<T>* Wk = (cx<T>*)c->W;
-    const bool form_v = scale_in_precond(c);
+    const bool form_v = precond_forms_basis(c);
     if (form_v) {
         // the preconditioner's first stages form v_k and store it: v_0 = r / beta, or
         // v_k = (w_{k-1} - sum_{l < k} h_{l,k-1} v_l) / h_{k,k-1} with the previous iteration's column
