@@ -580,7 +580,7 @@ __global__ __launch_bounds__(64 * BY) void k_cb_init3d(const Sys* sys, const Til
             const cx<T> dv = scale * rv;
             r[i] = rv;
             if (d) d[i] = dv;   // not kept by the three-term form (k_cx_iter3d)
-            xv[i] = dv;
+            if (xv) xv[i] = dv;   // the three-term form re-forms x_1 = d_0 from r where it needs it
         });
 }
 
@@ -649,32 +649,42 @@ __global__ __launch_bounds__(kBlock) void k_cb_first3d(const Sys* sys, const Til
 }
 
 // Iteration j >= 1 of the Chebyshev solve for L in three-term form on the iterates (3D):
-//   x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 (b - L x_j),   x_0 = 0 (FIRST: j = 1),
+//   x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 (b - L x_j),   x_0 = 0,
 // with the scalars (c1, c2) of iteration j of the correction form (k_cb_iter3d: d_j = c1 d_{j-1} + c2 r_j,
 // x_{j+1} = x_j + d_j, where d_{j-1} = x_j - x_{j-1} and r_j = b - L x_j), so the iterates are the same in
 // exact arithmetic; per node it reads x_j (stencil), x_{j-1} and b and writes x_{j+1}, two vectors fewer
-// than the correction form.  xout may be xkm1 (each node is read, then written, by one thread).  FINAL:
-// also step 4, z_zeta = x1 - (x2 - chi2 / sqrt(dt)) / sqrt(kappa) with chi2 = x_{j+1}.
-template <int RR, int BY, typename T, bool FIRST, bool FINAL>
+// than the correction form.  x_1 = d_0 = s b (s = the first scalar of the table) is not stored: FIRST
+// (j = 1) stages s b in place of x_1, PREVB (j = 2) forms x_{j-1} = s b from the b it reads anyway.  xout
+// may be xkm1 (each node is read, then written, by one thread).  FINAL: also step 4,
+// z_zeta = x1 - (x2 - chi2 / sqrt(dt)) / sqrt(kappa) with chi2 = x_{j+1}.
+template <int RR, int BY, typename T, bool FIRST, bool PREVB, bool FINAL>
 __global__ __launch_bounds__(64 * BY) void k_cx_iter3d(const Sys* sys, const Tile* tiles, const int* mask, int j,
                                                       const cx<T>* xk, const cx<T>* xkm1, const cx<T>* b,
                                                       cx<T>* xout, const cx<T>* x1, const cx<T>* x2, cx<T>* zz) {
     TILE_PROLOGUE();
+    static_assert(!(FIRST && PREVB), "x_{j-1} is formed from b only at j = 2");
     const T c1 = T(sys[tile.sys].cb[1][j][0]), c2 = T(sys[tile.sys].cb[1][j][1]);
+    const T s0 = T(sys[tile.sys].cb[1][0][0]);
     const T cM = T(s.isq_dt), cK = T(s.sq_kap);
     const int y = tile.y0 + ty;
     const T h = T(s.h), m0 = h * T(1.0 / 6.0), m1 = h * T(4.0 / 6.0), ih = T(1) / h;
     __shared__ cx<T> buf[2][1][kPPb<BY>];
     zmarch_lds<RR, 1, true, false, T, T, BY>(
-        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih, [&](int, long long i) { return xk[s.off + i]; },
+        s, tile, (int)(threadIdx.x & 63), ty, buf, m0, m1, ih,
+        [&](int, long long i) {
+            if constexpr (FIRST)
+                return s0 * b[s.off + i];
+            else
+                return xk[s.off + i];
+        },
         [&](int z, const auto& P) {
             if (x >= s.nx || y >= s.ny || z >= s.nz) return;
             const long long i = s.off + ((long long)z * s.ny + y) * s.nx + x;
             cx<T> Mu, Ku, Tu;
             zcombine<true, false, T>(P[0][0], P[0][1], P[0][2], m0, m1, ih, T(0), T(0), T(0), Mu, Ku, Tu);
-            const cx<T> xc = P[0][1].c;
-            const cx<T> dprev = FIRST ? xc : xc - ld<T>(xkm1, i);
-            const cx<T> xn = xc + c1 * dprev + c2 * (ld<T>(b, i) - (cM * Mu + cK * Ku));
+            const cx<T> xc = P[0][1].c, bv = ld<T>(b, i);
+            const cx<T> dprev = FIRST ? xc : xc - (PREVB ? s0 * bv : ld<T>(xkm1, i));
+            const cx<T> xn = xc + c1 * dprev + c2 * (bv - (cM * Mu + cK * Ku));
             xout[i] = xn;
             if constexpr (FINAL) zz[i] = ld<T>(x1, i) - T(s.isq_kap) * (ld<T>(x2, i) - T(s.isq_dt) * xn);
         });
@@ -1656,33 +1666,38 @@ static void cb_iterations3d(const Dev& d, int j0, int its, cx<T>* d0, cx<T>* d1,
     }
 }
 
-// Iterations 1 .. its - 1 of a three-term Chebyshev solve for L (3D) after the start wrote x_1 to A: x_j
-// in A or B by the parity of j, the last iterate into out (with x1, x2, zz: step 4 as well).
+// Iterations 1 .. its - 1 of a three-term Chebyshev solve for L (3D) after the start wrote b: x_1 = s b is
+// formed where needed (j = 1, 2), x_j (j >= 2) in A or B by the parity of j, the last iterate into out (with
+// x1, x2, zz: step 4 as well).
 template <int TYv, typename T>
 static void cx_iterations3d(const Dev& d, int its, cx<T>* A, cx<T>* B, const cx<T>* b, cx<T>* out, const cx<T>* x1,
                             const cx<T>* x2, cx<T>* zz, const int* mask, hipStream_t st) {
     for (int j = 1; j < its; ++j) {
-        const bool last = j == its - 1, first = j == 1;
+        const bool last = j == its - 1, first = j == 1, prevb = j == 2, fin = last && zz;
         cx<T>* xk = ((j - 1) & 1) ? B : A;
         cx<T>* xkm1 = (j & 1) ? B : A;
         cx<T>* xo = last ? out : xkm1;
-        const double vecs = (first ? 3.0 : 4.0) + (last && zz ? 3.0 : 0.0);
+        // b (and at j = 1 x_1 = s b from it), x_j, x_{j-1} unless formed from b, x_{j+1}; step 4: x1, x2, z_zeta
+        const double vecs = (first ? 2.0 : prevb ? 3.0 : 4.0) + (fin ? 3.0 : 0.0);
         ProbeScope ps(d, KID_CHEB, st, (double)d.NT * sizeof(cx<T>) * vecs, mask, true);
-        auto go = [&](auto f, auto fin) {
+        auto go = [&](auto f, auto p, auto fn) {
             brick_depth(d, [&](auto bz) {
-                ps.launch(k_cx_iter3d<decltype(bz)::value, kMassBY, T, decltype(f)::value, decltype(fin)::value>,
+                ps.launch(k_cx_iter3d<decltype(bz)::value, kMassBY, T, decltype(f)::value, decltype(p)::value,
+                                      decltype(fn)::value>,
                           dim3(d.nmtiles), dim3(kMassThreads), d.sys, d.mtiles, mask, j, (const cx<T>*)xk,
                           (const cx<T>*)xkm1, b, xo, x1, x2, zz);
             });
         };
         using TT = std::true_type;
         using FF = std::false_type;
-        if (last && zz) {
-            if (first) go(TT{}, TT{});
-            else go(FF{}, TT{});
+        if (fin) {
+            if (first) go(TT{}, FF{}, TT{});
+            else if (prevb) go(FF{}, TT{}, TT{});
+            else go(FF{}, FF{}, TT{});
         } else {
-            if (first) go(TT{}, FF{});
-            else go(FF{}, FF{});
+            if (first) go(TT{}, FF{}, FF{});
+            else if (prevb) go(FF{}, TT{}, FF{});
+            else go(FF{}, FF{}, FF{});
         }
     }
 }
@@ -1710,22 +1725,24 @@ void launch_precond_cheb_unfused(const Dev& d, const cx<T>* v, cx<T>* z, cx<T>* 
             if (mass_sep == 0)
                 cb_iterations3d<TYv, T, 0>(d, 2, mass_iters, d0, d1, r, x1, nullptr, nullptr, nullptr, mask, st);
             // steps 2 and 3 in three-term form on the 64 x 8 x mbz bricks (shorter halos than the 64 x 4
-            // tiles): the start writes b (into r) and x_1
+            // tiles): the start writes b (into r), and x_1 = s b only when it is the result (one iteration)
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 4.0 * sizeof(cx<T>), mask, true);
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (diff_iters == 1 ? 4.0 : 3.0) * sizeof(cx<T>), mask,
+                              true);
                 brick_depth(d, [&](auto bz) {
                     ps.launch(k_cb_init3d<decltype(bz)::value, kMassBY, T, 1>, dim3(d.nmtiles), dim3(kMassThreads),
                               d.sys, d.mtiles, mask, v, (const cx<T>*)x1, r, (cx<T>*)nullptr,
-                              diff_iters == 1 ? x2 : d0, d.NT);
+                              diff_iters == 1 ? x2 : (cx<T>*)nullptr, d.NT);
                 });
             }
             cx_iterations3d<TYv, T>(d, diff_iters, d0, d1, r, x2, nullptr, nullptr, nullptr, mask, st);
             {
-                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * 3.0 * sizeof(cx<T>), mask, true);
+                ProbeScope ps(d, KID_CHEB, st, (double)d.NT * (diff_iters == 1 ? 3.0 : 2.0) * sizeof(cx<T>), mask,
+                              true);
                 brick_depth(d, [&](auto bz) {
                     ps.launch(k_cb_init3d<decltype(bz)::value, kMassBY, T, 2>, dim3(d.nmtiles), dim3(kMassThreads),
                               d.sys, d.mtiles, mask, v, (const cx<T>*)x2, r, (cx<T>*)nullptr,
-                              diff_iters == 1 ? z + d.NT : d0, d.NT);
+                              diff_iters == 1 ? z + d.NT : (cx<T>*)nullptr, d.NT);
                 });
             }
             // steps 3 and 4: the last iteration also forms z_zeta
@@ -1766,10 +1783,10 @@ template void launch_precond_cheb_unfused<float>(const Dev&, const zf*, zf*, zf*
 
 int brick_occupancy(int bz, bool single) {
     const void* f =
-        single ? (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, float, false, false>
-                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, float, false, false>)
-               : (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, double, false, false>
-                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, double, false, false>);
+        single ? (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, float, false, false, false>
+                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, float, false, false, false>)
+               : (bz == kBrickZDeep ? (const void*)&k_cx_iter3d<kBrickZDeep, kMassBY, double, false, false, false>
+                                    : (const void*)&k_cx_iter3d<kBrickZShallow, kMassBY, double, false, false, false>);
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kMassThreads, 0) != hipSuccess) {
         (void)hipGetLastError();
