@@ -7,11 +7,13 @@ namespace apfc {
 // ------------------------------------------------------------------------------------------
 // Block preconditioner with Chebyshev-Jacobi inner solves, fused per step (2D).
 //
-// A workgroup owns a region of kChebRX x kChebRY nodes = an interior tile plus `halo` layers
-// (periodic wrap).  Every stencil application inside the region is evaluated from LDS and is
-// exact one layer further in than the previous one, so after `halo` applications the interior
-// holds the same values an unfused sweep over the whole mesh would give.  Three kernels per
-// preconditioner application:
+// A workgroup owns a region of RX x RY nodes = an interior tile plus `halo` layers (periodic wrap).
+// Every stencil application inside the region is evaluated from the region's values (staged in LDS, or,
+// for FP32 regions one wave wide, held in registers with the edge rows of the waves exchanged through
+// LDS) and is exact one layer further in than the previous one, so after `halo` applications the interior
+// holds the same values an unfused sweep over the whole mesh would give.  Stages 0 and 1 can also form
+// their half of the next FGMRES basis vector as they load it (VIn).  Three kernels per preconditioner
+// application:
 //   STAGE 0: x1   = Cheb_M^{sM}(beta1)                         (step 1)
 //   STAGE 1: x2   = Cheb_L^{sL}(beta2 - kappa G x1)             (step 2)
 //   STAGE 2: chi2 = Cheb_L^{sL}(M x2);  chi1 = x1 - (x2 - chi2/sqrt(dt))/sqrt(kappa)   (steps 3, 4)

@@ -353,10 +353,10 @@ __device__ __forceinline__ void zmarch_prefetch(const Sys& s, int xc, int yc, in
     }
 }
 
-// 3D plane march with the planes of the workgroup's 64 x 4 columns plus a one-node halo (66 x 6) staged in
-// LDS: the workgroup loads a plane with two coalesced loads per thread and field, the next plane while
-// the current one is in use, and every thread takes its x/y pass from LDS (9 LDS reads instead of 9
-// global loads).  buf: [2][NF][66 * 6] values in the storage type S.
+// 3D plane march with the planes of the workgroup's 64 x BY columns plus a one-node halo ((64 + 2) x
+// (BY + 2)) staged in LDS: the workgroup loads a plane with two coalesced loads per thread and field, the
+// next plane while the current one is in use, and every thread takes its x/y pass from LDS (9 LDS reads
+// instead of 9 global loads).  buf: [2][NF][(64 + 2) * (BY + 2)] values in the storage type S.
 constexpr int kPX = 66, kPY = 6, kPP = kPX * kPY;
 
 template <bool WK, bool WT, typename R, typename S>
