@@ -88,6 +88,19 @@ def test_3d_bricks_match_oracle(n, R, precision, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("diff", [1, 2, 5])
+@pytest.mark.parametrize("precision,tol", [(apfc.APFC_FP64, 1e-12), (apfc.APFC_MIXED, 2e-5)])
+def test_3d_diffusion_iteration_counts(diff, precision, tol):
+    """The three-term 3D L solves for every shape of the iteration sequence: one iteration (the start
+    writes the result), two (the first iteration also forms step 4), five (plain iterations after the
+    second); 20 x 12 x 18, ragged in every direction."""
+    n = (20, 12, 18)
+    mesh = inputs.Mesh(3, n, tuple(v * H_BCC for v in n))
+    err = _pinv_err(mesh, apfc.APFC_BCC3D, bcc_k(), apfc.APFC_INNER_CHEB, precision, 3, diff, 0.9)
+    print("3d diffusion iterations", diff, precision, err)
+    assert err <= tol
+
+
 @pytest.mark.parametrize("precision,tol", [(apfc.APFC_FP64, 1e-12), (apfc.APFC_MIXED, 2e-5)])
 def test_deep_bricks_in_a_large_batch(precision, tol):
     """128 bcc systems of 16 x 16 x 32 (768 amplitude systems: 3072 bricks of 16 planes, which fill three
